@@ -1,0 +1,156 @@
+/*
+ * libcola -- the COLA particle-mesh step on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Koda, Blake, Beutler, Kazin & Marin (2015), "Fast and accurate mock
+ * catalogue generation for low-mass galaxies", Sec. 2: COmoving Lagrangian
+ * Acceleration (COLA).  Particles move in the frame of their 2LPT
+ * trajectory x_2LPT = q + D1 Psi1(q) + D2 Psi2(q); only the residual is
+ * integrated, with the kick/drift ansatz of eqs. cola-kick and cola-drift,
+ * driven by a particle-mesh (PM) force.
+ *
+ * Conventions used by every call
+ *   - Units: lengths Mpc/h at the boundary of cola_init_2lpt / cola_pk;
+ *     particle state (displacement, residual velocity, Psi1, Psi2) is held in
+ *     units of the PM mesh spacing dx = box / nmesh; time in 1/H0.
+ *   - Particle id p = (i * np + j) * np + k for lattice indices (i, j, k) on
+ *     axes (x, y, z); Lagrangian point q = (i, j, k) * box / np.
+ *   - Particle arrays are structure-of-arrays float32, 3 * np^3 values:
+ *     component c of particle p at [c * np^3 + p].
+ *   - Meshes are C order [x][y][z], z fastest.  Mesh nodes sit at cell
+ *     centres, (n + 1/2) dx.
+ *   - Device pointers are HIP device memory owned by the caller.  The library
+ *     never allocates device memory: all of its device state lives in the
+ *     caller's workspace (cola_workspace_query gives the size).
+ *   - Every call is enqueued on the context's HIP stream and returns without
+ *     waiting, except where a call returns host data (stated per call).
+ *   - Return value: COLA_OK (0) or a negative COLA_E* code.  No call aborts
+ *     or throws; cola_last_error() gives a message.  A call that fails with
+ *     anything but COLA_EHIP leaves the context state unchanged.
+ */
+#ifndef COLA_H
+#define COLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COLA_OK            0
+#define COLA_EINVAL       -1   /* bad argument (null pointer, size, range)         */
+#define COLA_ENOMEM       -2   /* workspace smaller than cola_workspace_query      */
+#define COLA_ESTATE       -3   /* call not valid in the current state (a0 != a_x)  */
+#define COLA_EUNSUPPORTED -4   /* mesh not 8 * {2,3}-smooth, ratio not supported   */
+#define COLA_EHIP         -5   /* HIP runtime error (message in cola_last_error)   */
+#define COLA_ENONFINITE   -6   /* non-finite value found (COLA_F_CHECK_FINITE)     */
+
+#define COLA_F_CHECK_FINITE 1  /* after each step, check the state for NaN/Inf */
+
+typedef struct cola_ctx cola_ctx;
+
+/* Run parameters.  Cosmology is flat LCDM, Omega_Lambda = 1 - omega_m
+ * (Sec. 1).  nmesh: PM mesh per side, a multiple of 8 whose only prime
+ * factors are 2 and 3, and nmesh >= np.  np: particles per side, even,
+ * {2,3}-smooth. */
+typedef struct cola_params {
+  int32_t np;              /* particles per side                                   */
+  int32_t nmesh;           /* PM mesh per side                                     */
+  double  box;             /* periodic box side [Mpc/h]                            */
+  double  omega_m;         /* matter density parameter                             */
+  double  n_lpt;           /* kick/drift ansatz exponent, Sec. 2.1 (paper: -2.5)   */
+  double  a_init;          /* scale factor of the initial conditions               */
+  int32_t flags;           /* COLA_F_* bits                                        */
+  int32_t reserved;
+} cola_params;
+
+/* Fills p with defaults: omega_m 0.27, n_lpt -2.5, a_init 0.02, flags 0. */
+void cola_params_default(cola_params* p, int32_t np, int32_t nmesh, double box);
+
+/* Workspace the context needs, in bytes (alignment 256).  Sizes scale as
+ * 4 meshes of nmesh^2 (nmesh + 2) floats plus 12 + 4 floats of particle
+ * state and sort data per particle. */
+int cola_workspace_query(const cola_params* p, size_t* bytes);
+
+/* Creates a context that uses dev_workspace (>= cola_workspace_query bytes,
+ * 256-byte aligned device memory, owned by the caller and kept alive until
+ * cola_destroy) and enqueues all work on hip_stream (a hipStream_t; NULL =
+ * the default stream).  Uploads FFT twiddle tables into the workspace. */
+int cola_create(const cola_params* p, void* dev_workspace, size_t bytes,
+                void* hip_stream, cola_ctx** out);
+int cola_destroy(cola_ctx* ctx);
+
+/* Initial conditions (Sec. 2.1 2LPT growing mode; Sec. 2.3 Gaussian initial
+ * random modes).  dev_noise: np^3 float32 N(0,1) white noise, C order, device.
+ * k[nk], pk[nk]: host tables of the z=0 linear P(k) [h/Mpc, (Mpc/h)^3], k
+ * strictly increasing, pk > 0, nk >= 2; interpolated linearly in (ln k, ln P),
+ * end segments extended.  Builds Psi1, Psi2 and sets displacement
+ * d = D1(a_init) Psi1 + D2(a_init) Psi2, residual velocity 0, a_x = a_v =
+ * a_init.  Reads dev_noise only during the call's stream work. */
+int cola_init_2lpt_from_noise(cola_ctx* ctx, const float* dev_noise,
+                              const double* k, const double* pk, int32_t nk);
+
+/* Same, drawing the white noise on the GPU from a Philox4x32-10 stream
+ * (Salmon et al. 2011; key = seed, counter = particle id) with the
+ * Box-Muller transform.  box and np must equal the context's (COLA_EINVAL
+ * otherwise); they are repeated to follow the method's problem statement. */
+int cola_init_2lpt(cola_ctx* ctx, uint64_t seed, const double* k, const double* pk,
+                   int32_t nk, double box, int32_t np);
+
+/* Writes the np^3 white noise cola_init_2lpt(seed) would draw. */
+int cola_noise(cola_ctx* ctx, uint64_t seed, float* dev_noise);
+
+/* One COLA step a0 -> a1 (eqs. cola-kick and cola-drift): PM force at the
+ * positions at a0; residual kick from a_v to (a0+a1)/2; drift of the
+ * residual plus the 2LPT increment to a1.  Requires a0 == current a_x
+ * (COLA_ESTATE otherwise) and a1 > a0. */
+int cola_step(cola_ctx* ctx, double a0, double a1);
+
+/* Density contrast delta = rho/rho_bar - 1 of the current positions on the
+ * nmesh^3 mesh by the deterministic CIC deposit (Sec. 3.3 CIC), written to
+ * dev_out (nmesh^3 float32, C order).  Bitwise reproducible: per cell the
+ * weights are summed in ascending particle id, nodes add their 8 source
+ * cells in a fixed order. */
+int cola_density(cola_ctx* ctx, float* dev_out);
+
+/* Matter power spectrum (Sec. 3.3): CIC onto ngrid^3 (8 <= ngrid <= nmesh,
+ * multiple of 8, {2,3}-smooth), FFT, divide by the CIC window, P = |delta_k|^2
+ * / V over the half space {kz>0} U {kz=0,ky>0} U {kz=0,ky=0,kx>0} with
+ * |k| <= pi ngrid / box, binned by k_edges[nbins+1] (h/Mpc, increasing; bin b
+ * holds edges[b] <= |k| < edges[b+1]).  Host outputs: mean |k|, mean P and
+ * mode count per bin.  Synchronises the stream.  nbins <= 4096. */
+int cola_pk(cola_ctx* ctx, int32_t ngrid, const double* k_edges, int32_t nbins,
+            double* host_kmean, double* host_pk, int64_t* host_nmodes);
+
+/* PM force F (mesh units) at the current positions, 3 * np^3 float32 into
+ * dev_force; no state change (the force of Sec. 2.2 as used by cola_step). */
+int cola_force(cola_ctx* ctx, float* dev_force);
+
+/* Copies the particle state out / in (device, 3 * np^3 float32 each, mesh
+ * units).  Any pointer may be NULL to skip that array.  set_state also sets
+ * a_x, a_v. */
+int cola_get_state(cola_ctx* ctx, float* dev_disp, float* dev_vres,
+                   float* dev_psi1, float* dev_psi2, double* a_x, double* a_v);
+int cola_set_state(cola_ctx* ctx, const float* dev_disp, const float* dev_vres,
+                   const float* dev_psi1, const float* dev_psi2, double a_x, double a_v);
+
+/* In-place 3D real FFT on the context's FFT engine: dev_mesh holds an
+ * n^3 real field in padded rows of 2 (n/2 + 1) floats (n one of np, nmesh);
+ * forward (inverse = 0) leaves the unnormalised half spectrum
+ * [x][y][0..n/2] as interleaved complex; inverse (1) maps it back without
+ * the 1/n^3 factor. */
+int cola_fft3d(cola_ctx* ctx, int32_t n, float* dev_mesh, int32_t inverse);
+
+/* Host scalars of the step a_x -> a1 with velocity at a_v (FP64):
+ * out[0..9] = alpha, D1(a_x), D2(a_x), D1(a1)-D1(a_x), D2(a1)-D2(a_x),
+ * K (kick factor), I (drift factor), a_h, D1(a1), D2(a1). */
+int cola_step_scalars(const cola_params* p, double a_x, double a_v, double a1, double* out);
+
+int cola_synchronize(cola_ctx* ctx);
+const char* cola_strerror(int code);
+const char* cola_last_error(const cola_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLA_H */

@@ -1,0 +1,540 @@
+// libcola C ABI: context, workspace layout, and the step orchestration.
+//
+// The PM step (Koda et al. 2015, Sec. 2.2-2.3) on one GPU:
+//   tile sort -> deterministic CIC deposit -> r2c FFT (z, y) ->
+//   x pass: forward FFT, Green's function x i k for the 3 axes, inverse FFT ->
+//   y and z inverse passes on the 3 force meshes -> CIC readout fused with the
+//   COLA kick and drift (eqs. cola-kick, cola-drift; 2LPT terms of Sec. 2.1).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cola_internal.h"
+
+using namespace cola;
+
+namespace {
+
+constexpr int kMaxBins = 4096;
+constexpr int kPkChunks = 64;
+const double kPi = 3.14159265358979323846;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool smooth23(int n) {
+  if (n < 2) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+int fail(cola_ctx* c, int code, const char* msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(cola_ctx* c, hipError_t e, const char* where) {
+  if (c) {
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return COLA_EHIP;
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);   \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx, where)                             \
+  do {                                                       \
+    hipError_t e_ = hipGetLastError();                       \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where);   \
+  } while (0)
+
+struct Layout {
+  size_t disp, vres, psi1, psi2, pkey, prank, perm, counts, offsets, scan, mesh, tw, amp,
+      pk_partial, pk_out, pk_edges, flag, total;
+  long nbucket, mesh_stride, mesh_region, amp_len;
+  int tw_cap;
+};
+
+int validate(const cola_params* p) {
+  if (!p) return COLA_EINVAL;
+  if (p->np < 2 || p->nmesh < 16 || !(p->box > 0) || !(p->omega_m > 0) || p->omega_m > 1.0 ||
+      !(p->a_init > 0) || p->n_lpt == 0.0 || !std::isfinite(p->n_lpt))
+    return COLA_EINVAL;
+  if (p->np % 2 != 0 || !smooth23(p->np)) return COLA_EUNSUPPORTED;
+  if (p->nmesh % 8 != 0 || !smooth23(p->nmesh) || p->nmesh < p->np) return COLA_EUNSUPPORTED;
+  if ((long)p->np * p->np * p->np >= (1L << 32) - 1) return COLA_EUNSUPPORTED;
+  return COLA_OK;
+}
+
+Layout layout(const cola_params* p) {
+  Layout L{};
+  const long np3 = (long)p->np * p->np * p->np;
+  const long nt = p->nmesh / 8;
+  L.nbucket = 8 * nt * nt * nt;
+  L.mesh_stride = mesh_complex_count(p->nmesh);
+  const long pm = 3 * L.mesh_stride, ic = 4 * mesh_complex_count(p->np);
+  L.mesh_region = pm > ic ? pm : ic;
+  L.amp_len = 3L * (p->np / 2) * (p->np / 2) + 1;
+  L.tw_cap = p->nmesh > p->np ? p->nmesh : p->np;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  L.disp = take(3 * np3 * sizeof(float));
+  L.vres = take(3 * np3 * sizeof(float));
+  L.psi1 = take(3 * np3 * sizeof(float));
+  L.psi2 = take(3 * np3 * sizeof(float));
+  L.pkey = take(np3 * sizeof(uint32_t));
+  L.prank = take(np3 * sizeof(uint32_t));
+  L.perm = take(np3 * sizeof(uint32_t));
+  L.counts = take((L.nbucket + 1) * sizeof(uint32_t));
+  L.offsets = take((L.nbucket + 1) * sizeof(uint32_t));
+  L.scan = take(((L.nbucket + 1) / 4096 + 2) * sizeof(uint32_t));
+  L.mesh = take(L.mesh_region * sizeof(float2));
+  L.tw = take(4 * (size_t)L.tw_cap * sizeof(float2));
+  L.amp = take(L.amp_len * sizeof(float));
+  L.pk_partial = take((size_t)kMaxBins * kPkChunks * 3 * sizeof(double));
+  L.pk_out = take((size_t)kMaxBins * 3 * sizeof(double));
+  L.pk_edges = take((size_t)(kMaxBins + 1) * sizeof(double));
+  L.flag = take(sizeof(uint32_t) * 64);
+  L.total = o;
+  return L;
+}
+
+// Uploads exp(-2 pi i k / n) for k < n into a free twiddle slot.
+int ensure_twiddles(cola_ctx* c, int n) {
+  if (c->tw.get(n)) return COLA_OK;
+  for (int i = 0; i < 4; ++i) {
+    if (c->tw.n[i] == 0) {
+      if (n > c->tw_cap) return fail(c, COLA_EINVAL, "transform length exceeds the twiddle capacity");
+      std::vector<float2> h(n);
+      for (int k = 0; k < n; ++k) {
+        const double a = -2.0 * kPi * (double)k / (double)n;
+        h[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+      }
+      float2* dst = c->twbuf + (size_t)i * c->tw_cap;
+      HIP_TRY(c, hipMemcpyAsync(dst, h.data(), n * sizeof(float2), hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      c->tw.n[i] = n;
+      c->tw.tw[i] = dst;
+      return COLA_OK;
+    }
+  }
+  // all slots taken: recycle the last slot (never the PM or particle grids, slots 0 and 1)
+  c->tw.n[3] = 0;
+  return ensure_twiddles(c, n);
+}
+
+float2* ic_buf(cola_ctx* c, int i) { return c->meshbase + (size_t)i * mesh_complex_count(c->p.np); }
+
+// Tile sort of the current positions on an ng^3 grid.
+void tile_sort(cola_ctx* c, int ng) {
+  const float dscale = (float)((double)ng / (double)c->p.nmesh);
+  const long nt = ng / 8;
+  const long nb = 8 * nt * nt * nt;
+  launch_fill_u32(c->counts, nb + 1, 0u, c->stream);
+  launch_bin_count(c->disp, c->p.np, ng, dscale, c->counts, c->pkey, c->prank, c->stream);
+  launch_exclusive_scan(c->counts, c->offsets, nb, c->scan_scratch, c->stream);
+  launch_scatter(c->pkey, c->prank, c->offsets, c->np3, c->perm, c->stream);
+}
+
+void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast) {
+  const float dscale = (float)((double)ng / (double)c->p.nmesh);
+  tile_sort(c, ng);
+  launch_deposit(c->disp, c->perm, c->offsets, c->p.np, ng, dscale, out, row_stride, contrast,
+                 c->stream);
+}
+
+// Deposit + FFT + Green x ik + inverse FFTs: the three force meshes in c->mesh[0..2].
+void force_meshes(cola_ctx* c, double alpha) {
+  const int nm = c->p.nmesh;
+  const long rs = 2 * padded_cols(nm);
+  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1);
+  fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream);
+  fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream);
+  XPassArgs a;
+  a.in = c->mesh[0];
+  a.out[0] = c->mesh[0];
+  a.out[1] = c->mesh[1];
+  a.out[2] = c->mesh[2];
+  a.mode = X_FWD_GREEN3;
+  // g_d = IDFT[i n_d alpha nm / (2 pi |n|^2) DFT(delta)] / nm^3, in mesh units.
+  a.scale = (float)(alpha * nm / (2.0 * kPi) / ((double)nm * nm * nm));
+  fft_x(a, nm, c->tw, c->stream);
+  fft_y(c->mesh[0], nm, 3, c->mesh_stride, 1, c->tw, c->stream);
+  fft_c2r_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream);
+}
+
+bool same_a(double a, double b) { return std::fabs(a - b) <= 1e-12 * (std::fabs(a) > 1 ? std::fabs(a) : 1.0); }
+
+void step_scalars(const cola_params* p, double a_x, double a_v, double a1, double* o) {
+  const double om = p->omega_m, n = p->n_lpt;
+  const double ah = 0.5 * (a_x + a1);
+  const double d1a = growth_D1(a_x, om), d1b = growth_D1(a1, om);
+  const double d2a = growth_D2(a_x, om), d2b = growth_D2(a1, om);
+  o[0] = 1.5 * om / a_x;
+  o[1] = d1a;
+  o[2] = d2a;
+  o[3] = d1b - d1a;
+  o[4] = d2b - d2a;
+  o[5] = kick_factor(a_v, a_x, ah, om, n);
+  o[6] = drift_factor(a_x, a1, ah, om, n);
+  o[7] = ah;
+  o[8] = d1b;
+  o[9] = d2b;
+}
+
+int check_finite(cola_ctx* c) {
+  if (!(c->p.flags & COLA_F_CHECK_FINITE)) return COLA_OK;
+  launch_fill_u32(c->flag, 1, 0u, c->stream);
+  launch_check_finite(c->disp, 3 * c->np3, c->flag, c->stream);
+  launch_check_finite(c->vres, 3 * c->np3, c->flag, c->stream);
+  LAUNCH_CHECK(c, "check_finite");
+  uint32_t h = 0;
+  HIP_TRY(c, hipMemcpyAsync(&h, c->flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h) return fail(c, COLA_ENONFINITE, "non-finite value in the particle state");
+  return COLA_OK;
+}
+
+int ic_from_mesh_noise(cola_ctx* c, const double* k, const double* pk, int nk) {
+  const int np = c->p.np, nm = c->p.nmesh;
+  const long rs = 2 * padded_cols(np);
+  const double box = c->p.box;
+  // amplitude table sqrt(P(|k|) / dq^3) by integer |n|^2
+  std::vector<float> amp(c->amp_len);
+  const double kf = 2.0 * kPi / box, dq3 = std::pow(box / np, 3);
+  for (long n2 = 0; n2 < c->amp_len; ++n2)
+    amp[n2] = n2 == 0 ? 0.f : (float)std::sqrt(interp_pk(kf * std::sqrt((double)n2), k, pk, nk) / dq3);
+  HIP_TRY(c, hipMemcpyAsync(c->amp, amp.data(), amp.size() * sizeof(float), hipMemcpyHostToDevice,
+                            c->stream));
+  float2* A = ic_buf(c, 0);
+  float2* B[3] = {ic_buf(c, 1), ic_buf(c, 2), ic_buf(c, 3)};
+  // delta_L(k) = DFT[w] sqrt(P / dq^3), k = 0 and Nyquist-index modes zeroed
+  fft_r2c_z(A, np, 1, 0, c->tw, c->stream);
+  fft_y(A, np, 1, 0, 0, c->tw, c->stream);
+  XPassArgs xa;
+  xa.in = A;
+  xa.out[0] = A;
+  xa.mode = X_FWD_AMP;
+  xa.amp = c->amp;
+  fft_x(xa, np, c->tw, c->stream);
+  const double inv3 = 1.0 / ((double)np * np * np);
+  const float sgrad = (float)(nm / (2.0 * kPi) * inv3);  // mesh units of the PM grid
+  auto inverse_into = [&](const float2* in, float2* out, int kind, int ca, int cb, float scale) {
+    XPassArgs m;
+    m.in = in;
+    m.out[0] = out;
+    m.mode = X_MULT_INV;
+    m.mult = kind;
+    m.comp_a = ca;
+    m.comp_b = cb;
+    m.scale = scale;
+    fft_x(m, np, c->tw, c->stream);
+    fft_y(out, np, 1, 0, 1, c->tw, c->stream);
+    fft_c2r_z(out, np, 1, 0, c->tw, c->stream);
+  };
+  // Psi1_d = IDFT[i k_d delta_L / k^2]
+  for (int d = 0; d < 3; ++d) {
+    inverse_into(A, B[0], M_GRAD, d, 0, sgrad);
+    launch_copy_from_mesh(reinterpret_cast<float*>(B[0]), np, rs, c->psi1 + d * c->np3, 1.0f, c->stream);
+  }
+  // S = phi_xx phi_yy + phi_yy phi_zz + phi_zz phi_xx - phi_xy^2 - phi_yz^2 - phi_zx^2
+  for (int d = 0; d < 3; ++d) inverse_into(A, B[d], M_HESS, d, d, (float)inv3);
+  float* S = reinterpret_cast<float*>(B[0]);
+  launch_source_diag(S, reinterpret_cast<float*>(B[1]), reinterpret_cast<float*>(B[2]), np, rs, c->stream);
+  const int off[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+  for (int q = 0; q < 3; ++q) {
+    inverse_into(A, B[1], M_HESS, off[q][0], off[q][1], (float)inv3);
+    launch_source_sub_sq(S, reinterpret_cast<float*>(B[1]), np, rs, c->stream);
+  }
+  // Psi2_d = IDFT[-i k_d S(k) / k^2]
+  fft_r2c_z(B[0], np, 1, 0, c->tw, c->stream);
+  fft_y(B[0], np, 1, 0, 0, c->tw, c->stream);
+  XPassArgs fx;
+  fx.in = B[0];
+  fx.out[0] = B[0];
+  fx.mode = X_FWD;
+  fft_x(fx, np, c->tw, c->stream);
+  for (int d = 0; d < 3; ++d) {
+    inverse_into(B[0], B[1], M_GRAD, d, 0, -sgrad);
+    launch_copy_from_mesh(reinterpret_cast<float*>(B[1]), np, rs, c->psi2 + d * c->np3, 1.0f, c->stream);
+  }
+  const double a0 = c->p.a_init;
+  launch_init_particles(c->disp, c->vres, c->psi1, c->psi2, c->np3,
+                        (float)growth_D1(a0, c->p.omega_m), (float)growth_D2(a0, c->p.omega_m),
+                        c->stream);
+  LAUNCH_CHECK(c, "init_2lpt");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // the amplitude table's host copy is released here
+  c->a_x = c->a_v = a0;
+  c->have_state = true;
+  return COLA_OK;
+}
+
+int check_table(const double* k, const double* pk, int nk) {
+  if (!k || !pk || nk < 2) return COLA_EINVAL;
+  for (int i = 0; i < nk; ++i) {
+    if (!(k[i] > 0) || !(pk[i] > 0) || !std::isfinite(k[i]) || !std::isfinite(pk[i])) return COLA_EINVAL;
+    if (i > 0 && !(k[i] > k[i - 1])) return COLA_EINVAL;
+  }
+  return COLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cola_params_default(cola_params* p, int32_t np, int32_t nmesh, double box) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->np = np;
+  p->nmesh = nmesh;
+  p->box = box;
+  p->omega_m = 0.27;
+  p->n_lpt = -2.5;
+  p->a_init = 0.02;
+  p->flags = 0;
+}
+
+int cola_workspace_query(const cola_params* p, size_t* bytes) {
+  if (!bytes) return COLA_EINVAL;
+  const int v = validate(p);
+  if (v != COLA_OK) return v;
+  *bytes = layout(p).total;
+  return COLA_OK;
+}
+
+int cola_create(const cola_params* p, void* ws, size_t bytes, void* stream, cola_ctx** out) {
+  if (!out) return COLA_EINVAL;
+  *out = nullptr;
+  const int v = validate(p);
+  if (v != COLA_OK) return v;
+  if (!ws || ((uintptr_t)ws & 255)) return COLA_EINVAL;
+  const Layout L = layout(p);
+  if (bytes < L.total) return COLA_ENOMEM;
+  cola_ctx* c = new (std::nothrow) cola_ctx();
+  if (!c) return COLA_ENOMEM;
+  c->p = *p;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)ws;
+  c->ws_bytes = bytes;
+  c->np3 = (long)p->np * p->np * p->np;
+  c->disp = (float*)(c->ws + L.disp);
+  c->vres = (float*)(c->ws + L.vres);
+  c->psi1 = (float*)(c->ws + L.psi1);
+  c->psi2 = (float*)(c->ws + L.psi2);
+  c->pkey = (uint32_t*)(c->ws + L.pkey);
+  c->prank = (uint32_t*)(c->ws + L.prank);
+  c->perm = (uint32_t*)(c->ws + L.perm);
+  c->counts = (uint32_t*)(c->ws + L.counts);
+  c->offsets = (uint32_t*)(c->ws + L.offsets);
+  c->scan_scratch = (uint32_t*)(c->ws + L.scan);
+  c->nbucket = L.nbucket;
+  c->meshbase = (float2*)(c->ws + L.mesh);
+  c->mesh_stride = L.mesh_stride;
+  c->mesh_region = L.mesh_region;
+  for (int i = 0; i < 3; ++i) c->mesh[i] = c->meshbase + (size_t)i * L.mesh_stride;
+  c->twbuf = (float2*)(c->ws + L.tw);
+  c->tw_cap = L.tw_cap;
+  c->amp = (float*)(c->ws + L.amp);
+  c->amp_len = L.amp_len;
+  c->pk_partial = (double*)(c->ws + L.pk_partial);
+  c->pk_out = (double*)(c->ws + L.pk_out);
+  c->pk_edges = (double*)(c->ws + L.pk_edges);
+  c->flag = (uint32_t*)(c->ws + L.flag);
+  int r = ensure_twiddles(c, p->nmesh);
+  if (r == COLA_OK) r = ensure_twiddles(c, p->np);
+  if (r != COLA_OK) {
+    delete c;
+    return r;
+  }
+  // second slot is always the particle grid's; keep slots 0/1 fixed
+  *out = c;
+  return COLA_OK;
+}
+
+int cola_destroy(cola_ctx* c) {
+  if (!c) return COLA_EINVAL;
+  delete c;
+  return COLA_OK;
+}
+
+int cola_init_2lpt_from_noise(cola_ctx* c, const float* noise, const double* k, const double* pk,
+                              int32_t nk) {
+  if (!c || !noise) return fail(c, COLA_EINVAL, "null argument");
+  if (check_table(k, pk, nk) != COLA_OK) return fail(c, COLA_EINVAL, "bad P(k) table");
+  const long rs = 2 * padded_cols(c->p.np);
+  launch_copy_to_mesh(noise, c->p.np, reinterpret_cast<float*>(ic_buf(c, 0)), rs, c->stream);
+  LAUNCH_CHECK(c, "copy noise");
+  return ic_from_mesh_noise(c, k, pk, nk);
+}
+
+int cola_init_2lpt(cola_ctx* c, uint64_t seed, const double* k, const double* pk, int32_t nk,
+                   double box, int32_t np) {
+  if (!c) return COLA_EINVAL;
+  if (np != c->p.np || !(std::fabs(box - c->p.box) <= 1e-12 * c->p.box))
+    return fail(c, COLA_EINVAL, "box/np differ from the context parameters");
+  if (check_table(k, pk, nk) != COLA_OK) return fail(c, COLA_EINVAL, "bad P(k) table");
+  const long rs = 2 * padded_cols(c->p.np);
+  launch_philox_noise(seed, c->p.np, reinterpret_cast<float*>(ic_buf(c, 0)), rs, c->stream);
+  LAUNCH_CHECK(c, "philox noise");
+  return ic_from_mesh_noise(c, k, pk, nk);
+}
+
+int cola_noise(cola_ctx* c, uint64_t seed, float* out) {
+  if (!c || !out) return fail(c, COLA_EINVAL, "null argument");
+  launch_philox_noise(seed, c->p.np, out, c->p.np, c->stream);
+  LAUNCH_CHECK(c, "philox noise");
+  return COLA_OK;
+}
+
+int cola_step(cola_ctx* c, double a0, double a1) {
+  if (!c) return COLA_EINVAL;
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no initial conditions");
+  if (!same_a(a0, c->a_x)) return fail(c, COLA_ESTATE, "a0 differs from the current position time");
+  if (!(a1 > a0) || !std::isfinite(a1)) return fail(c, COLA_EINVAL, "a1 must exceed a0");
+  double s[10];
+  step_scalars(&c->p, c->a_x, c->a_v, a1, s);
+  const double alpha = s[0], D1 = s[1], D2 = s[2], K = s[5], I = s[6];
+  KickDrift kd;
+  kd.K = (float)K;
+  kd.c1 = (float)(K * alpha * D1);
+  kd.c2 = (float)(K * alpha * (D2 - D1 * D1));
+  kd.I = (float)I;
+  kd.e1 = (float)s[3];
+  kd.e2 = (float)s[4];
+  force_meshes(c, alpha);
+  const long rs = 2 * padded_cols(c->p.nmesh);
+  launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
+                            reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
+                            c->psi2, c->p.np, c->p.nmesh, kd, nullptr, c->stream);
+  LAUNCH_CHECK(c, "cola_step");
+  c->a_v = s[7];
+  c->a_x = a1;
+  return check_finite(c);
+}
+
+int cola_force(cola_ctx* c, float* out) {
+  if (!c || !out) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  const double alpha = 1.5 * c->p.omega_m / c->a_x;
+  force_meshes(c, alpha);
+  KickDrift kd{};
+  const long rs = 2 * padded_cols(c->p.nmesh);
+  launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
+                            reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
+                            c->psi2, c->p.np, c->p.nmesh, kd, out, c->stream);
+  LAUNCH_CHECK(c, "cola_force");
+  return COLA_OK;
+}
+
+int cola_density(cola_ctx* c, float* out) {
+  if (!c || !out) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  deposit(c, c->p.nmesh, out, c->p.nmesh, 1);
+  LAUNCH_CHECK(c, "cola_density");
+  return COLA_OK;
+}
+
+int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double* kmean, double* pk,
+            int64_t* nmodes) {
+  if (!c || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  if (nbins < 1 || nbins > kMaxBins) return fail(c, COLA_EINVAL, "nbins out of range");
+  if (ng < 16 || ng > c->p.nmesh || ng % 8 != 0 || !smooth23(ng))
+    return fail(c, COLA_EUNSUPPORTED, "ngrid must be a {2,3}-smooth multiple of 8 in [16, nmesh]");
+  for (int i = 0; i < nbins; ++i)
+    if (!(edges[i + 1] > edges[i])) return fail(c, COLA_EINVAL, "edges must increase");
+  int r = ensure_twiddles(c, ng);
+  if (r != COLA_OK) return r;
+  HIP_TRY(c, hipMemcpyAsync(c->pk_edges, edges, (nbins + 1) * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  float2* m = c->mesh[0];
+  deposit(c, ng, reinterpret_cast<float*>(m), 2 * padded_cols(ng), 1);
+  fft3d_forward(m, ng, c->tw, c->stream);
+  launch_pk_bin(m, ng, c->p.box, c->pk_edges, nbins, c->pk_partial, kPkChunks, c->stream);
+  launch_pk_reduce(c->pk_partial, nbins, kPkChunks, c->pk_out, c->stream);
+  LAUNCH_CHECK(c, "cola_pk");
+  std::vector<double> h(3 * (size_t)nbins);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), c->pk_out, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < nbins; ++b) {
+    const double n = h[3 * b + 2];
+    nmodes[b] = (int64_t)llround(n);
+    kmean[b] = n > 0 ? h[3 * b] / n : NAN;
+    pk[b] = n > 0 ? h[3 * b + 1] / n : NAN;
+  }
+  return COLA_OK;
+}
+
+int cola_get_state(cola_ctx* c, float* d, float* v, float* p1, float* p2, double* ax, double* av) {
+  if (!c) return COLA_EINVAL;
+  const size_t b = 3 * c->np3 * sizeof(float);
+  if (d) HIP_TRY(c, hipMemcpyAsync(d, c->disp, b, hipMemcpyDeviceToDevice, c->stream));
+  if (v) HIP_TRY(c, hipMemcpyAsync(v, c->vres, b, hipMemcpyDeviceToDevice, c->stream));
+  if (p1) HIP_TRY(c, hipMemcpyAsync(p1, c->psi1, b, hipMemcpyDeviceToDevice, c->stream));
+  if (p2) HIP_TRY(c, hipMemcpyAsync(p2, c->psi2, b, hipMemcpyDeviceToDevice, c->stream));
+  if (ax) *ax = c->a_x;
+  if (av) *av = c->a_v;
+  return COLA_OK;
+}
+
+int cola_set_state(cola_ctx* c, const float* d, const float* v, const float* p1, const float* p2,
+                   double ax, double av) {
+  if (!c) return COLA_EINVAL;
+  if (!(ax > 0) || !(av > 0)) return fail(c, COLA_EINVAL, "scale factors must be positive");
+  if (!c->have_state && (!d || !v || !p1 || !p2))
+    return fail(c, COLA_ESTATE, "first set_state must provide every array");
+  const size_t b = 3 * c->np3 * sizeof(float);
+  if (d) HIP_TRY(c, hipMemcpyAsync(c->disp, d, b, hipMemcpyDeviceToDevice, c->stream));
+  if (v) HIP_TRY(c, hipMemcpyAsync(c->vres, v, b, hipMemcpyDeviceToDevice, c->stream));
+  if (p1) HIP_TRY(c, hipMemcpyAsync(c->psi1, p1, b, hipMemcpyDeviceToDevice, c->stream));
+  if (p2) HIP_TRY(c, hipMemcpyAsync(c->psi2, p2, b, hipMemcpyDeviceToDevice, c->stream));
+  c->a_x = ax;
+  c->a_v = av;
+  c->have_state = true;
+  return COLA_OK;
+}
+
+int cola_fft3d(cola_ctx* c, int32_t n, float* mesh, int32_t inverse) {
+  if (!c || !mesh) return fail(c, COLA_EINVAL, "null argument");
+  if (n != c->p.np && n != c->p.nmesh) return fail(c, COLA_EINVAL, "n must be np or nmesh");
+  if (inverse) fft3d_inverse(reinterpret_cast<float2*>(mesh), n, c->tw, c->stream);
+  else fft3d_forward(reinterpret_cast<float2*>(mesh), n, c->tw, c->stream);
+  LAUNCH_CHECK(c, "cola_fft3d");
+  return COLA_OK;
+}
+
+int cola_step_scalars(const cola_params* p, double a_x, double a_v, double a1, double* out) {
+  if (!p || !out || !(a_x > 0) || !(a_v > 0) || !(a1 > 0)) return COLA_EINVAL;
+  step_scalars(p, a_x, a_v, a1, out);
+  return COLA_OK;
+}
+
+int cola_synchronize(cola_ctx* c) {
+  if (!c) return COLA_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return COLA_OK;
+}
+
+const char* cola_strerror(int code) {
+  switch (code) {
+    case COLA_OK: return "ok";
+    case COLA_EINVAL: return "invalid argument";
+    case COLA_ENOMEM: return "workspace too small";
+    case COLA_ESTATE: return "invalid state for this call";
+    case COLA_EUNSUPPORTED: return "unsupported size";
+    case COLA_EHIP: return "HIP runtime error";
+    case COLA_ENONFINITE: return "non-finite value in the state";
+    default: return "unknown error";
+  }
+}
+
+const char* cola_last_error(const cola_ctx* c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

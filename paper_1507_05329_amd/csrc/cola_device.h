@@ -1,0 +1,68 @@
+// Device helpers shared by the libcola kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cola {
+
+// Home cell and fractional offset of particle `id` (CIC, nodes at cell
+// centres).  Lattice point of axis e sits at i_e * nm / np cells; the node
+// coordinate is u = i_e nm / np - 1/2 + d_e, computed as
+//   qi = (i_e nm) div np,  qf = float(2 rem - np) / float(2 np)   (-1/2 exactly
+//   when nm/np is whole),  u = qf + d_e,  cell = qi + floor(u),  f = u - floor(u).
+// Every step is a single correctly rounded float32 operation so the deposit
+// is reproducible bit for bit.  `nm` is the target grid; displacements are
+// stored in cells of the PM mesh and multiplied by dscale = target/PM
+// (exactly 1 on the PM mesh, where the product is the identity).
+__device__ __forceinline__ void home_cell(const float* __restrict__ disp, long np3, uint32_t id,
+                                          int np, int nm, float dscale, int c[3], float f[3]) {
+  const uint32_t unp = (uint32_t)np;
+  const uint32_t li[3] = {id / (unp * unp), (id / unp) % unp, id % unp};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const long t = (long)li[e] * nm;
+    const int qi = (int)(t / np);
+    const int rem = (int)(t - (long)qi * np);
+    const float qf = __fdiv_rn((float)(2 * rem - np), (float)(2 * np));
+    const float u = __fadd_rn(qf, __fmul_rn(disp[e * np3 + id], dscale));
+    const float fl = floorf(u);
+    f[e] = __fsub_rn(u, fl);
+    int ci = (qi + (int)fl) % nm;
+    c[e] = ci < 0 ? ci + nm : ci;
+  }
+}
+
+// CIC weight of offset k = 4 sx + 2 sy + sz: (w_sx(fx) * w_sy(fy)) * w_sz(fz),
+// w_0(f) = 1 - f, w_1(f) = f; two float32 roundings, no fused multiply-add.
+__device__ __forceinline__ float cic_weight(const float f[3], int k) {
+  const float wx = (k & 4) ? f[0] : __fsub_rn(1.0f, f[0]);
+  const float wy = (k & 2) ? f[1] : __fsub_rn(1.0f, f[1]);
+  const float wz = (k & 1) ? f[2] : __fsub_rn(1.0f, f[2]);
+  return __fmul_rn(__fmul_rn(wx, wy), wz);
+}
+
+// Tile (8^3 cells) and class bits of a home cell: class bit 4/2/1 set when
+// the cell is on the upper x/y/z face of its tile (it then also feeds nodes
+// of the next tile along that axis).
+__device__ __forceinline__ uint32_t bucket_of(const int c[3], int nt) {
+  const uint32_t tile = ((uint32_t)(c[0] >> 3) * nt + (uint32_t)(c[1] >> 3)) * nt + (uint32_t)(c[2] >> 3);
+  const uint32_t cls = (((c[0] & 7) == 7) << 2) | (((c[1] & 7) == 7) << 1) | ((c[2] & 7) == 7);
+  return tile * 8u + cls;
+}
+
+// Workgroup order across the 8 XCDs of the chip: consecutive hardware
+// workgroup ids go to different XCDs; remap so each XCD walks a contiguous
+// range of tiles (shared cache lines stay in one XCD's L2).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
+  const uint32_t nx = 8;
+  const uint32_t per = (nblocks + nx - 1) / nx;
+  const uint32_t xcd = bid % nx, local = bid / nx;
+  const uint32_t full = nblocks % nx == 0 ? nx : nblocks % nx;  // XCDs that get `per` blocks
+  uint32_t base;
+  if (xcd < full) base = xcd * per;
+  else base = full * per + (xcd - full) * (per - 1);
+  return base + local;
+}
+
+}  // namespace cola

@@ -1,0 +1,149 @@
+// Internal declarations of libcola: context layout, host scalars, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <string>
+
+#include "../../include/cola.h"
+
+namespace cola {
+
+// ---------------------------------------------------------------------------
+// FFT plan: a {2,3}-smooth length factored into radices {16, 8, 4, 3, 2}.
+struct FftPlan {
+  int n = 0;          // transform length
+  int nstage = 0;
+  int radix[12] = {};
+};
+bool make_plan(int n, FftPlan* plan);
+
+// Padded complex row length of an n^3 real mesh in the r2c layout: the
+// (n/2+1) half-spectrum rounded up to 16 complex values (128-byte rows).
+inline long padded_cols(int n) { return ((long)(n / 2 + 1) + 15) / 16 * 16; }
+inline long mesh_complex_count(int n) { return (long)n * n * padded_cols(n); }
+
+// Twiddle tables: one per distinct length, tw[k] = exp(-2 pi i k / n).
+struct TwiddleSet {
+  int n[4] = {0, 0, 0, 0};
+  const float2* tw[4] = {nullptr, nullptr, nullptr, nullptr};
+  const float2* get(int len) const {
+    for (int i = 0; i < 4; ++i) if (n[i] == len) return tw[i];
+    return nullptr;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Host FP64 scalars of the method (cosmo.cpp).
+double hubble_E(double a, double om);
+double growth_D1(double a, double om);
+double growth_D2(double a, double om);
+double kick_factor(double a_v, double a_x, double a_h, double om, double n);
+double drift_factor(double a0, double a1, double a_h, double om, double n);
+// ln-ln interpolation of a P(k) table, end segments extended.
+double interp_pk(double k, const double* kt, const double* pt, int nk);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (all asynchronous on `s`).
+// Tile sort of particles by the 8^3 tile of their home cell (k_sort.hip).
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
+void launch_bin_count(const float* disp, int np, int nm, float dscale, uint32_t* counts,
+                      uint32_t* pkey, uint32_t* prank, hipStream_t s);
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, long n,
+                           uint32_t* scratch, hipStream_t s);
+void launch_scatter(const uint32_t* pkey, const uint32_t* prank, const uint32_t* off,
+                    long np3, uint32_t* perm, hipStream_t s);
+// Deterministic CIC gather (k_deposit.hip).
+void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off,
+                    int np, int nm, float dscale, float* out, long row_stride, int contrast,
+                    hipStream_t s);
+// FFT passes (k_fft.hip).
+enum XMode { X_FWD = 0, X_FWD_GREEN3 = 1, X_FWD_AMP = 2, X_MULT_INV = 3, X_INV = 4 };
+enum MultKind { M_NONE = 0, M_GRAD = 1, M_HESS = 2 };
+struct XPassArgs {
+  const float2* in = nullptr;
+  float2* out[3] = {nullptr, nullptr, nullptr};
+  int mode = X_FWD;
+  int mult = M_NONE;
+  int comp_a = 0, comp_b = 0;   // gradient axis / Hessian axes
+  float scale = 1.f;            // multiplier scale
+  const float* amp = nullptr;   // amplitude by integer |n|^2 (X_FWD_AMP)
+};
+void fft3d_forward(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
+void fft3d_inverse(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
+void fft_r2c_z(float2* mesh, int n, int nplanes_mesh, long mesh_stride, const TwiddleSet& tw, hipStream_t s);
+void fft_c2r_z(float2* mesh, int n, int nmesh_batch, long mesh_stride, const TwiddleSet& tw, hipStream_t s);
+void fft_y(float2* mesh, int n, int nmesh_batch, long mesh_stride, int inverse,
+           const TwiddleSet& tw, hipStream_t s);
+void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s);
+// Force readout + kick/drift (k_particles.hip).
+struct KickDrift {
+  float K, c1, c2;     // v += K F - c1 Psi1 - c2 Psi2
+  float I, e1, e2;     // d += I v + e1 Psi1 + e2 Psi2
+};
+void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2,
+                               long row_stride, float* disp, float* vres,
+                               const float* psi1, const float* psi2, int np, int nm,
+                               const KickDrift& kd, float* force_out, hipStream_t s);
+// Initial conditions (k_ic.hip).
+void launch_philox_noise(uint64_t seed, int np, float* out, long row_stride, hipStream_t s);
+void launch_copy_to_mesh(const float* src, int n, float* mesh, long row_stride, hipStream_t s);
+void launch_copy_from_mesh(const float* mesh, int n, long row_stride, float* dst, float scale,
+                           hipStream_t s);
+void launch_source_diag(float* a, const float* b, const float* c, int n, long row_stride,
+                        hipStream_t s);
+void launch_source_sub_sq(float* a, const float* b, int n, long row_stride, hipStream_t s);
+void launch_init_particles(float* disp, float* vres, const float* psi1, const float* psi2,
+                           long np3, float D1, float D2, hipStream_t s);
+void launch_axpby(float* y, const float* x, float a, float b, long n, hipStream_t s);
+// Power spectrum binning (k_pk.hip).
+void launch_pk_bin(const float2* spec, int ng, double box, const double* edges, int nbins,
+                   double* partial, int nchunk, hipStream_t s);
+void launch_pk_reduce(const double* partial, int nbins, int nchunk, double* out, hipStream_t s);
+// Non-finite check.
+void launch_check_finite(const float* x, long n, uint32_t* flag, hipStream_t s);
+
+}  // namespace cola
+
+// ---------------------------------------------------------------------------
+struct cola_ctx {
+  cola_params p;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  long np3 = 0;
+  // particle state, SoA 3 * np3 each
+  float* disp = nullptr;
+  float* vres = nullptr;
+  float* psi1 = nullptr;
+  float* psi2 = nullptr;
+  // tile sort
+  uint32_t* pkey = nullptr;
+  uint32_t* prank = nullptr;
+  uint32_t* perm = nullptr;
+  uint32_t* counts = nullptr;   // nbucket + 1
+  uint32_t* offsets = nullptr;  // nbucket + 1
+  uint32_t* scan_scratch = nullptr;
+  long nbucket = 0;
+  // mesh region: 3 padded complex half meshes of nmesh (PM step), also
+  // carved into 4 meshes of np for the initial conditions
+  float2* meshbase = nullptr;
+  float2* mesh[3] = {nullptr, nullptr, nullptr};
+  long mesh_stride = 0;         // complex values per PM mesh
+  long mesh_region = 0;         // complex values in the region
+  // small buffers
+  float2* twbuf = nullptr;
+  cola::TwiddleSet tw;
+  int tw_cap = 0;               // complex values per twiddle slot
+  float* amp = nullptr;         // amplitude table by |n|^2 on the particle grid
+  long amp_len = 0;
+  double* pk_partial = nullptr;
+  double* pk_out = nullptr;
+  double* pk_edges = nullptr;
+  uint32_t* flag = nullptr;
+  // time state
+  double a_x = 0, a_v = 0;
+  bool have_state = false;
+  std::string err;
+};

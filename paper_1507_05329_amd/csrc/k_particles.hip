@@ -1,0 +1,76 @@
+// CIC force readout fused with the COLA kick and drift (Koda et al. 2015,
+// Sec. 2.2, eqs. cola-kick and cola-drift; 2LPT growing mode of Sec. 2.1).
+//
+// Per particle (Lagrangian order, one thread each):
+//   F_d   = sum_s w_s g_d[c + s]                      (same CIC weights as the deposit)
+//   v_d  += K F_d - c1 Psi1_d - c2 Psi2_d             (c1 = K alpha D1, c2 = K alpha (D2 - D1^2):
+//                                                      the residual force F - d^2/dt^2-term of 2LPT)
+//   d_d  += I v_d + e1 Psi1_d + e2 Psi2_d             (e1 = dD1, e2 = dD2)
+// All three force meshes are read before the particle's own position is
+// updated, so the update is in place.
+#include "cola_device.h"
+#include "cola_internal.h"
+
+namespace cola {
+
+__global__ __launch_bounds__(256) void k_readout_kick_drift(
+    const float* __restrict__ g0, const float* __restrict__ g1, const float* __restrict__ g2,
+    long row_stride, float* __restrict__ disp, float* __restrict__ vres,
+    const float* __restrict__ psi1, const float* __restrict__ psi2, int np, int nm, long np3,
+    KickDrift kd, float* __restrict__ force_out) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= np3) return;
+  int c[3];
+  float f[3];
+  const float dscale = 1.0f;
+  home_cell(disp, np3, (uint32_t)i, np, nm, dscale, c, f);
+  const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
+  const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
+  const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
+  const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
+                        ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
+  float F[3] = {0.f, 0.f, 0.f};
+  const float* g[3] = {g0, g1, g2};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float w = cic_weight(f, k);
+    const long idx = rows[k >> 1] + ((k & 1) ? cz1 : c[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) F[d] += w * g[d][idx];
+  }
+  if (force_out) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) force_out[d * np3 + i] = F[d];
+    return;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const long j = d * np3 + i;
+    const float p1 = psi1[j], p2 = psi2[j];
+    const float v = vres[j] + kd.K * F[d] - kd.c1 * p1 - kd.c2 * p2;
+    vres[j] = v;
+    disp[j] = disp[j] + kd.I * v + kd.e1 * p1 + kd.e2 * p2;
+  }
+}
+
+void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2, long row_stride,
+                               float* disp, float* vres, const float* psi1, const float* psi2,
+                               int np, int nm, const KickDrift& kd, float* force_out,
+                               hipStream_t s) {
+  const long np3 = (long)np * np * np;
+  hipLaunchKernelGGL(k_readout_kick_drift, dim3((unsigned)((np3 + 255) / 256)), dim3(256), 0, s,
+                     g0, g1, g2, row_stride, disp, vres, psi1, psi2, np, nm, np3, kd, force_out);
+}
+
+__global__ void k_check_finite(const float* __restrict__ x, long n, uint32_t* flag) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) { atomicOr(flag, 1u); return; }
+}
+
+void launch_check_finite(const float* x, long n, uint32_t* flag, hipStream_t s) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+}
+
+}  // namespace cola

@@ -1,0 +1,144 @@
+"""ColaSim: PyTorch-facing wrapper of a libcola context.
+
+PyTorch provides the device memory (the workspace and the in/out tensors)
+and the HIP stream; every computation runs in libcola's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, cola_params, dptr
+
+
+def _ptr(t: torch.Tensor):
+    assert t.is_cuda and t.is_contiguous(), "device tensor must be contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+class ColaSim:
+    """One COLA realisation on one GPU.
+
+    Particle arrays are (3, np^3) float32 in mesh-cell units; meshes are
+    (nmesh, nmesh, nmesh) float32, C order.
+    """
+
+    def __init__(self, np_side, nmesh, box, omega_m=0.27, n_lpt=-2.5, a_init=0.02,
+                 flags=0, device="cuda", stream=None):
+        self.lib = _lib.load()
+        p = cola_params()
+        self.lib.cola_params_default(C.byref(p), np_side, nmesh, box)
+        p.omega_m, p.n_lpt, p.a_init, p.flags = omega_m, n_lpt, a_init, flags
+        self.params = p
+        nbytes = C.c_size_t()
+        check(self.lib.cola_workspace_query(C.byref(p), C.byref(nbytes)), what="workspace_query")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        check(self.lib.cola_create(C.byref(p), _ptr(self.workspace), nbytes.value,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(ctx)),
+              what="create")
+        self.ctx = ctx
+        self.np_side, self.nmesh, self.box = np_side, nmesh, box
+        self.n_particles = np_side ** 3
+
+    def close(self):
+        if self.ctx:
+            self.lib.cola_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------
+    def _chk(self, code, what):
+        return check(code, self.ctx, what)
+
+    def particles(self):
+        return torch.empty((3, self.n_particles), dtype=torch.float32, device=self.device)
+
+    # -- initial conditions ------------------------------------------------
+    def init_from_noise(self, noise: torch.Tensor, k, pk):
+        k = np.ascontiguousarray(k, np.float64)
+        pk = np.ascontiguousarray(pk, np.float64)
+        self._chk(self.lib.cola_init_2lpt_from_noise(self.ctx, _ptr(noise), dptr(k), dptr(pk), len(k)),
+                  "init_2lpt_from_noise")
+
+    def init_2lpt(self, seed: int, k, pk):
+        k = np.ascontiguousarray(k, np.float64)
+        pk = np.ascontiguousarray(pk, np.float64)
+        self._chk(self.lib.cola_init_2lpt(self.ctx, seed, dptr(k), dptr(pk), len(k), self.box,
+                                          self.np_side), "init_2lpt")
+
+    def noise(self, seed: int) -> torch.Tensor:
+        out = torch.empty((self.np_side,) * 3, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.cola_noise(self.ctx, seed, _ptr(out)), "noise")
+        return out
+
+    # -- stepping and outputs ----------------------------------------------
+    def step(self, a0: float, a1: float):
+        self._chk(self.lib.cola_step(self.ctx, a0, a1), "step")
+
+    def run(self, edges):
+        for a0, a1 in zip(edges[:-1], edges[1:]):
+            self.step(a0, a1)
+
+    def density(self, out=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.nmesh,) * 3, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.cola_density(self.ctx, _ptr(out)), "density")
+        return out
+
+    def force(self, out=None) -> torch.Tensor:
+        if out is None:
+            out = self.particles()
+        self._chk(self.lib.cola_force(self.ctx, _ptr(out)), "force")
+        return out
+
+    def pk(self, edges, ngrid=None):
+        edges = np.ascontiguousarray(edges, np.float64)
+        nb = len(edges) - 1
+        km, p = np.zeros(nb), np.zeros(nb)
+        nm = np.zeros(nb, np.int64)
+        self._chk(self.lib.cola_pk(self.ctx, ngrid or self.nmesh, dptr(edges), nb, dptr(km), dptr(p),
+                                   nm.ctypes.data_as(C.POINTER(C.c_int64))), "pk")
+        return km, p, nm
+
+    def get_state(self):
+        d, v, p1, p2 = (self.particles() for _ in range(4))
+        ax, av = C.c_double(), C.c_double()
+        self._chk(self.lib.cola_get_state(self.ctx, _ptr(d), _ptr(v), _ptr(p1), _ptr(p2),
+                                          C.byref(ax), C.byref(av)), "get_state")
+        return dict(disp=d, vres=v, psi1=p1, psi2=p2, a_x=ax.value, a_v=av.value)
+
+    def set_state(self, disp, vres, psi1, psi2, a_x, a_v):
+        self._chk(self.lib.cola_set_state(self.ctx, _ptr(disp), _ptr(vres), _ptr(psi1), _ptr(psi2),
+                                          a_x, a_v), "set_state")
+
+    def fft3d(self, mesh: torch.Tensor, n: int, inverse=False):
+        self._chk(self.lib.cola_fft3d(self.ctx, n, _ptr(mesh), int(inverse)), "fft3d")
+
+    def synchronize(self):
+        self._chk(self.lib.cola_synchronize(self.ctx), "synchronize")
+
+
+def padded_cols(n: int) -> int:
+    """Complex values per row of the padded in-place r2c mesh layout."""
+    return ((n // 2 + 1) + 15) // 16 * 16
+
+
+def step_scalars(np_side, nmesh, box, a_x, a_v, a1, omega_m=0.27, n_lpt=-2.5):
+    lib = _lib.load()
+    p = cola_params()
+    lib.cola_params_default(C.byref(p), np_side, nmesh, box)
+    p.omega_m, p.n_lpt = omega_m, n_lpt
+    out = np.zeros(10)
+    check(lib.cola_step_scalars(C.byref(p), a_x, a_v, a1, dptr(out)), what="step_scalars")
+    return out

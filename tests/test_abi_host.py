@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: symbols, host FP64 scalars, argument validation."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import cosmology as cosmo
+from paper_1507_05329_amd import _lib
+from paper_1507_05329_amd.inputs import step_edges
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "cola.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cola_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(_lib.exported_symbols())
+
+
+def params(np_side=32, nmesh=64, box=100.0):
+    lib = _lib.load()
+    p = _lib.cola_params()
+    lib.cola_params_default(C.byref(p), np_side, nmesh, box)
+    return lib, p
+
+
+def test_host_step_scalars_match_oracle():
+    lib, p = params()
+    edges = step_edges()
+    a_v = edges[0]
+    for a0, a1 in zip(edges[:-1], edges[1:]):
+        out = np.zeros(10)
+        assert lib.cola_step_scalars(C.byref(p), a0, a_v, a1, _lib.dptr(out)) == 0
+        c = cosmo.step_coefficients(a0, a_v, a1, 0.27, -2.5)
+        ref = [c["alpha"], c["D1"], c["D2"], c["dD1"], c["dD2"], c["K"], c["I"], c["a_h"],
+               cosmo.growth_D1(a1, 0.27), cosmo.growth_D2(a1, 0.27)]
+        np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-15)
+        a_v = c["a_h"]
+
+
+@pytest.mark.parametrize("np_side,nmesh,code", [
+    (32, 60, _lib.COLA_EUNSUPPORTED),    # not a multiple of 8
+    (32, 40, _lib.COLA_EUNSUPPORTED),    # 40 = 8 * 5: prime factor 5
+    (31, 64, _lib.COLA_EUNSUPPORTED),    # odd particle grid
+    (64, 32, _lib.COLA_EUNSUPPORTED),    # mesh coarser than the particle grid
+    (32, 8, _lib.COLA_EINVAL),           # mesh too small
+])
+def test_workspace_query_rejects_bad_sizes(np_side, nmesh, code):
+    lib, p = params(np_side, nmesh)
+    n = C.c_size_t()
+    assert lib.cola_workspace_query(C.byref(p), C.byref(n)) == code
+
+
+def test_workspace_query_bad_cosmology_and_null():
+    lib, p = params()
+    p.omega_m = 0.0
+    n = C.c_size_t()
+    assert lib.cola_workspace_query(C.byref(p), C.byref(n)) == _lib.COLA_EINVAL
+    assert lib.cola_workspace_query(None, C.byref(n)) == _lib.COLA_EINVAL
+    lib, p = params()
+    assert lib.cola_workspace_query(C.byref(p), None) == _lib.COLA_EINVAL
+
+
+def test_workspace_size_scales_with_mesh():
+    lib, p = params(32, 64)
+    a = C.c_size_t()
+    assert lib.cola_workspace_query(C.byref(p), C.byref(a)) == 0
+    lib, p = params(32, 128)
+    b = C.c_size_t()
+    assert lib.cola_workspace_query(C.byref(p), C.byref(b)) == 0
+    assert b.value - a.value > 3 * 8 * (128 ** 2 * 80 - 64 ** 2 * 48)
+    # 768^3 mesh / 256^3 particles fits easily in 288 GB
+    lib, p = params(256, 768, 600.0)
+    c = C.c_size_t()
+    assert lib.cola_workspace_query(C.byref(p), C.byref(c)) == 0
+    assert c.value < 12e9
+
+
+def test_create_rejects_small_or_misaligned_workspace():
+    lib, p = params()
+    ctx = C.c_void_p()
+    n = C.c_size_t()
+    lib.cola_workspace_query(C.byref(p), C.byref(n))
+    # sizes are checked before any device access
+    assert lib.cola_create(C.byref(p), C.c_void_p(256), n.value - 1, None, C.byref(ctx)) == _lib.COLA_ENOMEM
+    assert lib.cola_create(C.byref(p), C.c_void_p(257), n.value, None, C.byref(ctx)) == _lib.COLA_EINVAL
+    assert lib.cola_create(C.byref(p), None, n.value, None, C.byref(ctx)) == _lib.COLA_EINVAL
+
+
+def test_strerror_codes():
+    lib = _lib.load()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.cola_strerror(code)
