@@ -1,0 +1,168 @@
+"""Throughput of the COLA PM step on one MI355X.
+
+Workload: 256^3 particles, 768^3 PM mesh (3x the particle grid), 600 Mpc/h
+box, flat LCDM Omega_m = 0.27, BBKS P(k) with sigma_8 = 0.8, Gaussian
+white-noise initial conditions (GPU Philox, seed 2) displaced by 2LPT,
+10 COLA steps uniform in a from 0.02 to 1.  A "step" is one cola_step: tile
+sort, deterministic CIC deposit, r2c FFT, Green's function x ik with three
+inverse FFTs, CIC readout fused with the kick/drift.
+
+Timed region: K consecutive steps of the 10-step schedule (K <= 10) after a
+fresh initial condition, inputs resident in HBM, bracketed by
+torch.cuda.synchronize().  A second pass with the library's per-stage HIP
+event timers gives the dominant kernel's achieved bandwidth against the
+8 TB/s HBM peak.  The FP64 CPU oracle is timed on one step of the same
+workload on the host cores (cpu_baseline).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(np_side: int, nm: int) -> dict:
+    """Algorithmic HBM bytes per launch of each stage (what the method must move)."""
+    n_p = np_side ** 3
+    M = nm ** 3
+    R = 4 * M                               # real float32 mesh
+    C = 8 * nm * nm * (nm // 2 + 1)         # complex half mesh
+    return {
+        "sort": 32 * n_p,                   # read d (12), write+read key/rank (16), write perm (4)
+        "deposit": 16 * n_p + R,            # read perm + d, write delta
+        "fft_z": R + C,                     # real in, half spectrum out
+        "fft_y": 2 * C,
+        "fft_x_green": 4 * C,               # 1 read, 3 writes (three force components)
+        "ifft_y": 6 * C,                    # three meshes, read + write
+        "ifft_z": 3 * (C + R),              # three meshes, half spectrum in, real out
+        "kick_drift": 72 * n_p + 3 * 4 * min(M, 8 * n_p),  # state r/w + CIC gathers
+    }
+
+
+def cpu_baseline(cfg, table, seed):
+    """One oracle step of the same workload on the host (FP64, NumPy/SciPy)."""
+    from oracle import cola
+    from paper_1507_05329_amd.inputs import white_noise, step_edges
+    cores = len(os.sched_getaffinity(0))
+    w = white_noise(seed, cfg.np_side)
+    st = cola.init_state(w, cfg.box, cfg.nmesh, *table)
+    e = step_edges()
+    t0 = time.perf_counter()
+    cola.step(st, e[1])
+    dt = time.perf_counter() - t0
+    return {"value": cfg.n_particles / dt, "unit": "particle-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"one FP64 oracle COLA step (a {e[0]:.3f}->{e[1]:.3f}) of the full "
+                      f"{cfg.np_side}^3/{cfg.nmesh}^3 workload, {dt:.1f} s, scipy.fft workers={cores}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="production")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    if not (1 <= args.steps <= 10) or not (0 <= args.warmup <= 10):
+        print("bench.py: --steps and --warmup must lie in [1, 10] and [0, 10] "
+              "(the workload is a 10-step run)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1507_05329_amd import _lib
+    from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges
+    from paper_1507_05329_amd.sim import ColaSim
+
+    cfg = CONFIGS[args.config]
+    table = bbks_table(cfg.omega_m, cfg.h, cfg.n_s, cfg.sigma8)
+    e = step_edges(cfg.a_init, cfg.a_final, cfg.nstep)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    sim = ColaSim(cfg.np_side, cfg.nmesh, cfg.box, omega_m=cfg.omega_m, n_lpt=cfg.n_lpt,
+                  a_init=cfg.a_init, device=dev)
+    # warm-up (also first-touch of the workspace and code objects)
+    sim.init_2lpt(cfg.seed, *table)
+    for i in range(args.warmup):
+        sim.step(e[i], e[i + 1])
+    sim.init_2lpt(cfg.seed, *table)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        sim.step(e[i], e[i + 1])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / args.steps * 1e3
+    value = cfg.n_particles * args.steps / dt
+    sim.close()
+    del sim
+
+    # per-stage timing pass (HIP events on the library's stream)
+    simt = ColaSim(cfg.np_side, cfg.nmesh, cfg.box, omega_m=cfg.omega_m, n_lpt=cfg.n_lpt,
+                   a_init=cfg.a_init, device=dev, flags=_lib.COLA_F_STAGE_TIMERS)
+    simt.init_2lpt(cfg.seed, *table)
+    simt.step(e[0], e[1])
+    simt.stage_times()
+    for i in range(1, args.steps if args.steps > 1 else 2):
+        simt.step(e[i], e[i + 1])
+    st = simt.stage_times()
+    simt.close()
+    sb = stage_bytes(cfg.np_side, cfg.nmesh)
+    stages = {}
+    for name, (ms, cnt) in st.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        stages[name] = {"ms": round(avg, 4), "GB/s": round(sb[name] / (avg * 1e-3) / 1e9, 1)}
+    dom = max(stages, key=lambda n: stages[n]["ms"])
+    dom_gbs = sb[dom] / (stages[dom]["ms"] * 1e-3) / 1e9
+    step_bytes = sum(sb.values())
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "step_bytes_alg": step_bytes,
+                "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, table, cfg.seed)
+
+    out = {
+        "metric": "particle-updates/s per COLA PM step (fwd)",
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (BBKS Gaussian random field, GPU Philox seed %d)" % cfg.seed,
+        "config": {"workload": cfg.name, "np": cfg.np_side, "nmesh": cfg.nmesh, "box": cfg.box,
+                   "nstep": cfg.nstep, "a": [cfg.a_init, cfg.a_final]},
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

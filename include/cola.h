@@ -46,6 +46,18 @@ extern "C" {
 #define COLA_ENONFINITE   -6   /* non-finite value found (COLA_F_CHECK_FINITE)     */
 
 #define COLA_F_CHECK_FINITE 1  /* after each step, check the state for NaN/Inf */
+#define COLA_F_STAGE_TIMERS 2  /* record HIP events around every stage of cola_step */
+
+/* Stages timed under COLA_F_STAGE_TIMERS (index into cola_stage_times). */
+#define COLA_STAGE_SORT      0  /* tile sort: bucket counts, scan, scatter          */
+#define COLA_STAGE_DEPOSIT   1  /* deterministic CIC gather                          */
+#define COLA_STAGE_FFT_Z     2  /* forward real-to-complex pass along z              */
+#define COLA_STAGE_FFT_Y     3  /* forward pass along y                              */
+#define COLA_STAGE_FFT_X     4  /* x pass: forward, Green's function x ik, inverse x3 */
+#define COLA_STAGE_IFFT_Y    5  /* inverse pass along y, 3 force meshes              */
+#define COLA_STAGE_IFFT_Z    6  /* inverse complex-to-real pass along z, 3 meshes    */
+#define COLA_STAGE_KICKDRIFT 7  /* CIC readout fused with kick and drift             */
+#define COLA_NSTAGE          8
 
 typedef struct cola_ctx cola_ctx;
 
@@ -145,6 +157,12 @@ int cola_fft3d(cola_ctx* ctx, int32_t n, float* dev_mesh, int32_t inverse);
  * out[0..9] = alpha, D1(a_x), D2(a_x), D1(a1)-D1(a_x), D2(a1)-D2(a_x),
  * K (kick factor), I (drift factor), a_h, D1(a1), D2(a1). */
 int cola_step_scalars(const cola_params* p, double a_x, double a_v, double a1, double* out);
+
+/* Under COLA_F_STAGE_TIMERS: synchronises, then writes per-stage totals
+ * (milliseconds, summed over the steps since the last call) to
+ * ms[COLA_NSTAGE] and the launch count per stage to count[COLA_NSTAGE]
+ * (either may be NULL), and resets the totals.  COLA_ESTATE without the flag. */
+int cola_stage_times(cola_ctx* ctx, double* ms, int64_t* count);
 
 int cola_synchronize(cola_ctx* ctx);
 const char* cola_strerror(int code);

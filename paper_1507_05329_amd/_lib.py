@@ -21,6 +21,8 @@ COLA_EUNSUPPORTED = -4
 COLA_EHIP = -5
 COLA_ENONFINITE = -6
 COLA_F_CHECK_FINITE = 1
+COLA_F_STAGE_TIMERS = 2
+STAGES = ["sort", "deposit", "fft_z", "fft_y", "fft_x_green", "ifft_y", "ifft_z", "kick_drift"]
 
 
 class cola_params(C.Structure):
@@ -50,6 +52,7 @@ _SIGS = {
     "cola_set_state": (C.c_int, [_P, _P, _P, _P, _P, _D, _D]),
     "cola_fft3d": (C.c_int, [_P, _I, _P, _I]),
     "cola_step_scalars": (C.c_int, [C.POINTER(cola_params), _D, _D, _D, _DP]),
+    "cola_stage_times": (C.c_int, [_P, _DP, C.POINTER(C.c_int64)]),
     "cola_synchronize": (C.c_int, [_P]),
     "cola_strerror": (C.c_char_p, [C.c_int]),
     "cola_last_error": (C.c_char_p, [_P]),

@@ -11,6 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcola.so")
 SOURCES = ["cola_api.cpp", "cosmo.cpp", "k_sort.hip", "k_deposit.hip", "k_fft.hip",
            "k_particles.hip", "k_ic.hip", "k_pk.hip"]
+# translation units whose float results must follow the written order bit for bit
+STRICT = {"k_sort.hip", "k_deposit.hip"}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -27,7 +29,8 @@ def build_library(verbose=False, jobs=8):
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC, *FLAGS, *lang, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        strict = ["-ffp-contract=off"] if src in STRICT else []
+        cmd = [HIPCC, *FLAGS, *strict, *lang, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

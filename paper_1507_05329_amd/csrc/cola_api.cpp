@@ -66,8 +66,8 @@ int validate(const cola_params* p) {
   if (p->np < 2 || p->nmesh < 16 || !(p->box > 0) || !(p->omega_m > 0) || p->omega_m > 1.0 ||
       !(p->a_init > 0) || p->n_lpt == 0.0 || !std::isfinite(p->n_lpt))
     return COLA_EINVAL;
-  if (p->np % 2 != 0 || !smooth23(p->np)) return COLA_EUNSUPPORTED;
-  if (p->nmesh % 8 != 0 || !smooth23(p->nmesh) || p->nmesh < p->np) return COLA_EUNSUPPORTED;
+  if (!fft_size_supported(p->np)) return COLA_EUNSUPPORTED;
+  if (p->nmesh % 8 != 0 || !fft_size_supported(p->nmesh) || p->nmesh < p->np) return COLA_EUNSUPPORTED;
   if ((long)p->np * p->np * p->np >= (1L << 32) - 1) return COLA_EUNSUPPORTED;
   return COLA_OK;
 }
@@ -129,10 +129,36 @@ int ensure_twiddles(cola_ctx* c, int n) {
   return ensure_twiddles(c, n);
 }
 
+// Stage timer: records an event pair around a stage when COLA_F_STAGE_TIMERS is set.
+struct StageTimer {
+  cola_ctx* c;
+  hipEvent_t stop = nullptr;
+  StageTimer(cola_ctx* ctx, int stage) : c(ctx) {
+    if (!(c->p.flags & COLA_F_STAGE_TIMERS)) { c = nullptr; return; }
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+      if (c->ev_pool.size() >= 1 << 16) { c = nullptr; return; }  // bounded: stop recording
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { c = nullptr; return; }
+        c->ev_pool.push_back(e);
+      }
+    }
+    hipEvent_t start = c->ev_pool[c->ev_used];
+    stop = c->ev_pool[c->ev_used + 1];
+    c->ev_used += 2;
+    c->ev_stage.push_back(stage);
+    hipEventRecord(start, c->stream);
+  }
+  ~StageTimer() {
+    if (c) hipEventRecord(stop, c->stream);
+  }
+};
+
 float2* ic_buf(cola_ctx* c, int i) { return c->meshbase + (size_t)i * mesh_complex_count(c->p.np); }
 
 // Tile sort of the current positions on an ng^3 grid.
 void tile_sort(cola_ctx* c, int ng) {
+  StageTimer t(c, COLA_STAGE_SORT);
   const float dscale = (float)((double)ng / (double)c->p.nmesh);
   const long nt = ng / 8;
   const long nb = 8 * nt * nt * nt;
@@ -145,6 +171,7 @@ void tile_sort(cola_ctx* c, int ng) {
 void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast) {
   const float dscale = (float)((double)ng / (double)c->p.nmesh);
   tile_sort(c, ng);
+  StageTimer t(c, COLA_STAGE_DEPOSIT);
   launch_deposit(c->disp, c->perm, c->offsets, c->p.np, ng, dscale, out, row_stride, contrast,
                  c->stream);
 }
@@ -154,8 +181,14 @@ void force_meshes(cola_ctx* c, double alpha) {
   const int nm = c->p.nmesh;
   const long rs = 2 * padded_cols(nm);
   deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1);
-  fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream);
-  fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream);
+  {
+    StageTimer t(c, COLA_STAGE_FFT_Z);
+    fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream);
+  }
+  {
+    StageTimer t(c, COLA_STAGE_FFT_Y);
+    fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream);
+  }
   XPassArgs a;
   a.in = c->mesh[0];
   a.out[0] = c->mesh[0];
@@ -164,9 +197,18 @@ void force_meshes(cola_ctx* c, double alpha) {
   a.mode = X_FWD_GREEN3;
   // g_d = IDFT[i n_d alpha nm / (2 pi |n|^2) DFT(delta)] / nm^3, in mesh units.
   a.scale = (float)(alpha * nm / (2.0 * kPi) / ((double)nm * nm * nm));
-  fft_x(a, nm, c->tw, c->stream);
-  fft_y(c->mesh[0], nm, 3, c->mesh_stride, 1, c->tw, c->stream);
-  fft_c2r_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream);
+  {
+    StageTimer t(c, COLA_STAGE_FFT_X);
+    fft_x(a, nm, c->tw, c->stream);
+  }
+  {
+    StageTimer t(c, COLA_STAGE_IFFT_Y);
+    fft_y(c->mesh[0], nm, 3, c->mesh_stride, 1, c->tw, c->stream);
+  }
+  {
+    StageTimer t(c, COLA_STAGE_IFFT_Z);
+    fft_c2r_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream);
+  }
 }
 
 bool same_a(double a, double b) { return std::fabs(a - b) <= 1e-12 * (std::fabs(a) > 1 ? std::fabs(a) : 1.0); }
@@ -359,6 +401,7 @@ int cola_create(const cola_params* p, void* ws, size_t bytes, void* stream, cola
 
 int cola_destroy(cola_ctx* c) {
   if (!c) return COLA_EINVAL;
+  for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   delete c;
   return COLA_OK;
 }
@@ -409,9 +452,12 @@ int cola_step(cola_ctx* c, double a0, double a1) {
   kd.e2 = (float)s[4];
   force_meshes(c, alpha);
   const long rs = 2 * padded_cols(c->p.nmesh);
-  launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
-                            reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
-                            c->psi2, c->p.np, c->p.nmesh, kd, nullptr, c->stream);
+  {
+    StageTimer t(c, COLA_STAGE_KICKDRIFT);
+    launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
+                              reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
+                              c->psi2, c->p.np, c->p.nmesh, kd, nullptr, c->stream);
+  }
   LAUNCH_CHECK(c, "cola_step");
   c->a_v = s[7];
   c->a_x = a1;
@@ -445,7 +491,7 @@ int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double*
   if (!c || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
   if (nbins < 1 || nbins > kMaxBins) return fail(c, COLA_EINVAL, "nbins out of range");
-  if (ng < 16 || ng > c->p.nmesh || ng % 8 != 0 || !smooth23(ng))
+  if (ng < 16 || ng > c->p.nmesh || ng % 8 != 0 || !fft_size_supported(ng))
     return fail(c, COLA_EUNSUPPORTED, "ngrid must be a {2,3}-smooth multiple of 8 in [16, nmesh]");
   for (int i = 0; i < nbins; ++i)
     if (!(edges[i + 1] > edges[i])) return fail(c, COLA_EINVAL, "edges must increase");
@@ -513,6 +559,27 @@ int cola_fft3d(cola_ctx* c, int32_t n, float* mesh, int32_t inverse) {
 int cola_step_scalars(const cola_params* p, double a_x, double a_v, double a1, double* out) {
   if (!p || !out || !(a_x > 0) || !(a_v > 0) || !(a1 > 0)) return COLA_EINVAL;
   step_scalars(p, a_x, a_v, a1, out);
+  return COLA_OK;
+}
+
+int cola_stage_times(cola_ctx* c, double* ms, int64_t* count) {
+  if (!c) return COLA_EINVAL;
+  if (!(c->p.flags & COLA_F_STAGE_TIMERS)) return fail(c, COLA_ESTATE, "stage timers not enabled");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double acc[COLA_NSTAGE] = {};
+  int64_t cnt[COLA_NSTAGE] = {};
+  for (size_t i = 0; i < c->ev_stage.size(); ++i) {
+    float t = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&t, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+    acc[c->ev_stage[i]] += t;
+    cnt[c->ev_stage[i]] += 1;
+  }
+  for (int s = 0; s < COLA_NSTAGE; ++s) {
+    if (ms) ms[s] = acc[s];
+    if (count) count[s] = cnt[s];
+  }
+  c->ev_stage.clear();
+  c->ev_used = 0;
   return COLA_OK;
 }
 

@@ -17,6 +17,7 @@ namespace cola {
 // (exactly 1 on the PM mesh, where the product is the identity).
 __device__ __forceinline__ void home_cell(const float* __restrict__ disp, long np3, uint32_t id,
                                           int np, int nm, float dscale, int c[3], float f[3]) {
+#pragma clang fp contract(off)
   const uint32_t unp = (uint32_t)np;
   const uint32_t li[3] = {id / (unp * unp), (id / unp) % unp, id % unp};
 #pragma unroll
@@ -36,6 +37,7 @@ __device__ __forceinline__ void home_cell(const float* __restrict__ disp, long n
 // CIC weight of offset k = 4 sx + 2 sy + sz: (w_sx(fx) * w_sy(fy)) * w_sz(fz),
 // w_0(f) = 1 - f, w_1(f) = f; two float32 roundings, no fused multiply-add.
 __device__ __forceinline__ float cic_weight(const float f[3], int k) {
+#pragma clang fp contract(off)
   const float wx = (k & 4) ? f[0] : __fsub_rn(1.0f, f[0]);
   const float wy = (k & 2) ? f[1] : __fsub_rn(1.0f, f[1]);
   const float wz = (k & 1) ? f[2] : __fsub_rn(1.0f, f[2]);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <string>
+#include <vector>
 
 #include "../../include/cola.h"
 
@@ -18,6 +19,7 @@ struct FftPlan {
   int radix[12] = {};
 };
 bool make_plan(int n, FftPlan* plan);
+bool fft_size_supported(int n);   // transform sizes with compiled kernels
 
 // Padded complex row length of an n^3 real mesh in the r2c layout: the
 // (n/2+1) half-spectrum rounded up to 16 complex values (128-byte rows).
@@ -142,6 +144,10 @@ struct cola_ctx {
   double* pk_out = nullptr;
   double* pk_edges = nullptr;
   uint32_t* flag = nullptr;
+  // stage timers (COLA_F_STAGE_TIMERS): pairs of events per recorded stage
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_stage;       // stage of each recorded pair
+  size_t ev_used = 0;              // events handed out (2 per pair)
   // time state
   double a_x = 0, a_v = 0;
   bool have_state = false;

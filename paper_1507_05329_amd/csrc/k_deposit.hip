@@ -15,6 +15,10 @@
 #include "cola_device.h"
 #include "cola_internal.h"
 
+// Every float operation in this file is a single IEEE rounding (the
+// deterministic order is part of the result): no fused multiply-add.
+#pragma clang fp contract(off)
+
 namespace cola {
 
 constexpr int kDT = 256;        // threads per workgroup

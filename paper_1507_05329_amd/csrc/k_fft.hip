@@ -20,26 +20,40 @@
 
 namespace cola {
 
-constexpr int kFT = 256;        // threads per workgroup
-constexpr int kMaxE = 32;       // complex elements per thread (lines * length <= kFT * kMaxE)
-constexpr int kLdsC = kFT * kMaxE;
+// Compile-time plan: a {2,3}-smooth length factored as 3s first, then 16s,
+// then one each of 8, 4, 2 as needed.
+constexpr int radix_at(int n, int s) {
+  int r[16] = {};
+  int ns = 0, m = n;
+  while (m % 3 == 0) { m /= 3; r[ns++] = 3; }
+  while (m % 16 == 0) { m /= 16; r[ns++] = 16; }
+  if (m % 8 == 0) { m /= 8; r[ns++] = 8; }
+  if (m % 4 == 0) { m /= 4; r[ns++] = 4; }
+  if (m % 2 == 0) { m /= 2; r[ns++] = 2; }
+  return (m == 1 && s < ns) ? r[s] : 0;
+}
+constexpr int nstage(int n) { int s = 0; while (radix_at(n, s)) ++s; return s; }
+constexpr int ns_before(int n, int s) { int p = 1; for (int i = 0; i < s; ++i) p *= radix_at(n, i); return p; }
 
-bool make_plan(int n, FftPlan* plan) {
-  if (n < 2) return false;
-  plan->n = n;
-  plan->nstage = 0;
-  int m = n;
-  int threes = 0;
-  while (m % 3 == 0) { m /= 3; ++threes; }
-  for (int i = 0; i < threes; ++i) plan->radix[plan->nstage++] = 3;
-  while (m % 16 == 0) { m /= 16; plan->radix[plan->nstage++] = 16; }
-  if (m % 8 == 0) { m /= 8; plan->radix[plan->nstage++] = 8; }
-  if (m % 4 == 0) { m /= 4; plan->radix[plan->nstage++] = 4; }
-  if (m % 2 == 0) { m /= 2; plan->radix[plan->nstage++] = 2; }
-  if (m != 1 || plan->nstage > 12) return false;
-  return true;
+// Launch shapes: at most ~66 KB of LDS per workgroup, 256 threads below
+// 8192 staged complex values, 512 at 8192.
+constexpr int kLdsLimit = 66 * 1024;
+constexpr int cols_w(int n) { int w = 16; while (w > 1 && w * (n + 1) * 8 > kLdsLimit) w /= 2; return w; }
+constexpr int rows_nl(int h) { int nl = 16; while (nl > 1 && nl * (h + 1) * 8 > kLdsLimit) nl /= 2; return nl; }
+constexpr int threads_for(int elems) { return elems >= 8192 ? 512 : 256; }
+// The fused Green's-function pass keeps the forward spectrum in registers
+// across its three inverse transforms: spread it over 512 threads.
+constexpr int cols_threads(int n, int mode) {
+  return (mode == X_FWD_GREEN3 && cols_w(n) * n >= 4096) ? 512 : threads_for(cols_w(n) * n);
 }
 
+bool make_plan(int n, FftPlan* plan) {
+  if (n < 2 || nstage(n) == 0) return false;
+  plan->n = n;
+  plan->nstage = nstage(n);
+  for (int s = 0; s < plan->nstage; ++s) plan->radix[s] = radix_at(n, s);
+  return true;
+}
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -116,93 +130,81 @@ template <> struct Dft<16> {
   }
 };
 
-template <int R>
-__device__ __forceinline__ void stockham_stage(float2* __restrict__ buf, int len, int nl, int ld,
-                                               int Ns, const float2* __restrict__ tw, int tw_stride,
-                                               float sgn) {
-  constexpr int kB = (kMaxE + R - 1) / R;
-  const int nbl = len / R;
-  const int nbf = nbl * nl;
-  const int step = (len / (Ns * R)) * tw_stride;
-  float2 v[kB][R];
+// Stages S.. of a length-N transform of NL lines (line l at buf[l * LD]), T
+// threads, twiddle table stride TWS, FWD = 1 forward / 0 inverse.
+template <int N, int NL, int LD, int T, int TWS, int FWD, int S>
+__device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float2* __restrict__ tw) {
+  if constexpr (S < nstage(N)) {
+    constexpr int R = radix_at(N, S), NS = ns_before(N, S);
+    constexpr int NBL = N / R, NBF = NBL * NL, KB = (NBF + T - 1) / T;
+    constexpr int STEP = (N / (NS * R)) * TWS;
+    constexpr float sgn = FWD ? -1.f : 1.f;
+    float2 v[KB][R];
 #pragma unroll
-  for (int b = 0; b < kB; ++b) {
-    const int t = threadIdx.x + b * kFT;
-    if (t < nbf) {
-      const int l = t / nbl, j = t - l * nbl;
-      const float2* src = buf + l * ld + j;
+    for (int b = 0; b < KB; ++b) {
+      const int t = threadIdx.x + b * T;
+      if (NBF % T == 0 || t < NBF) {
+        const int l = t / NBL, j = t - l * NBL;
+        const float2* src = buf + l * LD + j;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = src[r * nbl];
-      const int k = j % Ns;
-      if (k != 0) {
+        for (int r = 0; r < R; ++r) v[b][r] = src[r * NBL];
+        if constexpr (NS > 1) {
+          const int k = j % NS;
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * step];  // exp(-2 pi i m / n)
-          if (sgn > 0.f) w.y = -w.y;    // inverse: conjugate
-          v[b][r] = cmul(v[b][r], w);
+          for (int r = 1; r < R; ++r) {
+            float2 w = tw[r * k * STEP];  // exp(-2 pi i m / n)
+            if (!FWD) w.y = -w.y;         // inverse: conjugate
+            v[b][r] = cmul(v[b][r], w);
+          }
         }
+        Dft<R>::run(v[b], sgn);
       }
-      Dft<R>::run(v[b], sgn);
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int b = 0; b < kB; ++b) {
-    const int t = threadIdx.x + b * kFT;
-    if (t < nbf) {
-      const int l = t / nbl, j = t - l * nbl;
-      const int k = j % Ns;
-      float2* dst = buf + l * ld + (j - k) * R + k;
+    for (int b = 0; b < KB; ++b) {
+      const int t = threadIdx.x + b * T;
+      if (NBF % T == 0 || t < NBF) {
+        const int l = t / NBL, j = t - l * NBL;
+        const int k = j % NS;
+        float2* dst = buf + l * LD + (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[b][r];
+        for (int r = 0; r < R; ++r) dst[r * NS] = v[b][r];
+      }
     }
+    __syncthreads();
+    fft_stages<N, NL, LD, T, TWS, FWD, S + 1>(buf, tw);
   }
-  __syncthreads();
 }
 
-// Transforms nl lines of length plan.n stored at buf[l * ld + i].
-// sgn = -1 forward (exp(-i...)), +1 inverse (unnormalised).
-__device__ void lds_fft(float2* __restrict__ buf, int nl, int ld, const FftPlan& plan,
-                        const float2* __restrict__ tw, int tw_stride, float sgn) {
-  int Ns = 1;
-  for (int s = 0; s < plan.nstage; ++s) {
-    const int R = plan.radix[s];
-    switch (R) {
-      case 16: stockham_stage<16>(buf, plan.n, nl, ld, Ns, tw, tw_stride, sgn); break;
-      case 8: stockham_stage<8>(buf, plan.n, nl, ld, Ns, tw, tw_stride, sgn); break;
-      case 4: stockham_stage<4>(buf, plan.n, nl, ld, Ns, tw, tw_stride, sgn); break;
-      case 3: stockham_stage<3>(buf, plan.n, nl, ld, Ns, tw, tw_stride, sgn); break;
-      default: stockham_stage<2>(buf, plan.n, nl, ld, Ns, tw, tw_stride, sgn); break;
-    }
-    Ns *= R;
-  }
+template <int N, int NL, int LD, int T, int TWS, int FWD>
+__device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* __restrict__ tw) {
+  fft_stages<N, NL, LD, T, TWS, FWD, 0>(buf, tw);
 }
 
 // ---------------------------------------------------------------------------
-// z pass: rows of n reals (row stride `cols` complex).  nl rows per workgroup.
-__global__ __launch_bounds__(kFT) void k_r2c_z(float2* __restrict__ mesh, long nrows, int cols,
-                                               int nl, long mesh_stride, FftPlan plan,
-                                               const float2* __restrict__ tw) {
-  extern __shared__ float2 lds[];
-  const int h = plan.n;  // half length
-  const int n = 2 * h;
-  const int ld = h + 1;
+// z pass: rows of N reals (row stride `cols` complex).  NL rows per workgroup.
+template <int N>
+__global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z(
+    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw) {
+  constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
+  __shared__ float2 lds[NL * LD];
   float2* base = mesh + blockIdx.y * mesh_stride;
-  const long r0 = (long)blockIdx.x * nl;
-  const int nrow = (int)((nrows - r0) < nl ? (nrows - r0) : nl);
-  for (int i = threadIdx.x; i < nrow * h; i += kFT) {
-    const int l = i / h, j = i - l * h;
-    lds[l * ld + j] = base[(r0 + l) * cols + j];
+  const long r0 = (long)blockIdx.x * NL;
+  for (int i = threadIdx.x; i < NL * H; i += T) {
+    const int l = i / H, j = i - l * H;
+    if (r0 + l < nrows) lds[l * LD + j] = base[(r0 + l) * cols + j];
   }
   __syncthreads();
-  lds_fft(lds, nrow, ld, plan, tw, 2, -1.f);
+  lds_fft<H, NL, LD, T, 2, 1>(lds, tw);
   // split step: X_k = E_k + W_n^k O_k, E = (Z_k + conj Z_{h-k})/2, O = -i (Z_k - conj Z_{h-k})/2
-  for (int i = threadIdx.x; i < nrow * cols; i += kFT) {
+  for (int i = threadIdx.x; i < NL * cols; i += T) {
     const int l = i / cols, k = i - l * cols;
+    if (r0 + l >= nrows) continue;
     float2 x = make_float2(0.f, 0.f);
-    if (k <= h) {
-      const float2 a = lds[l * ld + (k == h ? 0 : k)];
-      float2 b = lds[l * ld + (k == 0 ? 0 : h - k)];
+    if (k <= H) {
+      const float2 a = lds[l * LD + (k == H ? 0 : k)];
+      float2 b = lds[l * LD + (k == 0 ? 0 : H - k)];
       b.y = -b.y;
       const float2 e = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
       const float2 o = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
@@ -212,28 +214,26 @@ __global__ __launch_bounds__(kFT) void k_r2c_z(float2* __restrict__ mesh, long n
   }
 }
 
-// Inverse z pass: half spectrum (h+1 values) -> n reals, unnormalised.
-__global__ __launch_bounds__(kFT) void k_c2r_z(float2* __restrict__ mesh, long nrows, int cols,
-                                               int nl, long mesh_stride, FftPlan plan,
-                                               const float2* __restrict__ tw) {
-  extern __shared__ float2 lds[];
-  const int h = plan.n;
-  const int ld = h + 1;
+// Inverse z pass: half spectrum (H+1 values) -> N reals, unnormalised.
+template <int N>
+__global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z(
+    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw) {
+  constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
+  __shared__ float2 lds[NL * LD];
   float2* base = mesh + blockIdx.y * mesh_stride;
-  const long r0 = (long)blockIdx.x * nl;
-  const int nrow = (int)((nrows - r0) < nl ? (nrows - r0) : nl);
-  for (int i = threadIdx.x; i < nrow * (h + 1); i += kFT) {
-    const int l = i / (h + 1), j = i - l * (h + 1);
-    lds[l * ld + j] = base[(r0 + l) * cols + j];
+  const long r0 = (long)blockIdx.x * NL;
+  for (int i = threadIdx.x; i < NL * (H + 1); i += T) {
+    const int l = i / (H + 1), j = i - l * (H + 1);
+    lds[l * LD + j] = r0 + l < nrows ? base[(r0 + l) * cols + j] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   // Z'_k = (X_k + conj X_{h-k}) + i (X_k - conj X_{h-k}) exp(+2 pi i k / n), k < h.
-  // Pairs (k, h-k) are handled by one thread, in place.
-  const int hp = h / 2 + 1;
-  for (int i = threadIdx.x; i < nrow * hp; i += kFT) {
-    const int l = i / hp, k = i - l * hp;
-    const int k2 = h - k;
-    const float2 xa = lds[l * ld + k], xb = lds[l * ld + k2];
+  // Each pair (k, h-k) belongs to one thread, updated in place.
+  constexpr int HP = H / 2 + 1;
+  for (int i = threadIdx.x; i < NL * HP; i += T) {
+    const int l = i / HP, k = i - l * HP;
+    const int k2 = H - k;
+    const float2 xa = lds[l * LD + k], xb = lds[l * LD + k2];
     float2 za, zb;
     {
       const float2 cb = make_float2(xb.x, -xb.y);
@@ -251,15 +251,14 @@ __global__ __launch_bounds__(kFT) void k_c2r_z(float2* __restrict__ mesh, long n
       const float2 o = cmul(csub(xb, ca), w);
       zb = cadd(e, make_float2(-o.y, o.x));
     }
-    // each pair belongs to exactly one thread: no other thread touches k or k2
-    lds[l * ld + k] = za;
-    if (k2 != k && k2 != h) lds[l * ld + k2] = zb;
+    lds[l * LD + k] = za;
+    if (k2 != k && k2 != H) lds[l * LD + k2] = zb;
   }
   __syncthreads();
-  lds_fft(lds, nrow, ld, plan, tw, 2, 1.f);
-  for (int i = threadIdx.x; i < nrow * h; i += kFT) {
-    const int l = i / h, j = i - l * h;
-    base[(r0 + l) * cols + j] = lds[l * ld + j];
+  lds_fft<H, NL, LD, T, 2, 0>(lds, tw);
+  for (int i = threadIdx.x; i < NL * H; i += T) {
+    const int l = i / H, j = i - l * H;
+    if (r0 + l < nrows) base[(r0 + l) * cols + j] = lds[l * LD + j];
   }
 }
 
@@ -270,8 +269,7 @@ struct ColGeom {
   long elem_stride;
   long plane_stride;
   int cols;       // padded columns (multiple of W)
-  int w;          // columns per workgroup
-  int nchunk;     // cols / w
+  int nchunk;     // cols / W
   int nplanes;
 };
 
@@ -305,114 +303,100 @@ __device__ __forceinline__ float2 multiplier(int kind, int green, int ca, int cb
   return make_float2(1.f, 0.f);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kFT) void k_cols(const float2* __restrict__ in, float2* out0,
-                                              float2* out1, float2* out2, long mesh_stride,
-                                              ColGeom g, FftPlan plan,
-                                              const float2* __restrict__ tw, int mult, int ca,
-                                              int cb, float scale, const float* __restrict__ amp,
-                                              int y_is_plane_freq) {
-  extern __shared__ float2 lds[];
-  const int n = plan.n;
-  const int ld = n + 1;
+template <int N, int MODE>
+__global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
+    const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
+    ColGeom g, const float2* __restrict__ tw, int mult, int ca, int cb, float scale,
+    const float* __restrict__ amp, int y_is_plane_freq) {
+  constexpr int W = cols_w(N), LD = N + 1, T = cols_threads(N, MODE);
+  constexpr int E = (W * N + T - 1) / T;
+  __shared__ float2 lds[W * LD];
   const uint32_t nblk = (uint32_t)g.nchunk * g.nplanes;
   const uint32_t bid = xcd_remap(blockIdx.x, nblk);
   const int p = bid / g.nchunk;
-  const int c0 = (bid - p * g.nchunk) * g.w;
+  const int c0 = (bid - p * g.nchunk) * W;
   const long mofs = (long)blockIdx.y * mesh_stride;
   const float2* src = in + mofs + p * g.plane_stride + c0;
   // load: consecutive threads take consecutive columns
-  for (int i = threadIdx.x; i < n * g.w; i += kFT) {
-    const int e = i / g.w, c = i - e * g.w;
-    lds[c * ld + e] = src[e * g.elem_stride + c];
+  for (int i = threadIdx.x; i < N * W; i += T) {
+    const int e = i / W, c = i - e * W;
+    lds[c * LD + e] = src[e * g.elem_stride + c];
   }
   __syncthreads();
-  const int pfreq = y_is_plane_freq ? signed_freq(p, n) : 0;
+  const int pfreq = y_is_plane_freq ? signed_freq(p, N) : 0;
 
-  if (MODE == X_FWD || MODE == X_INV) {
-    lds_fft(lds, g.w, ld, plan, tw, 1, MODE == X_FWD ? -1.f : 1.f);
-  } else if (MODE == X_FWD_AMP) {
-    lds_fft(lds, g.w, ld, plan, tw, 1, -1.f);
-    for (int i = threadIdx.x; i < n * g.w; i += kFT) {
-      const int c = i / n, e = i - c * n;
-      const float2 m = multiplier(0, 0, 0, 0, 0.f, signed_freq(e, n), pfreq, c0 + c, n, amp, 1);
-      lds[c * ld + e] = cmul(lds[c * ld + e], m);
+  if constexpr (MODE == X_FWD || MODE == X_INV) {
+    lds_fft<N, W, LD, T, 1, MODE == X_FWD ? 1 : 0>(lds, tw);
+  } else if constexpr (MODE == X_FWD_AMP) {
+    lds_fft<N, W, LD, T, 1, 1>(lds, tw);
+    for (int i = threadIdx.x; i < N * W; i += T) {
+      const int c = i / N, e = i - c * N;
+      const float2 m = multiplier(0, 0, 0, 0, 0.f, signed_freq(e, N), pfreq, c0 + c, N, amp, 1);
+      lds[c * LD + e] = cmul(lds[c * LD + e], m);
     }
     __syncthreads();
-  } else if (MODE == X_MULT_INV) {
-    for (int i = threadIdx.x; i < n * g.w; i += kFT) {
-      const int c = i / n, e = i - c * n;
-      const float2 m = multiplier(mult, 0, ca, cb, scale, signed_freq(e, n), pfreq, c0 + c, n, amp, 0);
-      lds[c * ld + e] = cmul(lds[c * ld + e], m);
+  } else if constexpr (MODE == X_MULT_INV) {
+    for (int i = threadIdx.x; i < N * W; i += T) {
+      const int c = i / N, e = i - c * N;
+      const float2 m = multiplier(mult, 0, ca, cb, scale, signed_freq(e, N), pfreq, c0 + c, N, amp, 0);
+      lds[c * LD + e] = cmul(lds[c * LD + e], m);
     }
     __syncthreads();
-    lds_fft(lds, g.w, ld, plan, tw, 1, 1.f);
+    lds_fft<N, W, LD, T, 1, 0>(lds, tw);
   }
 
-  if (MODE != X_FWD_GREEN3) {
+  if constexpr (MODE != X_FWD_GREEN3) {
     float2* dst = out0 + mofs + p * g.plane_stride + c0;
-    for (int i = threadIdx.x; i < n * g.w; i += kFT) {
-      const int e = i / g.w, c = i - e * g.w;
-      dst[e * g.elem_stride + c] = lds[c * ld + e];
+    for (int i = threadIdx.x; i < N * W; i += T) {
+      const int e = i / W, c = i - e * W;
+      dst[e * g.elem_stride + c] = lds[c * LD + e];
     }
-    return;
-  }
-
-  // PM: forward along x, then for each axis d: multiply by i k_d alpha / k^2
-  // (scaled to mesh units and 1/N^3), inverse along x, store to out_d.
-  lds_fft(lds, g.w, ld, plan, tw, 1, -1.f);
-  float2 spec[kMaxE];
+  } else {
+    // PM: forward along x, then for each axis d: multiply by i k_d alpha / k^2
+    // (scaled to mesh units and 1/N^3), inverse along x, store to out_d.
+    lds_fft<N, W, LD, T, 1, 1>(lds, tw);
+    float2 spec[E];
 #pragma unroll
-  for (int b = 0; b < kMaxE; ++b) {
-    const int i = threadIdx.x + b * kFT;
-    if (i < n * g.w) {
-      const int c = i / n, e = i - c * n;
-      spec[b] = lds[c * ld + e];
-    }
-  }
-  __syncthreads();
-  float2* outs[3] = {out0, out1, out2};
-  for (int d = 0; d < 3; ++d) {
-#pragma unroll
-    for (int b = 0; b < kMaxE; ++b) {
-      const int i = threadIdx.x + b * kFT;
-      if (i < n * g.w) {
-        const int c = i / n, e = i - c * n;
-        const float2 m = multiplier(M_GRAD, 1, d, 0, scale, signed_freq(e, n), pfreq, c0 + c, n, amp, 0);
-        lds[c * ld + e] = cmul(spec[b], m);
+    for (int b = 0; b < E; ++b) {
+      const int i = threadIdx.x + b * T;
+      if ((W * N) % T == 0 || i < N * W) {
+        const int c = i / N, e = i - c * N;
+        spec[b] = lds[c * LD + e];
       }
     }
     __syncthreads();
-    lds_fft(lds, g.w, ld, plan, tw, 1, 1.f);
-    float2* dst = outs[d] + p * g.plane_stride + c0;
-    for (int i = threadIdx.x; i < n * g.w; i += kFT) {
-      const int e = i / g.w, c = i - e * g.w;
-      dst[e * g.elem_stride + c] = lds[c * ld + e];
+    float2* outs[3] = {out0, out1, out2};
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int b = 0; b < E; ++b) {
+        const int i = threadIdx.x + b * T;
+        if ((W * N) % T == 0 || i < N * W) {
+          const int c = i / N, e = i - c * N;
+          const float2 m = multiplier(M_GRAD, 1, d, 0, scale, signed_freq(e, N), pfreq, c0 + c, N, amp, 0);
+          lds[c * LD + e] = cmul(spec[b], m);
+        }
+      }
+      __syncthreads();
+      lds_fft<N, W, LD, T, 1, 0>(lds, tw);
+      float2* dst = outs[d] + p * g.plane_stride + c0;
+      for (int i = threadIdx.x; i < N * W; i += T) {
+        const int e = i / W, c = i - e * W;
+        dst[e * g.elem_stride + c] = lds[c * LD + e];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 namespace {
 
-int cols_per_wg(int n) {
-  int w = kLdsC / (n + 1);
-  if (w > 16) w = 16;
-  int p = 1;
-  while (p * 2 <= w) p *= 2;
-  return p;
-}
-
-size_t lds_bytes_cols(int n, int w) { return (size_t)w * (n + 1) * sizeof(float2); }
-
-ColGeom geom(int n, int axis) {
+ColGeom geom(int n, int w, int axis) {
   ColGeom g;
   const long cols = padded_cols(n);
   g.cols = (int)cols;
-  g.w = cols_per_wg(n);
-  if (g.w > g.cols) g.w = g.cols;
-  g.nchunk = (int)(cols / g.w);
+  g.nchunk = (int)(cols / w);
   g.nplanes = n;
   if (axis == 1) {  // y: planes are x
     g.elem_stride = cols;
@@ -424,77 +408,104 @@ ColGeom geom(int n, int axis) {
   return g;
 }
 
+template <int N>
+void r2c_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s) {
+  constexpr int NL = rows_nl(N / 2), T = threads_for(NL * (N / 2));
+  const long nrows = (long)N * N;
+  dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch);
+  hipLaunchKernelGGL(k_r2c_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw);
+}
+
+template <int N>
+void c2r_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s) {
+  constexpr int NL = rows_nl(N / 2), T = threads_for(NL * (N / 2));
+  const long nrows = (long)N * N;
+  dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch);
+  hipLaunchKernelGGL(k_c2r_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw);
+}
+
+template <int N>
+void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbatch, long mesh_stride,
+            const float2* tw, int mult, int ca, int cb, float scale, const float* amp, hipStream_t s) {
+  constexpr int W = cols_w(N);
+  const ColGeom g = geom(N, W, axis);
+  dim3 grid((unsigned)(g.nchunk * g.nplanes), (unsigned)nbatch);
+  const int yf = axis == 0 ? 1 : 0;
+  switch (mode) {
+    case X_FWD:
+      hipLaunchKernelGGL((k_cols<N, X_FWD>), grid, dim3(cols_threads(N, X_FWD)), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf);
+      break;
+    case X_INV:
+      hipLaunchKernelGGL((k_cols<N, X_INV>), grid, dim3(cols_threads(N, X_INV)), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf);
+      break;
+    case X_FWD_AMP:
+      hipLaunchKernelGGL((k_cols<N, X_FWD_AMP>), grid, dim3(cols_threads(N, X_FWD_AMP)), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, amp, yf);
+      break;
+    case X_MULT_INV:
+      hipLaunchKernelGGL((k_cols<N, X_MULT_INV>), grid, dim3(cols_threads(N, X_MULT_INV)), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, mult, ca, cb, scale, nullptr, yf);
+      break;
+    case X_FWD_GREEN3:
+      hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN3>), grid, dim3(cols_threads(N, X_FWD_GREEN3)), 0, s, in, out[0], out[1], out[2],
+                         mesh_stride, g, tw, M_GRAD, 0, 0, scale, nullptr, yf);
+      break;
+  }
+}
+
+#define COLA_FFT_SIZES(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) \
+  X(768) X(1024) X(1536) X(2048)
+
 }  // namespace
 
+bool fft_size_supported(int n) {
+  switch (n) {
+#define X(NN) case NN: return true;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
 void fft_r2c_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleSet& tw, hipStream_t s) {
-  FftPlan plan;
-  make_plan(n / 2, &plan);
-  const int h = n / 2;
-  int nl = kLdsC / (h + 1);
-  if (nl > 16) nl = 16;
-  const long nrows = (long)n * n;
-  const int cols = (int)padded_cols(n);
-  dim3 grid((unsigned)((nrows + nl - 1) / nl), (unsigned)nbatch);
-  hipLaunchKernelGGL(k_r2c_z, grid, dim3(kFT), (size_t)nl * (h + 1) * sizeof(float2), s, mesh,
-                     nrows, cols, nl, mesh_stride, plan, tw.get(n));
+  switch (n) {
+#define X(NN) case NN: r2c_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s); break;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: break;
+  }
 }
 
 void fft_c2r_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleSet& tw, hipStream_t s) {
-  FftPlan plan;
-  make_plan(n / 2, &plan);
-  const int h = n / 2;
-  int nl = kLdsC / (h + 1);
-  if (nl > 16) nl = 16;
-  const long nrows = (long)n * n;
-  const int cols = (int)padded_cols(n);
-  dim3 grid((unsigned)((nrows + nl - 1) / nl), (unsigned)nbatch);
-  hipLaunchKernelGGL(k_c2r_z, grid, dim3(kFT), (size_t)nl * (h + 1) * sizeof(float2), s, mesh,
-                     nrows, cols, nl, mesh_stride, plan, tw.get(n));
+  switch (n) {
+#define X(NN) case NN: c2r_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s); break;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: break;
+  }
 }
 
 void fft_y(float2* mesh, int n, int nbatch, long mesh_stride, int inverse, const TwiddleSet& tw,
            hipStream_t s) {
-  FftPlan plan;
-  make_plan(n, &plan);
-  const ColGeom g = geom(n, 1);
-  dim3 grid((unsigned)(g.nchunk * g.nplanes), (unsigned)nbatch);
-  const size_t lds = lds_bytes_cols(n, g.w);
-  if (inverse)
-    hipLaunchKernelGGL(k_cols<X_INV>, grid, dim3(kFT), lds, s, mesh, mesh, nullptr, nullptr,
-                       mesh_stride, g, plan, tw.get(n), 0, 0, 0, 1.f, nullptr, 0);
-  else
-    hipLaunchKernelGGL(k_cols<X_FWD>, grid, dim3(kFT), lds, s, mesh, mesh, nullptr, nullptr,
-                       mesh_stride, g, plan, tw.get(n), 0, 0, 0, 1.f, nullptr, 0);
+  float2* outs[3] = {mesh, nullptr, nullptr};
+  const int mode = inverse ? X_INV : X_FWD;
+  switch (n) {
+#define X(NN) case NN: cols_n<NN>(mode, 1, mesh, outs, nbatch, mesh_stride, tw.get(NN), 0, 0, 0, 1.f, nullptr, s); break;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: break;
+  }
 }
 
 void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s) {
-  FftPlan plan;
-  make_plan(n, &plan);
-  const ColGeom g = geom(n, 0);
-  dim3 grid((unsigned)(g.nchunk * g.nplanes), 1);
-  const size_t lds = lds_bytes_cols(n, g.w);
-  const float2* twp = tw.get(n);
-  switch (a.mode) {
-    case X_FWD:
-      hipLaunchKernelGGL(k_cols<X_FWD>, grid, dim3(kFT), lds, s, a.in, a.out[0], nullptr, nullptr, 0L,
-                         g, plan, twp, 0, 0, 0, 1.f, nullptr, 1);
-      break;
-    case X_INV:
-      hipLaunchKernelGGL(k_cols<X_INV>, grid, dim3(kFT), lds, s, a.in, a.out[0], nullptr, nullptr, 0L,
-                         g, plan, twp, 0, 0, 0, 1.f, nullptr, 1);
-      break;
-    case X_FWD_AMP:
-      hipLaunchKernelGGL(k_cols<X_FWD_AMP>, grid, dim3(kFT), lds, s, a.in, a.out[0], nullptr, nullptr,
-                         0L, g, plan, twp, 0, 0, 0, 1.f, a.amp, 1);
-      break;
-    case X_MULT_INV:
-      hipLaunchKernelGGL(k_cols<X_MULT_INV>, grid, dim3(kFT), lds, s, a.in, a.out[0], nullptr, nullptr,
-                         0L, g, plan, twp, a.mult, a.comp_a, a.comp_b, a.scale, nullptr, 1);
-      break;
-    case X_FWD_GREEN3:
-      hipLaunchKernelGGL(k_cols<X_FWD_GREEN3>, grid, dim3(kFT), lds, s, a.in, a.out[0], a.out[1],
-                         a.out[2], 0L, g, plan, twp, M_GRAD, 0, 0, a.scale, nullptr, 1);
-      break;
+  float2* outs[3] = {a.out[0], a.out[1], a.out[2]};
+  switch (n) {
+#define X(NN) case NN: cols_n<NN>(a.mode, 0, a.in, outs, 1, 0, tw.get(NN), a.mult, a.comp_a, a.comp_b, a.scale, a.amp, s); break;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: break;
   }
 }
 

@@ -125,6 +125,14 @@ class ColaSim:
     def fft3d(self, mesh: torch.Tensor, n: int, inverse=False):
         self._chk(self.lib.cola_fft3d(self.ctx, n, _ptr(mesh), int(inverse)), "fft3d")
 
+    def stage_times(self):
+        """Per-stage (ms total, launches) since the last call (needs COLA_F_STAGE_TIMERS)."""
+        ms = np.zeros(len(_lib.STAGES))
+        cnt = np.zeros(len(_lib.STAGES), np.int64)
+        self._chk(self.lib.cola_stage_times(self.ctx, dptr(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64))),
+                  "stage_times")
+        return {n: (float(m), int(k)) for n, m, k in zip(_lib.STAGES, ms, cnt)}
+
     def synchronize(self):
         self._chk(self.lib.cola_synchronize(self.ctx), "synchronize")
 

@@ -43,7 +43,9 @@ def to_dev(a):
 
 
 def rel_l2(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+    a = np.asarray(a)
+    a = a.astype(np.complex128) if np.iscomplexobj(a) else a.astype(np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def lattice_mesh_units():
