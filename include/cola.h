@@ -41,7 +41,7 @@ extern "C" {
 #define COLA_EINVAL       -1   /* bad argument (null pointer, size, range)         */
 #define COLA_ENOMEM       -2   /* workspace smaller than cola_workspace_query      */
 #define COLA_ESTATE       -3   /* call not valid in the current state (a0 != a_x)  */
-#define COLA_EUNSUPPORTED -4   /* mesh not 8 * {2,3}-smooth, ratio not supported   */
+#define COLA_EUNSUPPORTED -4   /* size without compiled FFT kernels                */
 #define COLA_EHIP         -5   /* HIP runtime error (message in cola_last_error)   */
 #define COLA_ENONFINITE   -6   /* non-finite value found (COLA_F_CHECK_FINITE)     */
 
@@ -62,9 +62,9 @@ extern "C" {
 typedef struct cola_ctx cola_ctx;
 
 /* Run parameters.  Cosmology is flat LCDM, Omega_Lambda = 1 - omega_m
- * (Sec. 1).  nmesh: PM mesh per side, a multiple of 8 whose only prime
- * factors are 2 and 3, and nmesh >= np.  np: particles per side, even,
- * {2,3}-smooth. */
+ * (Sec. 1).  np and nmesh must be one of the compiled FFT sizes
+ * {16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048}
+ * (COLA_EUNSUPPORTED otherwise), with nmesh >= 32 and nmesh >= np. */
 typedef struct cola_params {
   int32_t np;              /* particles per side                                   */
   int32_t nmesh;           /* PM mesh per side                                     */
@@ -125,8 +125,8 @@ int cola_step(cola_ctx* ctx, double a0, double a1);
  * cells in a fixed order. */
 int cola_density(cola_ctx* ctx, float* dev_out);
 
-/* Matter power spectrum (Sec. 3.3): CIC onto ngrid^3 (8 <= ngrid <= nmesh,
- * multiple of 8, {2,3}-smooth), FFT, divide by the CIC window, P = |delta_k|^2
+/* Matter power spectrum (Sec. 3.3): CIC onto ngrid^3 (a supported size,
+ * 32 <= ngrid <= nmesh), FFT, divide by the CIC window, P = |delta_k|^2
  * / V over the half space {kz>0} U {kz=0,ky>0} U {kz=0,ky=0,kx>0} with
  * |k| <= pi ngrid / box, binned by k_edges[nbins+1] (h/Mpc, increasing; bin b
  * holds edges[b] <= |k| < edges[b+1]).  Host outputs: mean |k|, mean P and

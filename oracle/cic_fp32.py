@@ -21,8 +21,9 @@ For the 8 offsets s = (sx, sy, sz), taken in the order k = 4 sx + 2 sy + sz:
     w_s = (w_sx(fx) * w_sy(fy)) * w_sz(fz)          (float32, no fused multiply-add)
 Per home cell c and offset s, the partial sum P_s(c) adds w_s of the cell's
 particles in ascending particle id, starting from 0.0f.
-Node n then takes rho(n) = 0.0f + P_s0(n - s0) + P_s1(n - s1) + ... in the
-order k = 0..7 (a cell without particles contributes +0.0f).
+Node n then adds its 8 source cells in ascending cell order, i.e.
+rho(n) = 0.0f + P_s7(n - s7) + P_s6(n - s6) + ... + P_s0(n - s0), offsets
+k = 7 .. 0 (a cell without particles contributes +0.0f).
 The density contrast is delta = rho * c_inv - 1.0f, c_inv = float32(Nm^3 / Np)
 (two float32 roundings, no fused multiply-add).
 """
@@ -90,7 +91,7 @@ def density(disp, np_side: int, nm: int, contrast=True) -> np.ndarray:
     """rho (or delta) on the nm^3 mesh, float32, in the documented order."""
     P = cell_partials(disp, np_side, nm)
     rho = np.zeros((nm, nm, nm), dtype=F32)
-    for k in range(8):
+    for k in range(7, -1, -1):
         s = ((k >> 2) & 1, (k >> 1) & 1, k & 1)
         rho = rho + np.roll(P[k], shift=s, axis=(0, 1, 2))
     if not contrast:
@@ -109,7 +110,7 @@ def density_at_nodes(disp, np_side: int, nm: int, nodes: np.ndarray, contrast=Tr
     out = np.empty(len(nodes), dtype=F32)
     for j, n in enumerate(np.asarray(nodes)):
         rho = F32(0.0)
-        for k in range(8):
+        for k in range(7, -1, -1):
             s = np.array([(k >> 2) & 1, (k >> 1) & 1, k & 1])
             c = np.mod(n - s, nm)
             cf = (c[0] * nm + c[1]) * nm + c[2]

@@ -63,7 +63,7 @@ struct Layout {
 
 int validate(const cola_params* p) {
   if (!p) return COLA_EINVAL;
-  if (p->np < 2 || p->nmesh < 16 || !(p->box > 0) || !(p->omega_m > 0) || p->omega_m > 1.0 ||
+  if (p->np < 2 || p->nmesh < 32 || !(p->box > 0) || !(p->omega_m > 0) || p->omega_m > 1.0 ||
       !(p->a_init > 0) || p->n_lpt == 0.0 || !std::isfinite(p->n_lpt))
     return COLA_EINVAL;
   if (!fft_size_supported(p->np)) return COLA_EUNSUPPORTED;
@@ -75,7 +75,7 @@ int validate(const cola_params* p) {
 Layout layout(const cola_params* p) {
   Layout L{};
   const long np3 = (long)p->np * p->np * p->np;
-  const long nt = p->nmesh / 8;
+  const long nt = p->nmesh / 16;           // 16^3-cell tiles of the deposit
   L.nbucket = 8 * nt * nt * nt;
   L.mesh_stride = mesh_complex_count(p->nmesh);
   const long pm = 3 * L.mesh_stride, ic = 4 * mesh_complex_count(p->np);
@@ -160,7 +160,7 @@ float2* ic_buf(cola_ctx* c, int i) { return c->meshbase + (size_t)i * mesh_compl
 void tile_sort(cola_ctx* c, int ng) {
   StageTimer t(c, COLA_STAGE_SORT);
   const float dscale = (float)((double)ng / (double)c->p.nmesh);
-  const long nt = ng / 8;
+  const long nt = ng / 16;
   const long nb = 8 * nt * nt * nt;
   launch_fill_u32(c->counts, nb + 1, 0u, c->stream);
   launch_bin_count(c->disp, c->p.np, ng, dscale, c->counts, c->pkey, c->prank, c->stream);
@@ -491,8 +491,8 @@ int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double*
   if (!c || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
   if (nbins < 1 || nbins > kMaxBins) return fail(c, COLA_EINVAL, "nbins out of range");
-  if (ng < 16 || ng > c->p.nmesh || ng % 8 != 0 || !fft_size_supported(ng))
-    return fail(c, COLA_EUNSUPPORTED, "ngrid must be a {2,3}-smooth multiple of 8 in [16, nmesh]");
+  if (ng < 32 || ng > c->p.nmesh || !fft_size_supported(ng))
+    return fail(c, COLA_EUNSUPPORTED, "ngrid must be a supported size in [32, nmesh]");
   for (int i = 0; i < nbins; ++i)
     if (!(edges[i + 1] > edges[i])) return fail(c, COLA_EINVAL, "edges must increase");
   int r = ensure_twiddles(c, ng);

@@ -44,12 +44,12 @@ __device__ __forceinline__ float cic_weight(const float f[3], int k) {
   return __fmul_rn(__fmul_rn(wx, wy), wz);
 }
 
-// Tile (8^3 cells) and class bits of a home cell: class bit 4/2/1 set when
+// Tile (16^3 cells) and class bits of a home cell: class bit 4/2/1 set when
 // the cell is on the upper x/y/z face of its tile (it then also feeds nodes
-// of the next tile along that axis).
+// of the next tile along that axis).  nt = tiles per side.
 __device__ __forceinline__ uint32_t bucket_of(const int c[3], int nt) {
-  const uint32_t tile = ((uint32_t)(c[0] >> 3) * nt + (uint32_t)(c[1] >> 3)) * nt + (uint32_t)(c[2] >> 3);
-  const uint32_t cls = (((c[0] & 7) == 7) << 2) | (((c[1] & 7) == 7) << 1) | ((c[2] & 7) == 7);
+  const uint32_t tile = ((uint32_t)(c[0] >> 4) * nt + (uint32_t)(c[1] >> 4)) * nt + (uint32_t)(c[2] >> 4);
+  const uint32_t cls = (((c[0] & 15) == 15) << 2) | (((c[1] & 15) == 15) << 1) | ((c[2] & 15) == 15);
   return tile * 8u + cls;
 }
 

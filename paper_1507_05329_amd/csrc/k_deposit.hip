@@ -2,16 +2,19 @@
 //
 // CIC (Koda et al. 2015, Sec. 3.3; Hockney & Eastwood): a particle with home
 // cell c and fraction f gives weight prod_e w_{s_e}(f_e) to node c + s.
-// One workgroup owns an 8^3 tile of nodes.  The cells that feed those nodes
-// are the tile's own 8^3 cells plus the one-cell layer below it on each axis
-// (a 9^3 region); their particles come from the tile's buckets and from the
+// One workgroup owns a 16^3 tile of nodes.  The cells that feed those nodes
+// are the tile's 16^3 cells plus the one-cell layer below it on each axis
+// (a 17^3 region); their particles come from the tile's buckets and from the
 // face/edge/corner buckets of the 7 lower neighbour tiles.  Particles are
-// keyed (region cell, particle id) and sorted in LDS, so every cell's
-// weights are added in ascending particle id; a node then adds its 8 source
-// cells in the fixed offset order k = 4 sx + 2 sy + sz.  The result does not
-// depend on launch order, atomics or the bucket order inside the sort.
-// Tiles whose region holds more particles than fit in LDS are processed in
-// x-slabs of the region, then single cells, then by an ordered selection.
+// keyed (region cell, particle id, LDS slot) and sorted in LDS, so each
+// cell's 8 partial sums add its particles' weights in ascending id.  Nodes
+// then receive the partial sums of their 8 source cells in ascending
+// source-cell order: runs of equal cell are processed in sorted batches, and
+// within a batch in 8 phases (offset k = 7 .. 0), each phase conflict-free
+// (distinct cells -> distinct nodes).  The result is independent of launch
+// order, atomics and the order inside the buckets.  Regions holding more
+// particles than fit in LDS are processed by x-slab, then by single cell,
+// then by an ordered selection, keeping the same order.
 #include "cola_device.h"
 #include "cola_internal.h"
 
@@ -21,56 +24,69 @@
 
 namespace cola {
 
-constexpr int kDT = 256;        // threads per workgroup
-constexpr int kCap = 2048;      // keys held in LDS at once (power of two)
-constexpr int kReg = 9;         // region side (8 + 1 lower layer)
+constexpr int kDT = 512;                  // threads per workgroup
+constexpr int kTile = 16;                 // nodes per tile side
+constexpr int kReg = kTile + 1;           // region side (tile + lower layer)
 constexpr int kNReg = kReg * kReg * kReg;
+constexpr int kCap = 2048;                // particles held in LDS at once (power of two)
+constexpr int kSlotBits = 11;             // log2(kCap)
+constexpr int kIdBits = 30;
+constexpr int kMaxSeg = 32;
+static_assert((1 << kSlotBits) == kCap, "slot field");
+static_assert(kNReg < (1 << (64 - kIdBits - kSlotBits)), "cell field");
 
 struct DepShared {
-  uint64_t keys[kCap];
-  float P[8 * kNReg];           // per-cell partial sums, offset-major
-  uint32_t seg_start[27];
-  uint32_t seg_pre[28];
+  uint64_t keys[kCap];                    // cell << 41 | id << 11 | slot
+  float fx[kCap], fy[kCap], fz[kCap];
+  float rho[kTile * kTile * kTile];
+  uint16_t run[kCap + 1];                 // start of each run of equal cell
+  uint32_t scan[kDT];
+  uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
   int nseg;
+  int nrun;
   uint32_t count;
   uint32_t red[kDT / 64];
   float acc8[8];
 };
 
-__device__ __forceinline__ int region_coord(int c, int t8, int nm) {
-  int r = c - t8 + 1;
+__device__ __forceinline__ int region_coord(int c, int t0, int nm) {
+  int r = c - t0 + 1;
   if (r < 0) r += nm;
   if (r >= nm) r -= nm;
   return r;
 }
 
-// Entry j (0 <= j < total) of the workgroup's particle list -> particle id.
-__device__ __forceinline__ uint32_t list_id(const DepShared& sh, const uint32_t* __restrict__ perm,
-                                            uint32_t j) {
-  int s = 0;
-  while (s + 1 < sh.nseg && sh.seg_pre[s + 1] <= j) ++s;
-  return perm[sh.seg_start[s] + (j - sh.seg_pre[s])];
-}
+__device__ __forceinline__ uint32_t key_cell(uint64_t k) { return (uint32_t)(k >> (kIdBits + kSlotBits)); }
+__device__ __forceinline__ uint32_t key_slot(uint64_t k) { return (uint32_t)k & (kCap - 1); }
 
 // filter: 0 = all, 1 = region x index == fv, 2 = region cell == fv.
+// Returns the number of matching particles (keys stored only when <= kCap).
 __device__ uint32_t gather_keys(DepShared& sh, const float* __restrict__ disp,
                                 const uint32_t* __restrict__ perm, long np3, int np, int nm,
-                                float dscale, const int t8[3], uint32_t total, int filter, int fv) {
+                                float dscale, const int t0[3], int filter, int fv) {
   if (threadIdx.x == 0) sh.count = 0;
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < total; j += kDT) {
-    const uint32_t id = list_id(sh, perm, j);
-    int c[3];
-    float f[3];
-    home_cell(disp, np3, id, np, nm, dscale, c, f);
-    const int rx = region_coord(c[0], t8[0], nm), ry = region_coord(c[1], t8[1], nm),
-              rz = region_coord(c[2], t8[2], nm);
-    const int lc = (rx * kReg + ry) * kReg + rz;
-    const bool inside = rx < kReg && ry < kReg && rz < kReg;
-    const bool pass = inside && (filter == 0 || (filter == 1 && rx == fv) || (filter == 2 && lc == fv));
-    if (pass) {
-      const uint32_t slot = atomicAdd(&sh.count, 1u);
-      if (slot < (uint32_t)kCap) sh.keys[slot] = ((uint64_t)lc << 32) | id;
+  for (int s = 0; s < sh.nseg; ++s) {
+    const uint32_t start = sh.seg_start[s], len = sh.seg_len[s];
+    for (uint32_t j = threadIdx.x; j < len; j += kDT) {
+      const uint32_t id = perm[start + j];
+      int c[3];
+      float f[3];
+      home_cell(disp, np3, id, np, nm, dscale, c, f);
+      const int rx = region_coord(c[0], t0[0], nm), ry = region_coord(c[1], t0[1], nm),
+                rz = region_coord(c[2], t0[2], nm);
+      const bool inside = rx < kReg && ry < kReg && rz < kReg;
+      const int lc = (rx * kReg + ry) * kReg + rz;
+      const bool pass = inside && (filter == 0 || (filter == 1 && rx == fv) || (filter == 2 && lc == fv));
+      if (pass) {
+        const uint32_t slot = atomicAdd(&sh.count, 1u);
+        if (slot < (uint32_t)kCap) {
+          sh.keys[slot] = ((uint64_t)lc << (kIdBits + kSlotBits)) | ((uint64_t)id << kSlotBits) | slot;
+          sh.fx[slot] = f[0];
+          sh.fy[slot] = f[1];
+          sh.fz[slot] = f[2];
+        }
+      }
     }
   }
   __syncthreads();
@@ -100,50 +116,101 @@ __device__ void sort_keys(DepShared& sh, uint32_t n) {
   }
 }
 
-// Per-cell partial sums of the n sorted keys (one thread per run of equal cell).
-__device__ void cell_partials(DepShared& sh, const float* __restrict__ disp, long np3, int np,
-                              int nm, float dscale, uint32_t n) {
-  for (uint32_t j = threadIdx.x; j < n; j += kDT) {
-    const uint32_t lc = (uint32_t)(sh.keys[j] >> 32);
-    if (j > 0 && (uint32_t)(sh.keys[j - 1] >> 32) == lc) continue;
-    float acc[8];
+// Ordered list of run starts (runs of equal cell in the sorted keys).
+__device__ void find_runs(DepShared& sh, uint32_t n) {
+  constexpr int kPer = kCap / kDT;
+  uint32_t flags = 0, cnt = 0;
+  const uint32_t base = threadIdx.x * kPer;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
-    for (uint32_t m = j; m < n && (uint32_t)(sh.keys[m] >> 32) == lc; ++m) {
-      int c[3];
-      float f[3];
-      home_cell(disp, np3, (uint32_t)sh.keys[m], np, nm, dscale, c, f);
+  for (int q = 0; q < kPer; ++q) {
+    const uint32_t j = base + q;
+    const bool st = j < n && (j == 0 || key_cell(sh.keys[j]) != key_cell(sh.keys[j - 1]));
+    flags |= (uint32_t)st << q;
+    cnt += st;
+  }
+  sh.scan[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 1; off < kDT; off <<= 1) {
+    const uint32_t a = threadIdx.x >= (unsigned)off ? sh.scan[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh.scan[threadIdx.x] += a;
+    __syncthreads();
+  }
+  uint32_t pos = sh.scan[threadIdx.x] - cnt;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) acc[k] = __fadd_rn(acc[k], cic_weight(f, k));
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh.P[k * kNReg + lc] = acc[k];
+  for (int q = 0; q < kPer; ++q)
+    if (flags >> q & 1u) sh.run[pos++] = (uint16_t)(base + q);
+  if (threadIdx.x == kDT - 1) {
+    sh.nrun = (int)sh.scan[kDT - 1];
+    sh.run[sh.scan[kDT - 1]] = (uint16_t)n;
   }
   __syncthreads();
 }
 
-// A cell with more than kCap particles: add them in ascending id by repeated
-// workgroup-wide minimum search (slow; only for extreme clustering).
-__device__ void cell_partials_select(DepShared& sh, const float* __restrict__ disp,
-                                     const uint32_t* __restrict__ perm, long np3, int np, int nm,
-                                     float dscale, const int t8[3], uint32_t total, int lc_target) {
+// Adds the 8 partial sums acc[k] of region cell lc to its tile nodes, in the
+// phase order k = 7 .. 0 (one barrier per phase; all threads participate).
+__device__ __forceinline__ void add_partials(DepShared& sh, bool active, int lc, const float acc[8]) {
+  const int rx = lc / (kReg * kReg), ry = (lc / kReg) % kReg, rz = lc % kReg;
+#pragma unroll
+  for (int k = 7; k >= 0; --k) {
+    if (active) {
+      const int nx = rx + ((k >> 2) & 1) - 1, ny = ry + ((k >> 1) & 1) - 1, nz = rz + (k & 1) - 1;
+      if (nx >= 0 && nx < kTile && ny >= 0 && ny < kTile && nz >= 0 && nz < kTile) {
+        float& r = sh.rho[(nx * kTile + ny) * kTile + nz];
+        r = __fadd_rn(r, acc[k]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Partial sums of the n sorted keys, then node accumulation in sorted batches.
+__device__ void accumulate_sorted(DepShared& sh, uint32_t n) {
+  find_runs(sh, n);
+  const int nrun = sh.nrun;
+  for (int b0 = 0; b0 < nrun; b0 += kDT) {
+    const int r = b0 + (int)threadIdx.x;
+    const bool active = r < nrun;
+    float acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+    int lc = 0;
+    if (active) {
+      const uint32_t j0 = sh.run[r], j1 = sh.run[r + 1];
+      lc = (int)key_cell(sh.keys[j0]);
+      for (uint32_t j = j0; j < j1; ++j) {
+        const uint32_t sl = key_slot(sh.keys[j]);
+        const float f[3] = {sh.fx[sl], sh.fy[sl], sh.fz[sl]};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = __fadd_rn(acc[k], cic_weight(f, k));
+      }
+    }
+    add_partials(sh, active, lc, acc);
+  }
+}
+
+// A cell with more than kCap particles: its weights added in ascending id by
+// repeated workgroup-wide minimum search (slow; extreme clustering only).
+__device__ void accumulate_select(DepShared& sh, const float* __restrict__ disp,
+                                  const uint32_t* __restrict__ perm, long np3, int np, int nm,
+                                  float dscale, const int t0[3], int lc_target) {
   if (threadIdx.x < 8) sh.acc8[threadIdx.x] = 0.0f;
   uint32_t last = 0;
   bool first = true;
   for (;;) {
     uint32_t best = 0xffffffffu;
-    for (uint32_t j = threadIdx.x; j < total; j += kDT) {
-      const uint32_t id = list_id(sh, perm, j);
-      if (!first && id <= last) continue;
-      if (id >= best) continue;
-      int c[3];
-      float f[3];
-      home_cell(disp, np3, id, np, nm, dscale, c, f);
-      const int lc = (region_coord(c[0], t8[0], nm) * kReg + region_coord(c[1], t8[1], nm)) * kReg +
-                     region_coord(c[2], t8[2], nm);
-      if (lc == lc_target) best = id;
+    for (int s = 0; s < sh.nseg; ++s) {
+      for (uint32_t j = threadIdx.x; j < sh.seg_len[s]; j += kDT) {
+        const uint32_t id = perm[sh.seg_start[s] + j];
+        if ((!first && id <= last) || id >= best) continue;
+        int c[3];
+        float f[3];
+        home_cell(disp, np3, id, np, nm, dscale, c, f);
+        const int lc = (region_coord(c[0], t0[0], nm) * kReg + region_coord(c[1], t0[1], nm)) * kReg +
+                       region_coord(c[2], t0[2], nm);
+        if (lc == lc_target) best = id;
+      }
     }
-    // workgroup min
     for (int o = 32; o > 0; o >>= 1) {
       const uint32_t other = __shfl_xor(best, o, 64);
       best = other < best ? other : best;
@@ -164,8 +231,10 @@ __device__ void cell_partials_select(DepShared& sh, const float* __restrict__ di
     first = false;
     __syncthreads();
   }
-  if (threadIdx.x < 8) sh.P[threadIdx.x * kNReg + lc_target] = sh.acc8[threadIdx.x];
-  __syncthreads();
+  float acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = sh.acc8[k];
+  add_partials(sh, threadIdx.x == 0, lc_target, acc);
 }
 
 __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
@@ -174,91 +243,92 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
                                                  float dscale, long np3, float* __restrict__ out,
                                                  long row_stride, int contrast, float cinv) {
   __shared__ DepShared sh;
-  const int nt = nm >> 3;
+  const int nt = nm / kTile;
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
-  const int t8[3] = {tx * 8, ty * 8, tz * 8};
+  const int t0[3] = {tx * kTile, ty * kTile, tz * kTile};
 
+  // Segments: thread nb < 8 handles the neighbour tile (tx-dx, ty-dy, tz-dz),
+  // taking the buckets whose face class covers the required offset bits.
+  if (threadIdx.x < 8) {
+    const int nb = threadIdx.x;
+    const int dx = (nb >> 2) & 1, dy = (nb >> 1) & 1, dz = nb & 1;
+    int ux = tx - dx, uy = ty - dy, uz = tz - dz;
+    if (ux < 0) ux += nt;
+    if (uy < 0) uy += nt;
+    if (uz < 0) uz += nt;
+    const uint32_t tn = ((uint32_t)ux * nt + uy) * nt + uz;
+    uint32_t o[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o[q] = off[tn * 8u + q];
+    int slot = nb * 4;
+    int cls = 0;
+    while (cls < 8) {
+      if ((cls & nb) != nb) { ++cls; continue; }
+      int c2 = cls;
+      while (c2 + 1 < 8 && ((c2 + 1) & nb) == nb) ++c2;
+      sh.seg_start[slot] = o[cls];
+      sh.seg_len[slot] = o[c2 + 1] - o[cls];
+      ++slot;
+      cls = c2 + 1;
+    }
+    for (; slot < nb * 4 + 4; ++slot) sh.seg_len[slot] = 0;
+  }
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT) sh.rho[i] = 0.0f;
+  __syncthreads();
   if (threadIdx.x == 0) {
     int ns = 0;
-    uint32_t acc = 0;
-    for (int nb = 0; nb < 8; ++nb) {
-      const int dx = (nb >> 2) & 1, dy = (nb >> 1) & 1, dz = nb & 1;
-      int ux = tx - dx, uy = ty - dy, uz = tz - dz;
-      if (ux < 0) ux += nt;
-      if (uy < 0) uy += nt;
-      if (uz < 0) uz += nt;
-      const uint32_t tn = ((uint32_t)ux * nt + uy) * nt + uz;
-      const int req = nb;
-      int cls = 0;
-      while (cls < 8) {
-        if ((cls & req) != req) { ++cls; continue; }
-        int c2 = cls;
-        while (c2 + 1 < 8 && ((c2 + 1) & req) == req) ++c2;
-        const uint32_t a = off[tn * 8u + cls], b = off[tn * 8u + c2 + 1];
-        if (b > a) {
-          sh.seg_start[ns] = a;
-          sh.seg_pre[ns] = acc;
-          acc += b - a;
-          ++ns;
-        }
-        cls = c2 + 1;
+    for (int q = 0; q < kMaxSeg; ++q)
+      if (sh.seg_len[q] > 0) {
+        sh.seg_start[ns] = sh.seg_start[q];
+        sh.seg_len[ns] = sh.seg_len[q];
+        ++ns;
       }
-    }
-    sh.seg_pre[ns] = acc;
     sh.nseg = ns;
   }
-  for (int i = threadIdx.x; i < 8 * kNReg; i += kDT) sh.P[i] = 0.0f;
   __syncthreads();
-  const uint32_t total = sh.seg_pre[sh.nseg];
 
-  if (total > 0) {
-    uint32_t n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t8, total, 0, 0);
-    if (n <= (uint32_t)kCap) {
+  uint32_t n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 0, 0);
+  if (n <= (uint32_t)kCap) {
+    if (n > 0) {
       sort_keys(sh, n);
-      cell_partials(sh, disp, np3, np, nm, dscale, n);
-    } else {
-      for (int slab = 0; slab < kReg; ++slab) {
-        n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t8, total, 1, slab);
+      accumulate_sorted(sh, n);
+    }
+  } else {
+    for (int slab = 0; slab < kReg; ++slab) {
+      n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 1, slab);
+      if (n == 0) continue;
+      if (n <= (uint32_t)kCap) {
+        sort_keys(sh, n);
+        accumulate_sorted(sh, n);
+        continue;
+      }
+      for (int cc = 0; cc < kReg * kReg; ++cc) {
+        const int lc = slab * kReg * kReg + cc;
+        n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 2, lc);
         if (n == 0) continue;
         if (n <= (uint32_t)kCap) {
           sort_keys(sh, n);
-          cell_partials(sh, disp, np3, np, nm, dscale, n);
-          continue;
-        }
-        for (int cc = 0; cc < kReg * kReg; ++cc) {
-          const int lc = slab * kReg * kReg + cc;
-          n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t8, total, 2, lc);
-          if (n == 0) continue;
-          if (n <= (uint32_t)kCap) {
-            sort_keys(sh, n);
-            cell_partials(sh, disp, np3, np, nm, dscale, n);
-          } else {
-            cell_partials_select(sh, disp, perm, np3, np, nm, dscale, t8, total, lc);
-          }
+          accumulate_sorted(sh, n);
+        } else {
+          accumulate_select(sh, disp, perm, np3, np, nm, dscale, t0, lc);
         }
       }
     }
   }
 
-  for (int nn = threadIdx.x; nn < 512; nn += kDT) {
-    const int nx = nn >> 6, ny = (nn >> 3) & 7, nz = nn & 7;
-    float rho = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int sx = (k >> 2) & 1, sy = (k >> 1) & 1, sz = k & 1;
-      const int lc = ((nx - sx + 1) * kReg + (ny - sy + 1)) * kReg + (nz - sz + 1);
-      rho = __fadd_rn(rho, sh.P[k * kNReg + lc]);
-    }
+  for (int nn = threadIdx.x; nn < kTile * kTile * kTile; nn += kDT) {
+    const int nx = nn / (kTile * kTile), ny = (nn / kTile) % kTile, nz = nn % kTile;
+    const float rho = sh.rho[nn];
     const float val = contrast ? __fsub_rn(__fmul_rn(rho, cinv), 1.0f) : rho;
-    out[((long)(t8[0] + nx) * nm + (t8[1] + ny)) * row_stride + (t8[2] + nz)] = val;
+    out[((long)(t0[0] + nx) * nm + (t0[1] + ny)) * row_stride + (t0[2] + nz)] = val;
   }
 }
 
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off, int np, int nm,
                     float dscale, float* out, long row_stride, int contrast, hipStream_t s) {
   const long np3 = (long)np * np * np;
-  const int nt = nm >> 3;
+  const int nt = nm / kTile;
   const long ntiles = (long)nt * nt * nt;
   const float cinv = (float)((double)nm * nm * nm / (double)np3);
   hipLaunchKernelGGL(k_deposit, dim3((unsigned)ntiles), dim3(kDT), 0, s, disp, perm, off, np, nm,

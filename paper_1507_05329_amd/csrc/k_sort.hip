@@ -1,4 +1,4 @@
-// Tile sort for the deterministic CIC deposit: bucket = (8^3 tile of the home
+// Tile sort for the deterministic CIC deposit: bucket = (16^3 tile of the home
 // cell, face class).  Integer atomics only; the order inside a bucket is left
 // to the deposit, which orders particles by id itself.
 #include "cola_device.h"
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ dis
   int c[3];
   float f[3];
   home_cell(disp, np3, (uint32_t)i, np, nm, dscale, c, f);
-  const uint32_t b = bucket_of(c, nm >> 3);
+  const uint32_t b = bucket_of(c, nm >> 4);
   pkey[i] = b;
   prank[i] = atomicAdd(&counts[b], 1u);
 }

@@ -52,9 +52,11 @@ def test_host_step_scalars_match_oracle():
 @pytest.mark.parametrize("np_side,nmesh,code", [
     (32, 60, _lib.COLA_EUNSUPPORTED),    # not a multiple of 8
     (32, 40, _lib.COLA_EUNSUPPORTED),    # 40 = 8 * 5: prime factor 5
+    (48, 144, _lib.COLA_EUNSUPPORTED),   # {2,3}-smooth but no compiled kernels for 144
     (31, 64, _lib.COLA_EUNSUPPORTED),    # odd particle grid
     (64, 32, _lib.COLA_EUNSUPPORTED),    # mesh coarser than the particle grid
     (32, 8, _lib.COLA_EINVAL),           # mesh too small
+    (16, 16, _lib.COLA_EINVAL),          # the deposit needs two 16^3 tiles per side
 ])
 def test_workspace_query_rejects_bad_sizes(np_side, nmesh, code):
     lib, p = params(np_side, nmesh)

@@ -34,7 +34,7 @@ def test_replay_against_scalar_loop():
     cells, f = cic_fp32.home_cells(disp, np_side, nm)
     for n in itertools.product(range(nm), repeat=3):
         acc = F32(0.0)
-        for k in range(8):
+        for k in range(7, -1, -1):           # source cells in ascending index
             s = ((k >> 2) & 1, (k >> 1) & 1, k & 1)
             c = [(n[e] - s[e]) % nm for e in range(3)]
             part = F32(0.0)
