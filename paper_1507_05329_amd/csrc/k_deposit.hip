@@ -9,9 +9,8 @@
 // keyed (region cell, particle id, LDS slot) and sorted in LDS, so each
 // cell's 8 partial sums add its particles' weights in ascending id.  Nodes
 // then receive the partial sums of their 8 source cells in ascending
-// source-cell order: runs of equal cell are processed in sorted batches, and
-// within a batch in 8 phases (offset k = 7 .. 0), each phase conflict-free
-// (distinct cells -> distinct nodes).  The result is independent of launch
+// source-cell order, in 8 phases (offset k = 7 .. 0) that are each
+// conflict-free (distinct cells -> distinct nodes).  The result is independent of launch
 // order, atomics and the order inside the buckets.  Regions holding more
 // particles than fit in LDS are processed by x-slab, then by single cell,
 // then by an ordered selection, keeping the same order.
@@ -40,7 +39,7 @@ struct DepShared {
   float fx[kCap], fy[kCap], fz[kCap];
   float rho[kTile * kTile * kTile];
   uint16_t run[kCap + 1];                 // start of each run of equal cell
-  uint32_t scan[kDT];
+  uint32_t scan[kDT / 64];
   uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
   int nseg;
   int nrun;
@@ -93,30 +92,83 @@ __device__ uint32_t gather_keys(DepShared& sh, const float* __restrict__ disp,
   return sh.count;
 }
 
-__device__ void sort_keys(DepShared& sh, uint32_t n) {
-  uint32_t p2 = 1;
-  while (p2 < n) p2 <<= 1;
-  for (uint32_t j = n + threadIdx.x; j < p2; j += kDT) sh.keys[j] = ~0ull;
-  __syncthreads();
+// Bitonic sort of keys[0, n) ascending (padding with ~0).  Each active
+// thread holds E = p2/kDT (>= 1) consecutive keys in registers; compare-
+// exchange partners closer than 64 E are reached through registers or lane
+// shuffles, farther ones through LDS (two barriers per such stage).
+template <int E>
+__device__ void bitonic_regs(DepShared& sh, uint32_t p2) {
+  const uint32_t tid = threadIdx.x;
+  const bool act = tid * E < p2;
+  uint64_t v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = act ? sh.keys[tid * E + e] : ~0ull;
   for (uint32_t k = 2; k <= p2; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < p2; i += kDT) {
-        const uint32_t ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t a = sh.keys[i], b = sh.keys[ixj];
+      if (j >= 64u * E) {
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) sh.keys[tid * E + e] = v[e];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const uint32_t i = tid * E + e;
+            const uint64_t o = sh.keys[i ^ j];
+            const bool up = (i & k) == 0;
+            const bool lower = (i & j) == 0;
+            v[e] = (lower == up) ? (v[e] < o ? v[e] : o) : (v[e] < o ? o : v[e]);
+          }
+        }
+      } else if (j >= (uint32_t)E) {
+        const int lanemask = (int)(j / E);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const uint32_t i = tid * E + e;
+          const uint64_t o = __shfl_xor(v[e], lanemask, 64);
           const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            sh.keys[i] = b;
-            sh.keys[ixj] = a;
+          const bool lower = (i & j) == 0;
+          v[e] = (lower == up) ? (v[e] < o ? v[e] : o) : (v[e] < o ? o : v[e]);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if ((e & j) == 0) {
+            const uint32_t i = tid * E + e;
+            const int e2 = e ^ (int)j;
+            const bool up = (i & k) == 0;
+            const uint64_t a = v[e], b = v[e2];
+            if ((a > b) == up) {
+              v[e] = b;
+              v[e2] = a;
+            }
           }
         }
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) sh.keys[tid * E + e] = v[e];
+  }
+  __syncthreads();
 }
 
-// Ordered list of run starts (runs of equal cell in the sorted keys).
+__device__ void sort_keys(DepShared& sh, uint32_t n) {
+  uint32_t p2 = 64;
+  while (p2 < n) p2 <<= 1;
+  for (uint32_t j = n + threadIdx.x; j < p2; j += kDT) sh.keys[j] = ~0ull;
+  __syncthreads();
+  if (p2 <= (uint32_t)kDT) bitonic_regs<1>(sh, p2);
+  else if (p2 <= 2u * kDT) bitonic_regs<2>(sh, p2);
+  else bitonic_regs<4>(sh, p2);
+}
+
+// Ordered list of run starts (runs of equal cell in the sorted keys):
+// wave-level scan of start flags, one barrier for the wave totals.
 __device__ void find_runs(DepShared& sh, uint32_t n) {
   constexpr int kPer = kCap / kDT;
   uint32_t flags = 0, cnt = 0;
@@ -128,64 +180,75 @@ __device__ void find_runs(DepShared& sh, uint32_t n) {
     flags |= (uint32_t)st << q;
     cnt += st;
   }
-  sh.scan[threadIdx.x] = cnt;
-  __syncthreads();
-  for (int off = 1; off < kDT; off <<= 1) {
-    const uint32_t a = threadIdx.x >= (unsigned)off ? sh.scan[threadIdx.x - off] : 0u;
-    __syncthreads();
-    sh.scan[threadIdx.x] += a;
-    __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t a = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += a;
   }
-  uint32_t pos = sh.scan[threadIdx.x] - cnt;
+  if (lane == 63) sh.scan[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int w = 0; w < kDT / 64; ++w) {
+    const uint32_t t = sh.scan[w];
+    if (w < wave) before += t;
+    total += t;
+  }
+  uint32_t pos = before + incl - cnt;
 #pragma unroll
   for (int q = 0; q < kPer; ++q)
     if (flags >> q & 1u) sh.run[pos++] = (uint16_t)(base + q);
-  if (threadIdx.x == kDT - 1) {
-    sh.nrun = (int)sh.scan[kDT - 1];
-    sh.run[sh.scan[kDT - 1]] = (uint16_t)n;
+  if (threadIdx.x == 0) {
+    sh.nrun = (int)total;
+    sh.run[total] = (uint16_t)n;
   }
   __syncthreads();
 }
 
-// Adds the 8 partial sums acc[k] of region cell lc to its tile nodes, in the
-// phase order k = 7 .. 0 (one barrier per phase; all threads participate).
-__device__ __forceinline__ void add_partials(DepShared& sh, bool active, int lc, const float acc[8]) {
+// Adds the 8 partial sums of region cell lc to its tile nodes for offset k.
+__device__ __forceinline__ void add_partial(DepShared& sh, int lc, int k, float acc) {
   const int rx = lc / (kReg * kReg), ry = (lc / kReg) % kReg, rz = lc % kReg;
-#pragma unroll
-  for (int k = 7; k >= 0; --k) {
-    if (active) {
-      const int nx = rx + ((k >> 2) & 1) - 1, ny = ry + ((k >> 1) & 1) - 1, nz = rz + (k & 1) - 1;
-      if (nx >= 0 && nx < kTile && ny >= 0 && ny < kTile && nz >= 0 && nz < kTile) {
-        float& r = sh.rho[(nx * kTile + ny) * kTile + nz];
-        r = __fadd_rn(r, acc[k]);
-      }
-    }
-    __syncthreads();
+  const int nx = rx + ((k >> 2) & 1) - 1, ny = ry + ((k >> 1) & 1) - 1, nz = rz + (k & 1) - 1;
+  if (nx >= 0 && nx < kTile && ny >= 0 && ny < kTile && nz >= 0 && nz < kTile) {
+    float& r = sh.rho[(nx * kTile + ny) * kTile + nz];
+    r = __fadd_rn(r, acc);
   }
 }
 
-// Partial sums of the n sorted keys, then node accumulation in sorted batches.
+// Partial sums of the n sorted keys (runs of equal cell, ascending id), then
+// the node accumulation in 8 phases k = 7 .. 0.  In phase k every node gets
+// at most one contribution (from cell n - s_k), so the phases fix the order
+// (ascending source cell) whatever the assignment of runs to threads.
 __device__ void accumulate_sorted(DepShared& sh, uint32_t n) {
+  constexpr int kRuns = kCap / kDT;  // runs per thread (nrun <= n <= kCap)
   find_runs(sh, n);
   const int nrun = sh.nrun;
-  for (int b0 = 0; b0 < nrun; b0 += kDT) {
-    const int r = b0 + (int)threadIdx.x;
-    const bool active = r < nrun;
-    float acc[8];
+  float acc[kRuns][8];
+  int lcs[kRuns];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
-    int lc = 0;
-    if (active) {
+  for (int q = 0; q < kRuns; ++q) {
+    const int r = (int)threadIdx.x + q * kDT;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[q][k] = 0.0f;
+    lcs[q] = -1;
+    if (r < nrun) {
       const uint32_t j0 = sh.run[r], j1 = sh.run[r + 1];
-      lc = (int)key_cell(sh.keys[j0]);
+      lcs[q] = (int)key_cell(sh.keys[j0]);
       for (uint32_t j = j0; j < j1; ++j) {
         const uint32_t sl = key_slot(sh.keys[j]);
         const float f[3] = {sh.fx[sl], sh.fy[sl], sh.fz[sl]};
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] = __fadd_rn(acc[k], cic_weight(f, k));
+        for (int k = 0; k < 8; ++k) acc[q][k] = __fadd_rn(acc[q][k], cic_weight(f, k));
       }
     }
-    add_partials(sh, active, lc, acc);
+  }
+#pragma unroll
+  for (int k = 7; k >= 0; --k) {
+#pragma unroll
+    for (int q = 0; q < kRuns; ++q)
+      if (lcs[q] >= 0) add_partial(sh, lcs[q], k, acc[q][k]);
+    __syncthreads();
   }
 }
 
@@ -231,10 +294,11 @@ __device__ void accumulate_select(DepShared& sh, const float* __restrict__ disp,
     first = false;
     __syncthreads();
   }
-  float acc[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = sh.acc8[k];
-  add_partials(sh, threadIdx.x == 0, lc_target, acc);
+  for (int k = 7; k >= 0; --k) {
+    if (threadIdx.x == 0) add_partial(sh, lc_target, k, sh.acc8[k]);
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,

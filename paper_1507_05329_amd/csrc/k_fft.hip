@@ -35,11 +35,11 @@ constexpr int radix_at(int n, int s) {
 constexpr int nstage(int n) { int s = 0; while (radix_at(n, s)) ++s; return s; }
 constexpr int ns_before(int n, int s) { int p = 1; for (int i = 0; i < s; ++i) p *= radix_at(n, i); return p; }
 
-// Launch shapes: at most ~66 KB of LDS per workgroup, 256 threads below
+// Launch shapes: at most 80 KB of LDS per workgroup, 256 threads below
 // 8192 staged complex values, 512 at 8192.
-constexpr int kLdsLimit = 66 * 1024;
-constexpr int cols_w(int n) { int w = 16; while (w > 1 && w * (n + 1) * 8 > kLdsLimit) w /= 2; return w; }
-constexpr int rows_nl(int h) { int nl = 16; while (nl > 1 && nl * (h + 1) * 8 > kLdsLimit) nl /= 2; return nl; }
+constexpr int kLdsLimit = 80 * 1024;
+constexpr int cols_w(int n) { int w = 16; while (w > 1 && w * (n + 1) * 8 + n * 4 > kLdsLimit) w /= 2; return w; }
+constexpr int rows_nl(int h) { int nl = 16; while (nl > 1 && nl * (h + 1) * 8 + h * 8 > kLdsLimit) nl /= 2; return nl; }
 constexpr int threads_for(int elems) { return elems >= 8192 ? 512 : 256; }
 // The fused Green's-function pass keeps the forward spectrum in registers
 // across its three inverse transforms: spread it over 512 threads.
@@ -130,6 +130,15 @@ template <> struct Dft<16> {
   }
 };
 
+// Twiddle exp(-2 pi i m / n) for 0 <= m < n from a half table of n/2 entries
+// (the second half is the negated first half).
+template <int NT>
+__device__ __forceinline__ float2 tw_get(const float2* __restrict__ twl, int m) {
+  if (m < NT / 2) return twl[m];
+  const float2 w = twl[m - NT / 2];
+  return make_float2(-w.x, -w.y);
+}
+
 // Stages S.. of a length-N transform of NL lines (line l at buf[l * LD]), T
 // threads, twiddle table stride TWS, FWD = 1 forward / 0 inverse.
 template <int N, int NL, int LD, int T, int TWS, int FWD, int S>
@@ -152,7 +161,7 @@ __device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float
           const int k = j % NS;
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            float2 w = tw[r * k * STEP];  // exp(-2 pi i m / n)
+            float2 w = tw_get<N * TWS>(tw, r * k * STEP);  // exp(-2 pi i m / n)
             if (!FWD) w.y = -w.y;         // inverse: conjugate
             v[b][r] = cmul(v[b][r], w);
           }
@@ -189,14 +198,16 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z
     float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw) {
   constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
   __shared__ float2 lds[NL * LD];
+  __shared__ float2 twl[N / 2];
   float2* base = mesh + blockIdx.y * mesh_stride;
   const long r0 = (long)blockIdx.x * NL;
+  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
   for (int i = threadIdx.x; i < NL * H; i += T) {
     const int l = i / H, j = i - l * H;
     if (r0 + l < nrows) lds[l * LD + j] = base[(r0 + l) * cols + j];
   }
   __syncthreads();
-  lds_fft<H, NL, LD, T, 2, 1>(lds, tw);
+  lds_fft<H, NL, LD, T, 2, 1>(lds, twl);
   // split step: X_k = E_k + W_n^k O_k, E = (Z_k + conj Z_{h-k})/2, O = -i (Z_k - conj Z_{h-k})/2
   for (int i = threadIdx.x; i < NL * cols; i += T) {
     const int l = i / cols, k = i - l * cols;
@@ -208,7 +219,7 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z
       b.y = -b.y;
       const float2 e = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
       const float2 o = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
-      x = cadd(e, cmul(tw[k], o));
+      x = cadd(e, cmul(tw_get<N>(twl, k), o));
     }
     base[(r0 + l) * cols + k] = x;
   }
@@ -220,8 +231,10 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z
     float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw) {
   constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
   __shared__ float2 lds[NL * LD];
+  __shared__ float2 twl[N / 2];
   float2* base = mesh + blockIdx.y * mesh_stride;
   const long r0 = (long)blockIdx.x * NL;
+  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
   for (int i = threadIdx.x; i < NL * (H + 1); i += T) {
     const int l = i / (H + 1), j = i - l * (H + 1);
     lds[l * LD + j] = r0 + l < nrows ? base[(r0 + l) * cols + j] : make_float2(0.f, 0.f);
@@ -238,7 +251,7 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z
     {
       const float2 cb = make_float2(xb.x, -xb.y);
       const float2 e = cadd(xa, cb);
-      float2 w = tw[k];
+      float2 w = tw_get<N>(twl, k);
       w.y = -w.y;
       const float2 o = cmul(csub(xa, cb), w);
       za = cadd(e, make_float2(-o.y, o.x));
@@ -246,7 +259,7 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z
     {
       const float2 ca = make_float2(xa.x, -xa.y);
       const float2 e = cadd(xb, ca);
-      float2 w = tw[k2];
+      float2 w = tw_get<N>(twl, k2);
       w.y = -w.y;
       const float2 o = cmul(csub(xb, ca), w);
       zb = cadd(e, make_float2(-o.y, o.x));
@@ -255,7 +268,7 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z
     if (k2 != k && k2 != H) lds[l * LD + k2] = zb;
   }
   __syncthreads();
-  lds_fft<H, NL, LD, T, 2, 0>(lds, tw);
+  lds_fft<H, NL, LD, T, 2, 0>(lds, twl);
   for (int i = threadIdx.x; i < NL * H; i += T) {
     const int l = i / H, j = i - l * H;
     if (r0 + l < nrows) base[(r0 + l) * cols + j] = lds[l * LD + j];
@@ -311,6 +324,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
   constexpr int W = cols_w(N), LD = N + 1, T = cols_threads(N, MODE);
   constexpr int E = (W * N + T - 1) / T;
   __shared__ float2 lds[W * LD];
+  __shared__ float2 twl[N / 2];
   const uint32_t nblk = (uint32_t)g.nchunk * g.nplanes;
   const uint32_t bid = xcd_remap(blockIdx.x, nblk);
   const int p = bid / g.nchunk;
@@ -318,6 +332,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
   const long mofs = (long)blockIdx.y * mesh_stride;
   const float2* src = in + mofs + p * g.plane_stride + c0;
   // load: consecutive threads take consecutive columns
+  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
   for (int i = threadIdx.x; i < N * W; i += T) {
     const int e = i / W, c = i - e * W;
     lds[c * LD + e] = src[e * g.elem_stride + c];
@@ -326,9 +341,9 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
   const int pfreq = y_is_plane_freq ? signed_freq(p, N) : 0;
 
   if constexpr (MODE == X_FWD || MODE == X_INV) {
-    lds_fft<N, W, LD, T, 1, MODE == X_FWD ? 1 : 0>(lds, tw);
+    lds_fft<N, W, LD, T, 1, MODE == X_FWD ? 1 : 0>(lds, twl);
   } else if constexpr (MODE == X_FWD_AMP) {
-    lds_fft<N, W, LD, T, 1, 1>(lds, tw);
+    lds_fft<N, W, LD, T, 1, 1>(lds, twl);
     for (int i = threadIdx.x; i < N * W; i += T) {
       const int c = i / N, e = i - c * N;
       const float2 m = multiplier(0, 0, 0, 0, 0.f, signed_freq(e, N), pfreq, c0 + c, N, amp, 1);
@@ -342,7 +357,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
       lds[c * LD + e] = cmul(lds[c * LD + e], m);
     }
     __syncthreads();
-    lds_fft<N, W, LD, T, 1, 0>(lds, tw);
+    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
   }
 
   if constexpr (MODE != X_FWD_GREEN3) {
@@ -352,39 +367,58 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
       dst[e * g.elem_stride + c] = lds[c * LD + e];
     }
   } else {
-    // PM: forward along x, then for each axis d: multiply by i k_d alpha / k^2
-    // (scaled to mesh units and 1/N^3), inverse along x, store to out_d.
-    lds_fft<N, W, LD, T, 1, 1>(lds, tw);
-    float2 spec[E];
+    // PM: forward along x gives S = DFT[delta]; with phi = scale S / |n|^2,
+    //   g_x = IDFT_x[i n_x phi]  (n_x on its Nyquist index -> 0),
+    //   g_y = i n_y IDFT_x[phi], g_z = i n_z IDFT_x[phi]
+    // (n_y, n_z are constant along an x line: one inverse transform serves
+    // both; their Nyquist planes give zero).  Two inverse transforms.
+    lds_fft<N, W, LD, T, 1, 1>(lds, twl);
+    float2 phi[E];
 #pragma unroll
     for (int b = 0; b < E; ++b) {
       const int i = threadIdx.x + b * T;
       if ((W * N) % T == 0 || i < N * W) {
         const int c = i / N, e = i - c * N;
-        spec[b] = lds[c * LD + e];
+        const int nx = signed_freq(e, N), nz = c0 + c;
+        const int n2 = nx * nx + pfreq * pfreq + nz * nz;
+        const float inv = (n2 == 0 || nz > N / 2) ? 0.f : scale / (float)n2;
+        const float2 v = lds[c * LD + e];
+        phi[b] = make_float2(inv * v.x, inv * v.y);
+        const float kx = (nx == N / 2 || nx == -N / 2) ? 0.f : (float)nx;
+        lds[c * LD + e] = make_float2(-kx * phi[b].y, kx * phi[b].x);  // i n_x phi
       }
     }
     __syncthreads();
-    float2* outs[3] = {out0, out1, out2};
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d) {
-#pragma unroll
-      for (int b = 0; b < E; ++b) {
-        const int i = threadIdx.x + b * T;
-        if ((W * N) % T == 0 || i < N * W) {
-          const int c = i / N, e = i - c * N;
-          const float2 m = multiplier(M_GRAD, 1, d, 0, scale, signed_freq(e, N), pfreq, c0 + c, N, amp, 0);
-          lds[c * LD + e] = cmul(spec[b], m);
-        }
-      }
-      __syncthreads();
-      lds_fft<N, W, LD, T, 1, 0>(lds, tw);
-      float2* dst = outs[d] + p * g.plane_stride + c0;
+    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
+    {
+      float2* dst = out0 + p * g.plane_stride + c0;
       for (int i = threadIdx.x; i < N * W; i += T) {
         const int e = i / W, c = i - e * W;
         dst[e * g.elem_stride + c] = lds[c * LD + e];
       }
-      __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E; ++b) {
+      const int i = threadIdx.x + b * T;
+      if ((W * N) % T == 0 || i < N * W) {
+        const int c = i / N, e = i - c * N;
+        lds[c * LD + e] = phi[b];
+      }
+    }
+    __syncthreads();
+    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
+    {
+      const float ky = (pfreq == N / 2 || pfreq == -N / 2) ? 0.f : (float)pfreq;
+      float2* dy = out1 + p * g.plane_stride + c0;
+      float2* dz = out2 + p * g.plane_stride + c0;
+      for (int i = threadIdx.x; i < N * W; i += T) {
+        const int e = i / W, c = i - e * W;
+        const float kz = (c0 + c >= N / 2) ? 0.f : (float)(c0 + c);
+        const float2 v = lds[c * LD + e];
+        dy[e * g.elem_stride + c] = make_float2(-ky * v.y, ky * v.x);
+        dz[e * g.elem_stride + c] = make_float2(-kz * v.y, kz * v.x);
+      }
     }
   }
 }

@@ -23,13 +23,28 @@ __global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ dis
                                                    uint32_t* __restrict__ pkey,
                                                    uint32_t* __restrict__ prank) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= np3) return;
+  if (i >= np3) return;  // np3 is a multiple of 64 for every supported size: whole waves exit
   int c[3];
   float f[3];
   home_cell(disp, np3, (uint32_t)i, np, nm, dscale, c, f);
   const uint32_t b = bucket_of(c, nm >> 4);
   pkey[i] = b;
-  prank[i] = atomicAdd(&counts[b], 1u);
+  // Wavefront-aggregated count: lanes with equal bucket share one atomic
+  // (consecutive particles are Lagrangian neighbours and share buckets).
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(1);
+  uint32_t rank = 0;
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const uint32_t lb = __shfl(b, leader, 64);
+    const uint64_t same = __ballot(b == lb) & todo;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&counts[lb], (uint32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if (b == lb) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  prank[i] = rank;
 }
 
 void launch_bin_count(const float* disp, int np, int nm, float dscale, uint32_t* counts,
