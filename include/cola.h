@@ -153,6 +153,43 @@ int cola_set_state(cola_ctx* ctx, const float* dev_disp, const float* dev_vres,
  * the 1/n^3 factor. */
 int cola_fft3d(cola_ctx* ctx, int32_t n, float* dev_mesh, int32_t inverse);
 
+/* ---- Reverse mode (adjoint).  Cotangents are float32 device arrays in the
+ * particle layout (3 * np^3, mesh units); the same conventions as above. */
+
+/* Adjoint of one cola_step a0 -> a1 whose velocity was at a_v0 and whose
+ * start positions (displacements) were dev_disp0.  On entry dev_dbar,
+ * dev_vbar hold the cotangents of (displacement, residual velocity) at a1;
+ * on return those at a0 (overwritten in place).  dev_psi1bar, dev_psi2bar
+ * accumulate (+=) the cotangents of Psi1, Psi2.  Recomputes the PM force at
+ * dev_disp0 (tile sort, deposit, FFTs), then: reverse kick/drift, readout
+ * weight gradient, transposed readout as a deterministic weighted deposit,
+ * transposed Green's function (-i k alpha / k^2; 3 forward, 1 inverse FFT)
+ * and the deposit weight gradient.  Uses the context's Psi1, Psi2 (from the
+ * last initial condition); does not change the particle state. */
+int cola_step_adjoint(cola_ctx* ctx, double a0, double a1, double a_v0, const float* dev_disp0,
+                      float* dev_dbar, float* dev_vbar, float* dev_psi1bar, float* dev_psi2bar);
+
+/* dev_dbar += d <delta_bar, delta(disp)> / d disp, where delta is the density
+ * contrast cola_density computes at displacements dev_disp and dev_delta_bar
+ * is an nmesh^3 float32 C-order mesh. */
+int cola_density_adjoint(cola_ctx* ctx, const float* dev_disp, const float* dev_delta_bar,
+                         float* dev_dbar);
+
+/* dev_dbar += d (sum_b cbar_b P_b) / d disp for the estimator of cola_pk at
+ * displacements dev_disp (ngrid, k_edges, nbins as for cola_pk; host_cbar has
+ * nbins entries; bins with no modes contribute nothing).  Synchronises. */
+int cola_pk_adjoint(cola_ctx* ctx, const float* dev_disp, int32_t ngrid, const double* k_edges,
+                    int32_t nbins, const double* host_cbar, float* dev_dbar);
+
+/* Adjoint of the 2LPT initial condition built from dev_noise (with the P(k)
+ * table of the last cola_init_2lpt* call): given the cotangent dev_dbar0 of
+ * the initial displacement and the accumulated dev_psi1bar, dev_psi2bar,
+ * writes the cotangent of the white noise to dev_noise_bar (np^3).  The
+ * initial residual velocity is zero and carries no dependence. */
+int cola_init_2lpt_adjoint(cola_ctx* ctx, const float* dev_noise, const float* dev_dbar0,
+                           const float* dev_psi1bar, const float* dev_psi2bar,
+                           float* dev_noise_bar);
+
 /* Host scalars of the step a_x -> a1 with velocity at a_v (FP64):
  * out[0..9] = alpha, D1(a_x), D2(a_x), D1(a1)-D1(a_x), D2(a1)-D2(a_x),
  * K (kick factor), I (drift factor), a_h, D1(a1), D2(a1). */

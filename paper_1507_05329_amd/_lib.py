@@ -53,6 +53,10 @@ _SIGS = {
     "cola_fft3d": (C.c_int, [_P, _I, _P, _I]),
     "cola_step_scalars": (C.c_int, [C.POINTER(cola_params), _D, _D, _D, _DP]),
     "cola_stage_times": (C.c_int, [_P, _DP, C.POINTER(C.c_int64)]),
+    "cola_step_adjoint": (C.c_int, [_P, _D, _D, _D, _P, _P, _P, _P, _P]),
+    "cola_density_adjoint": (C.c_int, [_P, _P, _P, _P]),
+    "cola_pk_adjoint": (C.c_int, [_P, _P, _I, _DP, _I, _DP, _P]),
+    "cola_init_2lpt_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "cola_synchronize": (C.c_int, [_P]),
     "cola_strerror": (C.c_char_p, [C.c_int]),
     "cola_last_error": (C.c_char_p, [_P]),

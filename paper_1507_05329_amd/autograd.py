@@ -1,0 +1,99 @@
+"""Differentiable COLA run: d(loss on the final density or binned P(k)) / d(white noise).
+
+The backward pass is the hand-written adjoint of libcola (reverse kick/drift,
+transposed CIC readout and deposit, transposed Green's function, transposed
+2LPT maps).  Memory: the full particle state is kept every ``segment`` steps;
+inside a segment the step-start positions are recomputed forward, then the
+segment is reversed (each step is recomputed at most once).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .sim import ColaSim
+
+
+def _run_segment(sim, edges, i0, i1):
+    """Forward steps i0..i1-1 from the current state; returns step-start (disp, a_v)."""
+    out = []
+    for i in range(i0, i1):
+        st = sim.get_state()
+        out.append((st["disp"], st["a_v"]))
+        sim.step(edges[i], edges[i + 1])
+    return out
+
+
+def _backward(sim, noise, edges, saved_states, segment, dbar, vbar):
+    p1b = torch.zeros_like(dbar)
+    p2b = torch.zeros_like(dbar)
+    nstep = len(edges) - 1
+    starts = list(range(0, nstep, segment))
+    for s0 in reversed(starts):
+        s1 = min(s0 + segment, nstep)
+        st = saved_states[s0]
+        sim.set_state(st["disp"], st["vres"], st["psi1"], st["psi2"], st["a_x"], st["a_v"])
+        steps = _run_segment(sim, edges, s0, s1)
+        for i in reversed(range(s0, s1)):
+            disp0, a_v0 = steps[i - s0]
+            sim.step_adjoint(edges[i], edges[i + 1], a_v0, disp0, dbar, vbar, p1b, p2b)
+    return sim.init_adjoint(noise, dbar, p1b, p2b)
+
+
+def _forward(sim, noise, k, pk, edges, segment):
+    sim.init_from_noise(noise, k, pk)
+    saved = {}
+    nstep = len(edges) - 1
+    for i in range(nstep):
+        if i % segment == 0:
+            saved[i] = {n: (v.clone() if torch.is_tensor(v) else v) for n, v in sim.get_state().items()}
+        sim.step(edges[i], edges[i + 1])
+    return saved
+
+
+class ColaDensity(torch.autograd.Function):
+    """noise (np^3) -> final density contrast (nmesh^3) through a full COLA run."""
+
+    @staticmethod
+    def forward(ctx, noise, sim: ColaSim, k, pk, edges, segment=1):
+        saved = _forward(sim, noise.detach().contiguous(), k, pk, edges, segment)
+        ctx.sim, ctx.edges, ctx.saved, ctx.segment = sim, list(edges), saved, segment
+        final = sim.get_state()
+        ctx.final_disp = final["disp"]
+        ctx.save_for_backward(noise)
+        return sim.density()
+
+    @staticmethod
+    def backward(ctx, grad_delta):
+        (noise,) = ctx.saved_tensors
+        sim = ctx.sim
+        dbar = torch.zeros_like(ctx.final_disp)
+        sim.density_adjoint(ctx.final_disp, grad_delta.contiguous(), dbar)
+        vbar = torch.zeros_like(dbar)
+        wbar = _backward(sim, noise.contiguous(), ctx.edges, ctx.saved, ctx.segment, dbar, vbar)
+        return wbar, None, None, None, None, None
+
+
+class ColaPowerSpectrum(torch.autograd.Function):
+    """noise -> binned P(k) of the final particles (host bins returned as a CPU tensor)."""
+
+    @staticmethod
+    def forward(ctx, noise, sim: ColaSim, k, pk, edges, kedges, ngrid=None, segment=1):
+        saved = _forward(sim, noise.detach().contiguous(), k, pk, edges, segment)
+        ctx.sim, ctx.edges, ctx.saved, ctx.segment = sim, list(edges), saved, segment
+        ctx.kedges, ctx.ngrid = np.asarray(kedges, np.float64), ngrid
+        final = sim.get_state()
+        ctx.final_disp = final["disp"]
+        ctx.save_for_backward(noise)
+        _, p, n = sim.pk(ctx.kedges, ngrid)
+        return torch.from_numpy(np.where(n > 0, p, 0.0))
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        (noise,) = ctx.saved_tensors
+        sim = ctx.sim
+        dbar = torch.zeros_like(ctx.final_disp)
+        sim.pk_adjoint(ctx.final_disp, ctx.kedges, grad_p.detach().cpu().double().numpy(), dbar, ctx.ngrid)
+        vbar = torch.zeros_like(dbar)
+        wbar = _backward(sim, noise.contiguous(), ctx.edges, ctx.saved, ctx.segment, dbar, vbar)
+        return wbar, None, None, None, None, None, None, None

@@ -56,7 +56,7 @@ int hip_fail(cola_ctx* c, hipError_t e, const char* where) {
 
 struct Layout {
   size_t disp, vres, psi1, psi2, pkey, prank, perm, counts, offsets, scan, mesh, tw, amp,
-      pk_partial, pk_out, pk_edges, flag, total;
+      pk_partial, pk_out, pk_edges, flag, fbar, pk_cbar, total;
   long nbucket, mesh_stride, mesh_region, amp_len;
   int tw_cap;
 };
@@ -78,7 +78,7 @@ Layout layout(const cola_params* p) {
   const long nt = p->nmesh / 16;           // 16^3-cell tiles of the deposit
   L.nbucket = 8 * nt * nt * nt;
   L.mesh_stride = mesh_complex_count(p->nmesh);
-  const long pm = 3 * L.mesh_stride, ic = 4 * mesh_complex_count(p->np);
+  const long pm = 3 * L.mesh_stride, ic = 6 * mesh_complex_count(p->np);  // IC adjoint: 6 meshes
   L.mesh_region = pm > ic ? pm : ic;
   L.amp_len = 3L * (p->np / 2) * (p->np / 2) + 1;
   L.tw_cap = p->nmesh > p->np ? p->nmesh : p->np;
@@ -101,6 +101,8 @@ Layout layout(const cola_params* p) {
   L.pk_out = take((size_t)kMaxBins * 3 * sizeof(double));
   L.pk_edges = take((size_t)(kMaxBins + 1) * sizeof(double));
   L.flag = take(sizeof(uint32_t) * 64);
+  L.fbar = take(3 * np3 * sizeof(float));
+  L.pk_cbar = take((size_t)kMaxBins * sizeof(double));
   L.total = o;
   return L;
 }
@@ -157,30 +159,30 @@ struct StageTimer {
 float2* ic_buf(cola_ctx* c, int i) { return c->meshbase + (size_t)i * mesh_complex_count(c->p.np); }
 
 // Tile sort of the current positions on an ng^3 grid.
-void tile_sort(cola_ctx* c, int ng) {
+void tile_sort(cola_ctx* c, int ng, const float* disp) {
   StageTimer t(c, COLA_STAGE_SORT);
   const float dscale = (float)((double)ng / (double)c->p.nmesh);
   const long nt = ng / 16;
   const long nb = 8 * nt * nt * nt;
   launch_fill_u32(c->counts, nb + 1, 0u, c->stream);
-  launch_bin_count(c->disp, c->p.np, ng, dscale, c->counts, c->pkey, c->prank, c->stream);
+  launch_bin_count(disp, c->p.np, ng, dscale, c->counts, c->pkey, c->prank, c->stream);
   launch_exclusive_scan(c->counts, c->offsets, nb, c->scan_scratch, c->stream);
   launch_scatter(c->pkey, c->prank, c->offsets, c->np3, c->perm, c->stream);
 }
 
-void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast) {
+void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast, const float* disp) {
   const float dscale = (float)((double)ng / (double)c->p.nmesh);
-  tile_sort(c, ng);
+  tile_sort(c, ng, disp);
   StageTimer t(c, COLA_STAGE_DEPOSIT);
-  launch_deposit(c->disp, c->perm, c->offsets, c->p.np, ng, dscale, out, row_stride, contrast,
+  launch_deposit(disp, c->perm, c->offsets, c->p.np, ng, dscale, out, row_stride, contrast,
                  c->stream);
 }
 
 // Deposit + FFT + Green x ik + inverse FFTs: the three force meshes in c->mesh[0..2].
-void force_meshes(cola_ctx* c, double alpha) {
+void force_meshes(cola_ctx* c, double alpha, const float* disp) {
   const int nm = c->p.nmesh;
   const long rs = 2 * padded_cols(nm);
-  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1);
+  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1, disp);
   {
     StageTimer t(c, COLA_STAGE_FFT_Z);
     fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream);
@@ -388,6 +390,8 @@ int cola_create(const cola_params* p, void* ws, size_t bytes, void* stream, cola
   c->pk_out = (double*)(c->ws + L.pk_out);
   c->pk_edges = (double*)(c->ws + L.pk_edges);
   c->flag = (uint32_t*)(c->ws + L.flag);
+  c->fbar = (float*)(c->ws + L.fbar);
+  c->pk_cbar = (double*)(c->ws + L.pk_cbar);
   int r = ensure_twiddles(c, p->nmesh);
   if (r == COLA_OK) r = ensure_twiddles(c, p->np);
   if (r != COLA_OK) {
@@ -450,7 +454,7 @@ int cola_step(cola_ctx* c, double a0, double a1) {
   kd.I = (float)I;
   kd.e1 = (float)s[3];
   kd.e2 = (float)s[4];
-  force_meshes(c, alpha);
+  force_meshes(c, alpha, c->disp);
   const long rs = 2 * padded_cols(c->p.nmesh);
   {
     StageTimer t(c, COLA_STAGE_KICKDRIFT);
@@ -468,7 +472,7 @@ int cola_force(cola_ctx* c, float* out) {
   if (!c || !out) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
   const double alpha = 1.5 * c->p.omega_m / c->a_x;
-  force_meshes(c, alpha);
+  force_meshes(c, alpha, c->disp);
   KickDrift kd{};
   const long rs = 2 * padded_cols(c->p.nmesh);
   launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
@@ -481,7 +485,7 @@ int cola_force(cola_ctx* c, float* out) {
 int cola_density(cola_ctx* c, float* out) {
   if (!c || !out) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
-  deposit(c, c->p.nmesh, out, c->p.nmesh, 1);
+  deposit(c, c->p.nmesh, out, c->p.nmesh, 1, c->disp);
   LAUNCH_CHECK(c, "cola_density");
   return COLA_OK;
 }
@@ -500,7 +504,7 @@ int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double*
   HIP_TRY(c, hipMemcpyAsync(c->pk_edges, edges, (nbins + 1) * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   float2* m = c->mesh[0];
-  deposit(c, ng, reinterpret_cast<float*>(m), 2 * padded_cols(ng), 1);
+  deposit(c, ng, reinterpret_cast<float*>(m), 2 * padded_cols(ng), 1, c->disp);
   fft3d_forward(m, ng, c->tw, c->stream);
   launch_pk_bin(m, ng, c->p.box, c->pk_edges, nbins, c->pk_partial, kPkChunks, c->stream);
   launch_pk_reduce(c->pk_partial, nbins, kPkChunks, c->pk_out, c->stream);
@@ -553,6 +557,194 @@ int cola_fft3d(cola_ctx* c, int32_t n, float* mesh, int32_t inverse) {
   if (inverse) fft3d_inverse(reinterpret_cast<float2*>(mesh), n, c->tw, c->stream);
   else fft3d_forward(reinterpret_cast<float2*>(mesh), n, c->tw, c->stream);
   LAUNCH_CHECK(c, "cola_fft3d");
+  return COLA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.
+
+int cola_step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const float* disp0,
+                      float* dbar, float* vbar, float* p1bar, float* p2bar) {
+  if (!c || !disp0 || !dbar || !vbar || !p1bar || !p2bar) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no 2LPT fields (run an initial condition first)");
+  if (!(a0 > 0) || !(a1 > a0) || !(a_v0 > 0) || !std::isfinite(a1))
+    return fail(c, COLA_EINVAL, "scale factors must satisfy 0 < a0 < a1, a_v0 > 0");
+  double s[10];
+  step_scalars(&c->p, a0, a_v0, a1, s);
+  const double alpha = s[0], D1 = s[1], D2 = s[2], K = s[5], I = s[6];
+  KickDrift kd;
+  kd.K = (float)K;
+  kd.c1 = (float)(K * alpha * D1);
+  kd.c2 = (float)(K * alpha * (D2 - D1 * D1));
+  kd.I = (float)I;
+  kd.e1 = (float)s[3];
+  kd.e2 = (float)s[4];
+  const int np = c->p.np, nm = c->p.nmesh;
+  const long rs = 2 * padded_cols(nm);
+  // forward force meshes at the checkpointed positions (also sorts them)
+  force_meshes(c, alpha, disp0);
+  float* g[3];
+  for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<float*>(c->mesh[d]);
+  // reverse kick/drift and the readout weight gradient; Fbar -> c->fbar
+  launch_adj_readout_kick(disp0, g[0], g[1], g[2], rs, np, nm, kd, dbar, vbar, p1bar, p2bar, c->fbar,
+                          c->stream);
+  // gbar_d = R^T Fbar_d (deterministic weighted deposit over the same sort)
+  launch_deposit3_weighted(disp0, c->perm, c->offsets, np, nm, c->fbar, g[0], rs, 2 * c->mesh_stride,
+                           c->stream);
+  // rhobar = (Nm^3/Np) deltabar,  deltabar = -sum_d G_d gbar_d
+  fft_r2c_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream);
+  fft_y(c->mesh[0], nm, 3, c->mesh_stride, 0, c->tw, c->stream);
+  CombineSpec cs;
+  cs.nin = 3;
+  cs.green = 1;
+  const double gscale = alpha * nm / (2.0 * kPi) / ((double)nm * nm * nm);
+  const double cratio = (double)nm * nm * nm / (double)c->np3;
+  cs.scale = (float)(-gscale * cratio);
+  const float2* ins[3] = {c->mesh[0], c->mesh[1], c->mesh[2]};
+  fft_combine_x(ins, c->mesh[0], nm, cs, nullptr, c->tw, c->stream);
+  fft_y(c->mesh[0], nm, 1, 0, 1, c->tw, c->stream);
+  fft_c2r_z(c->mesh[0], nm, 1, 0, c->tw, c->stream);
+  launch_adj_deposit_grad(disp0, g[0], rs, np, nm, 1.0f, 1.0f, dbar, c->stream);
+  LAUNCH_CHECK(c, "cola_step_adjoint");
+  return COLA_OK;
+}
+
+int cola_density_adjoint(cola_ctx* c, const float* disp, const float* delta_bar, float* dbar) {
+  if (!c || !disp || !delta_bar || !dbar) return fail(c, COLA_EINVAL, "null argument");
+  const int nm = c->p.nmesh;
+  const long rs = 2 * padded_cols(nm);
+  float* m = reinterpret_cast<float*>(c->mesh[0]);
+  launch_copy_to_mesh(delta_bar, nm, m, rs, c->stream);
+  const double cratio = (double)nm * nm * nm / (double)c->np3;
+  launch_adj_deposit_grad(disp, m, rs, c->p.np, nm, 1.0f, (float)cratio, dbar, c->stream);
+  LAUNCH_CHECK(c, "cola_density_adjoint");
+  return COLA_OK;
+}
+
+int cola_pk_adjoint(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32_t nbins,
+                    const double* cbar, float* dbar) {
+  if (!c || !disp || !edges || !cbar || !dbar) return fail(c, COLA_EINVAL, "null argument");
+  if (nbins < 1 || nbins > kMaxBins) return fail(c, COLA_EINVAL, "nbins out of range");
+  if (ng < 32 || ng > c->p.nmesh || !fft_size_supported(ng))
+    return fail(c, COLA_EUNSUPPORTED, "ngrid must be a supported size in [32, nmesh]");
+  for (int i = 0; i < nbins; ++i)
+    if (!(edges[i + 1] > edges[i])) return fail(c, COLA_EINVAL, "edges must increase");
+  int r = ensure_twiddles(c, ng);
+  if (r != COLA_OK) return r;
+  HIP_TRY(c, hipMemcpyAsync(c->pk_edges, edges, (nbins + 1) * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->pk_cbar, cbar, nbins * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const long rs = 2 * padded_cols(ng);
+  float2* X = c->mesh[0];
+  float2* Z = c->mesh[1];
+  deposit(c, ng, reinterpret_cast<float*>(X), rs, 1, disp);
+  fft3d_forward(X, ng, c->tw, c->stream);
+  launch_pk_bin(X, ng, c->p.box, c->pk_edges, nbins, c->pk_partial, kPkChunks, c->stream);
+  launch_pk_reduce(c->pk_partial, nbins, kPkChunks, c->pk_out, c->stream);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(Z), 2 * mesh_complex_count(ng), 0u, c->stream);
+  launch_pk_adj_modes(X, Z, ng, c->p.box, c->pk_edges, nbins, c->pk_cbar, c->pk_out, c->stream);
+  fft3d_inverse(Z, ng, c->tw, c->stream);
+  const float dscale = (float)((double)ng / (double)c->p.nmesh);
+  const double cratio = (double)ng * ng * ng / (double)c->np3;
+  launch_adj_deposit_grad(disp, reinterpret_cast<float*>(Z), rs, c->p.np, ng, dscale, (float)cratio,
+                          dbar, c->stream);
+  LAUNCH_CHECK(c, "cola_pk_adjoint");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // host edges / cbar released
+  return COLA_OK;
+}
+
+int cola_init_2lpt_adjoint(cola_ctx* c, const float* noise, const float* dbar0, const float* p1bar,
+                           const float* p2bar, float* noise_bar) {
+  if (!c || !noise || !dbar0 || !p1bar || !p2bar || !noise_bar)
+    return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no initial conditions (amplitude table)");
+  const int np = c->p.np, nm = c->p.nmesh;
+  const long rs = 2 * padded_cols(np);
+  const long ms = mesh_complex_count(np);
+  const double om = c->p.omega_m, a0 = c->p.a_init;
+  const float D1 = (float)growth_D1(a0, om), D2 = (float)growth_D2(a0, om);
+  const double inv3 = 1.0 / ((double)np * np * np);
+  const float sgrad = (float)(nm / (2.0 * kPi) * inv3);
+  float2* C0 = ic_buf(c, 0);
+  float2* S = ic_buf(c, 1);
+  float2* B = ic_buf(c, 2);   // B, B + ms, B + 2 ms
+  float2* Wb = ic_buf(c, 5);
+  auto fwd_zy3 = [&](float2* m) {
+    fft_r2c_z(m, np, 3, ms, c->tw, c->stream);
+    fft_y(m, np, 3, ms, 0, c->tw, c->stream);
+  };
+  auto inv_zy = [&](float2* m) {
+    fft_y(m, np, 1, 0, 1, c->tw, c->stream);
+    fft_c2r_z(m, np, 1, 0, c->tw, c->stream);
+  };
+  const float2* Bs[3] = {B, B + ms, B + 2 * ms};
+  // Sbar = IDFT[sum_d conj(M2_d) DFT(Psi2bar_d)], conj(M2_d) = +i n_d sg / |n|^2
+  launch_axpy_to_mesh(p2bar, dbar0, D2, np, reinterpret_cast<float*>(B), rs, 2 * ms, c->stream);
+  fwd_zy3(B);
+  CombineSpec cs;
+  cs.nin = 3;
+  cs.scale = sgrad;
+  fft_combine_x(Bs, S, np, cs, nullptr, c->tw, c->stream);
+  inv_zy(S);
+  // delta_L spectrum from the noise
+  launch_copy_to_mesh(noise, np, reinterpret_cast<float*>(C0), rs, c->stream);
+  fft_r2c_z(C0, np, 1, 0, c->tw, c->stream);
+  fft_y(C0, np, 1, 0, 0, c->tw, c->stream);
+  XPassArgs xa;
+  xa.in = C0;
+  xa.out[0] = C0;
+  xa.mode = X_FWD_AMP;
+  xa.amp = c->amp;
+  fft_x(xa, np, c->tw, c->stream);
+  auto phi_into = [&](float2* out, int i, int j) {
+    XPassArgs m;
+    m.in = C0;
+    m.out[0] = out;
+    m.mode = X_MULT_INV;
+    m.mult = M_HESS;
+    m.comp_a = i;
+    m.comp_b = j;
+    m.scale = (float)inv3;
+    fft_x(m, np, c->tw, c->stream);
+    inv_zy(out);
+  };
+  // diagonal phi_ii -> phibar_ii, then wbar += IDFT[A n_i n_i / n^2 / np^3 DFT(phibar_ii)]
+  for (int d = 0; d < 3; ++d) phi_into(B + d * ms, d, d);
+  launch_phibar_diag(reinterpret_cast<float*>(B), reinterpret_cast<float*>(B + ms),
+                     reinterpret_cast<float*>(B + 2 * ms), reinterpret_cast<float*>(S), np, rs, c->stream);
+  fwd_zy3(B);
+  CombineSpec hs;
+  hs.nin = 3;
+  hs.kind[0] = hs.kind[1] = hs.kind[2] = M_HESS;
+  hs.ca[0] = 0; hs.cb[0] = 0;
+  hs.ca[1] = 1; hs.cb[1] = 1;
+  hs.ca[2] = 2; hs.cb[2] = 2;
+  hs.scale = (float)inv3;
+  hs.use_amp = 1;
+  fft_combine_x(Bs, Wb, np, hs, c->amp, c->tw, c->stream);
+  // off-diagonal
+  const int od[3][2] = {{0, 1}, {1, 2}, {2, 0}};
+  for (int q = 0; q < 3; ++q) phi_into(B + q * ms, od[q][0], od[q][1]);
+  launch_phibar_off(reinterpret_cast<float*>(B), reinterpret_cast<float*>(S), np, rs, 2 * ms, c->stream);
+  fwd_zy3(B);
+  for (int q = 0; q < 3; ++q) {
+    hs.ca[q] = od[q][0];
+    hs.cb[q] = od[q][1];
+  }
+  hs.accumulate = 1;
+  fft_combine_x(Bs, Wb, np, hs, c->amp, c->tw, c->stream);
+  // Psi1: wbar += IDFT[A conj(M1_d) DFT(Psi1bar_d)], conj(M1_d) = -i n_d sg / |n|^2
+  launch_axpy_to_mesh(p1bar, dbar0, D1, np, reinterpret_cast<float*>(B), rs, 2 * ms, c->stream);
+  fwd_zy3(B);
+  CombineSpec gs;
+  gs.nin = 3;
+  gs.scale = -sgrad;
+  gs.use_amp = 1;
+  gs.accumulate = 1;
+  fft_combine_x(Bs, Wb, np, gs, c->amp, c->tw, c->stream);
+  inv_zy(Wb);
+  launch_copy_from_mesh(reinterpret_cast<float*>(Wb), np, rs, noise_bar, 1.0f, c->stream);
+  LAUNCH_CHECK(c, "cola_init_2lpt_adjoint");
   return COLA_OK;
 }
 

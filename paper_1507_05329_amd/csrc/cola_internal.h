@@ -60,6 +60,10 @@ void launch_scatter(const uint32_t* pkey, const uint32_t* prank, const uint32_t*
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off,
                     int np, int nm, float dscale, float* out, long row_stride, int contrast,
                     hipStream_t s);
+// Three weighted deposits at once (readout transpose): out[q] += sum_p wt[q][p] w_s(p).
+void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,
+                              int nm, const float* wt, float* out, long row_stride,
+                              long mesh_stride_floats, hipStream_t s);
 // FFT passes (k_fft.hip).
 enum XMode { X_FWD = 0, X_FWD_GREEN3 = 1, X_FWD_AMP = 2, X_MULT_INV = 3, X_INV = 4 };
 enum MultKind { M_NONE = 0, M_GRAD = 1, M_HESS = 2 };
@@ -72,6 +76,18 @@ struct XPassArgs {
   float scale = 1.f;            // multiplier scale
   const float* amp = nullptr;   // amplitude by integer |n|^2 (X_FWD_AMP)
 };
+// Spectral combination pass (adjoint): out = IDFT_x[sum_q m_q DFT_x(in_q)].
+struct CombineSpec {
+  int nin = 0;
+  int kind[3] = {M_GRAD, M_GRAD, M_GRAD};
+  int ca[3] = {0, 1, 2}, cb[3] = {0, 0, 0};
+  float scale = 1.f;
+  int green = 0;        // 1: a gradient is zeroed only on its own axis' Nyquist plane
+  int use_amp = 0;      // multiply by the amplitude table (all Nyquist modes zeroed)
+  int accumulate = 0;   // out += result
+};
+void fft_combine_x(const float2* const in[3], float2* out, int n, const CombineSpec& cs,
+                   const float* amp, const TwiddleSet& tw, hipStream_t s);
 void fft3d_forward(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
 void fft3d_inverse(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
 void fft_r2c_z(float2* mesh, int n, int nplanes_mesh, long mesh_stride, const TwiddleSet& tw, hipStream_t s);
@@ -103,6 +119,20 @@ void launch_axpby(float* y, const float* x, float a, float b, long n, hipStream_
 void launch_pk_bin(const float2* spec, int ng, double box, const double* edges, int nbins,
                    double* partial, int nchunk, hipStream_t s);
 void launch_pk_reduce(const double* partial, int nbins, int nchunk, double* out, hipStream_t s);
+// Adjoint kernels (k_adjoint.hip).
+void launch_adj_readout_kick(const float* disp, const float* g0, const float* g1, const float* g2,
+                             long row_stride, int np, int nm, const KickDrift& kd, float* dbar,
+                             float* vbar, float* p1bar, float* p2bar, float* fbar, hipStream_t s);
+void launch_adj_deposit_grad(const float* disp, const float* field, long row_stride, int np, int ng,
+                             float dscale, float coef, float* dbar, hipStream_t s);
+void launch_axpy_to_mesh(const float* a, const float* b, float alpha, int n, float* mesh,
+                         long row_stride, long mesh_stride_floats, hipStream_t s);
+void launch_phibar_diag(float* a, float* b, float* c, const float* sbar, int n, long row_stride,
+                        hipStream_t s);
+void launch_phibar_off(float* a, const float* sbar, int n, long row_stride, long mesh_stride_floats,
+                       hipStream_t s);
+void launch_pk_adj_modes(const float2* X, float2* Z, int ng, double box, const double* edges,
+                         int nbins, const double* cbar, const double* sums, hipStream_t s);
 // Non-finite check.
 void launch_check_finite(const float* x, long n, uint32_t* flag, hipStream_t s);
 
@@ -144,6 +174,8 @@ struct cola_ctx {
   double* pk_out = nullptr;
   double* pk_edges = nullptr;
   uint32_t* flag = nullptr;
+  float* fbar = nullptr;        // adjoint scratch, 3 * np3
+  double* pk_cbar = nullptr;    // P(k) loss cotangents (adjoint)
   // stage timers (COLA_F_STAGE_TIMERS): pairs of events per recorded stage
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_stage;       // stage of each recorded pair

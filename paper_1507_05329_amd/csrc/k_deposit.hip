@@ -27,17 +27,20 @@ constexpr int kDT = 512;                  // threads per workgroup
 constexpr int kTile = 16;                 // nodes per tile side
 constexpr int kReg = kTile + 1;           // region side (tile + lower layer)
 constexpr int kNReg = kReg * kReg * kReg;
-constexpr int kCap = 2048;                // particles held in LDS at once (power of two)
-constexpr int kSlotBits = 11;             // log2(kCap)
+constexpr int kSlotBits = 11;             // slot field width (capacity <= 2048)
 constexpr int kIdBits = 30;
 constexpr int kMaxSeg = 32;
-static_assert((1 << kSlotBits) == kCap, "slot field");
 static_assert(kNReg < (1 << (64 - kIdBits - kSlotBits)), "cell field");
 
+// NC = 1: unit masses (density).  NC = 3: three weighted deposits at once
+// (the transpose of the three-component CIC readout); weights are read by
+// particle id from global memory.
+template <int NC>
 struct DepShared {
+  static constexpr int kCap = NC == 1 ? 2048 : 1024;  // particles in LDS at once (power of two)
   uint64_t keys[kCap];                    // cell << 41 | id << 11 | slot
   float fx[kCap], fy[kCap], fz[kCap];
-  float rho[kTile * kTile * kTile];
+  float rho[NC][kTile * kTile * kTile];
   uint16_t run[kCap + 1];                 // start of each run of equal cell
   uint32_t scan[kDT / 64];
   uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
@@ -45,7 +48,7 @@ struct DepShared {
   int nrun;
   uint32_t count;
   uint32_t red[kDT / 64];
-  float acc8[8];
+  float acc8[8 * NC];
 };
 
 __device__ __forceinline__ int region_coord(int c, int t0, int nm) {
@@ -56,11 +59,13 @@ __device__ __forceinline__ int region_coord(int c, int t0, int nm) {
 }
 
 __device__ __forceinline__ uint32_t key_cell(uint64_t k) { return (uint32_t)(k >> (kIdBits + kSlotBits)); }
-__device__ __forceinline__ uint32_t key_slot(uint64_t k) { return (uint32_t)k & (kCap - 1); }
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)(k >> kSlotBits) & ((1u << kIdBits) - 1u); }
+__device__ __forceinline__ uint32_t key_slot(uint64_t k) { return (uint32_t)k & ((1u << kSlotBits) - 1u); }
 
 // filter: 0 = all, 1 = region x index == fv, 2 = region cell == fv.
 // Returns the number of matching particles (keys stored only when <= kCap).
-__device__ uint32_t gather_keys(DepShared& sh, const float* __restrict__ disp,
+template <int NC>
+__device__ uint32_t gather_keys(DepShared<NC>& sh, const float* __restrict__ disp,
                                 const uint32_t* __restrict__ perm, long np3, int np, int nm,
                                 float dscale, const int t0[3], int filter, int fv) {
   if (threadIdx.x == 0) sh.count = 0;
@@ -79,7 +84,7 @@ __device__ uint32_t gather_keys(DepShared& sh, const float* __restrict__ disp,
       const bool pass = inside && (filter == 0 || (filter == 1 && rx == fv) || (filter == 2 && lc == fv));
       if (pass) {
         const uint32_t slot = atomicAdd(&sh.count, 1u);
-        if (slot < (uint32_t)kCap) {
+        if (slot < (uint32_t)DepShared<NC>::kCap) {
           sh.keys[slot] = ((uint64_t)lc << (kIdBits + kSlotBits)) | ((uint64_t)id << kSlotBits) | slot;
           sh.fx[slot] = f[0];
           sh.fy[slot] = f[1];
@@ -96,8 +101,8 @@ __device__ uint32_t gather_keys(DepShared& sh, const float* __restrict__ disp,
 // thread holds E = p2/kDT (>= 1) consecutive keys in registers; compare-
 // exchange partners closer than 64 E are reached through registers or lane
 // shuffles, farther ones through LDS (two barriers per such stage).
-template <int E>
-__device__ void bitonic_regs(DepShared& sh, uint32_t p2) {
+template <int E, int NC>
+__device__ void bitonic_regs(DepShared<NC>& sh, uint32_t p2) {
   const uint32_t tid = threadIdx.x;
   const bool act = tid * E < p2;
   uint64_t v[E];
@@ -157,20 +162,22 @@ __device__ void bitonic_regs(DepShared& sh, uint32_t p2) {
   __syncthreads();
 }
 
-__device__ void sort_keys(DepShared& sh, uint32_t n) {
+template <int NC>
+__device__ void sort_keys(DepShared<NC>& sh, uint32_t n) {
   uint32_t p2 = 64;
   while (p2 < n) p2 <<= 1;
   for (uint32_t j = n + threadIdx.x; j < p2; j += kDT) sh.keys[j] = ~0ull;
   __syncthreads();
   if (p2 <= (uint32_t)kDT) bitonic_regs<1>(sh, p2);
   else if (p2 <= 2u * kDT) bitonic_regs<2>(sh, p2);
-  else bitonic_regs<4>(sh, p2);
+  else if constexpr (DepShared<NC>::kCap >= 4 * kDT) bitonic_regs<4>(sh, p2);
 }
 
 // Ordered list of run starts (runs of equal cell in the sorted keys):
 // wave-level scan of start flags, one barrier for the wave totals.
-__device__ void find_runs(DepShared& sh, uint32_t n) {
-  constexpr int kPer = kCap / kDT;
+template <int NC>
+__device__ void find_runs(DepShared<NC>& sh, uint32_t n) {
+  constexpr int kPer = DepShared<NC>::kCap / kDT;
   uint32_t flags = 0, cnt = 0;
   const uint32_t base = threadIdx.x * kPer;
 #pragma unroll
@@ -207,12 +214,16 @@ __device__ void find_runs(DepShared& sh, uint32_t n) {
 }
 
 // Adds the 8 partial sums of region cell lc to its tile nodes for offset k.
-__device__ __forceinline__ void add_partial(DepShared& sh, int lc, int k, float acc) {
+template <int NC>
+__device__ __forceinline__ void add_partial(DepShared<NC>& sh, int lc, int k, const float* acc) {
   const int rx = lc / (kReg * kReg), ry = (lc / kReg) % kReg, rz = lc % kReg;
   const int nx = rx + ((k >> 2) & 1) - 1, ny = ry + ((k >> 1) & 1) - 1, nz = rz + (k & 1) - 1;
   if (nx >= 0 && nx < kTile && ny >= 0 && ny < kTile && nz >= 0 && nz < kTile) {
-    float& r = sh.rho[(nx * kTile + ny) * kTile + nz];
-    r = __fadd_rn(r, acc);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      float& r = sh.rho[q][(nx * kTile + ny) * kTile + nz];
+      r = __fadd_rn(r, acc[q]);
+    }
   }
 }
 
@@ -220,26 +231,44 @@ __device__ __forceinline__ void add_partial(DepShared& sh, int lc, int k, float 
 // the node accumulation in 8 phases k = 7 .. 0.  In phase k every node gets
 // at most one contribution (from cell n - s_k), so the phases fix the order
 // (ascending source cell) whatever the assignment of runs to threads.
-__device__ void accumulate_sorted(DepShared& sh, uint32_t n) {
-  constexpr int kRuns = kCap / kDT;  // runs per thread (nrun <= n <= kCap)
+template <int NC>
+__device__ void accumulate_sorted(DepShared<NC>& sh, uint32_t n, const float* __restrict__ wt,
+                                  long np3) {
+  constexpr int kRuns = DepShared<NC>::kCap / kDT;  // runs per thread (nrun <= n <= kCap)
   find_runs(sh, n);
   const int nrun = sh.nrun;
-  float acc[kRuns][8];
+  float acc[kRuns][8][NC];
   int lcs[kRuns];
 #pragma unroll
   for (int q = 0; q < kRuns; ++q) {
     const int r = (int)threadIdx.x + q * kDT;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[q][k] = 0.0f;
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[q][k][c] = 0.0f;
     lcs[q] = -1;
     if (r < nrun) {
       const uint32_t j0 = sh.run[r], j1 = sh.run[r + 1];
       lcs[q] = (int)key_cell(sh.keys[j0]);
       for (uint32_t j = j0; j < j1; ++j) {
-        const uint32_t sl = key_slot(sh.keys[j]);
+        const uint64_t key = sh.keys[j];
+        const uint32_t sl = key_slot(key);
         const float f[3] = {sh.fx[sl], sh.fy[sl], sh.fz[sl]};
+        float m[NC];
+        if constexpr (NC == 1) {
+          m[0] = 1.0f;
+        } else {
+          const uint32_t id = key_id(key);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc[q][k] = __fadd_rn(acc[q][k], cic_weight(f, k));
+          for (int c = 0; c < NC; ++c) m[c] = wt[c * np3 + id];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float w = cic_weight(f, k);
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            acc[q][k][c] = __fadd_rn(acc[q][k][c], NC == 1 ? w : __fmul_rn(m[c], w));
+        }
       }
     }
   }
@@ -254,10 +283,12 @@ __device__ void accumulate_sorted(DepShared& sh, uint32_t n) {
 
 // A cell with more than kCap particles: its weights added in ascending id by
 // repeated workgroup-wide minimum search (slow; extreme clustering only).
-__device__ void accumulate_select(DepShared& sh, const float* __restrict__ disp,
+template <int NC>
+__device__ void accumulate_select(DepShared<NC>& sh, const float* __restrict__ disp,
                                   const uint32_t* __restrict__ perm, long np3, int np, int nm,
-                                  float dscale, const int t0[3], int lc_target) {
-  if (threadIdx.x < 8) sh.acc8[threadIdx.x] = 0.0f;
+                                  float dscale, const int t0[3], int lc_target,
+                                  const float* __restrict__ wt) {
+  if (threadIdx.x < 8 * NC) sh.acc8[threadIdx.x] = 0.0f;
   uint32_t last = 0;
   bool first = true;
   for (;;) {
@@ -288,7 +319,11 @@ __device__ void accumulate_select(DepShared& sh, const float* __restrict__ disp,
       int c[3];
       float f[3];
       home_cell(disp, np3, m, np, nm, dscale, c, f);
-      for (int k = 0; k < 8; ++k) sh.acc8[k] = __fadd_rn(sh.acc8[k], cic_weight(f, k));
+      for (int k = 0; k < 8; ++k) {
+        const float w = cic_weight(f, k);
+        for (int q = 0; q < NC; ++q)
+          sh.acc8[k * NC + q] = __fadd_rn(sh.acc8[k * NC + q], NC == 1 ? w : __fmul_rn(wt[q * np3 + m], w));
+      }
     }
     last = m;
     first = false;
@@ -296,17 +331,20 @@ __device__ void accumulate_select(DepShared& sh, const float* __restrict__ disp,
   }
 #pragma unroll
   for (int k = 7; k >= 0; --k) {
-    if (threadIdx.x == 0) add_partial(sh, lc_target, k, sh.acc8[k]);
+    if (threadIdx.x == 0) add_partial(sh, lc_target, k, &sh.acc8[k * NC]);
     __syncthreads();
   }
 }
 
+template <int NC>
 __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
                                                  const uint32_t* __restrict__ perm,
                                                  const uint32_t* __restrict__ off, int np, int nm,
                                                  float dscale, long np3, float* __restrict__ out,
-                                                 long row_stride, int contrast, float cinv) {
-  __shared__ DepShared sh;
+                                                 long row_stride, long mesh_stride, int contrast,
+                                                 float cinv, const float* __restrict__ wt) {
+  __shared__ DepShared<NC> sh;
+  constexpr uint32_t kCap = DepShared<NC>::kCap;
   const int nt = nm / kTile;
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
@@ -338,7 +376,9 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
     }
     for (; slot < nb * 4 + 4; ++slot) sh.seg_len[slot] = 0;
   }
-  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT) sh.rho[i] = 0.0f;
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sh.rho[q][i] = 0.0f;
   __syncthreads();
   if (threadIdx.x == 0) {
     int ns = 0;
@@ -353,29 +393,29 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   __syncthreads();
 
   uint32_t n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 0, 0);
-  if (n <= (uint32_t)kCap) {
+  if (n <= kCap) {
     if (n > 0) {
       sort_keys(sh, n);
-      accumulate_sorted(sh, n);
+      accumulate_sorted(sh, n, wt, np3);
     }
   } else {
     for (int slab = 0; slab < kReg; ++slab) {
       n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 1, slab);
       if (n == 0) continue;
-      if (n <= (uint32_t)kCap) {
+      if (n <= kCap) {
         sort_keys(sh, n);
-        accumulate_sorted(sh, n);
+        accumulate_sorted(sh, n, wt, np3);
         continue;
       }
       for (int cc = 0; cc < kReg * kReg; ++cc) {
         const int lc = slab * kReg * kReg + cc;
         n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 2, lc);
         if (n == 0) continue;
-        if (n <= (uint32_t)kCap) {
+        if (n <= kCap) {
           sort_keys(sh, n);
-          accumulate_sorted(sh, n);
+          accumulate_sorted(sh, n, wt, np3);
         } else {
-          accumulate_select(sh, disp, perm, np3, np, nm, dscale, t0, lc);
+          accumulate_select(sh, disp, perm, np3, np, nm, dscale, t0, lc, wt);
         }
       }
     }
@@ -383,9 +423,12 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
 
   for (int nn = threadIdx.x; nn < kTile * kTile * kTile; nn += kDT) {
     const int nx = nn / (kTile * kTile), ny = (nn / kTile) % kTile, nz = nn % kTile;
-    const float rho = sh.rho[nn];
-    const float val = contrast ? __fsub_rn(__fmul_rn(rho, cinv), 1.0f) : rho;
-    out[((long)(t0[0] + nx) * nm + (t0[1] + ny)) * row_stride + (t0[2] + nz)] = val;
+    const long o = ((long)(t0[0] + nx) * nm + (t0[1] + ny)) * row_stride + (t0[2] + nz);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const float rho = sh.rho[q][nn];
+      out[q * mesh_stride + o] = contrast ? __fsub_rn(__fmul_rn(rho, cinv), 1.0f) : rho;
+    }
   }
 }
 
@@ -395,8 +438,18 @@ void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off
   const int nt = nm / kTile;
   const long ntiles = (long)nt * nt * nt;
   const float cinv = (float)((double)nm * nm * nm / (double)np3);
-  hipLaunchKernelGGL(k_deposit, dim3((unsigned)ntiles), dim3(kDT), 0, s, disp, perm, off, np, nm,
-                     dscale, np3, out, row_stride, contrast, cinv);
+  hipLaunchKernelGGL(k_deposit<1>, dim3((unsigned)ntiles), dim3(kDT), 0, s, disp, perm, off, np, nm,
+                     dscale, np3, out, row_stride, 0L, contrast, cinv, nullptr);
+}
+
+void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,
+                              int nm, const float* wt, float* out, long row_stride,
+                              long mesh_stride_floats, hipStream_t s) {
+  const long np3 = (long)np * np * np;
+  const int nt = nm / kTile;
+  const long ntiles = (long)nt * nt * nt;
+  hipLaunchKernelGGL(k_deposit<3>, dim3((unsigned)ntiles), dim3(kDT), 0, s, disp, perm, off, np, nm,
+                     1.0f, np3, out, row_stride, mesh_stride_floats, 0, 1.0f, wt);
 }
 
 }  // namespace cola

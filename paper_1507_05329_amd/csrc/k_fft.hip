@@ -423,6 +423,79 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
   }
 }
 
+// x pass of a spectral combination: out = IDFT_x[ sum_q m_q(k) DFT_x(in_q) ]
+// for inputs already transformed along z and y (so m_q sees the full k).
+// m_q is the gradient (i n_d scale / |n|^2) or Hessian (n_a n_b scale / |n|^2)
+// multiplier, optionally times the amplitude table; accumulate adds the result
+// to out instead of overwriting it.  Used by the adjoint (transposed Green's
+// function and transposed 2LPT maps).
+template <int N>
+__global__ __launch_bounds__(cols_threads(N, X_FWD)) void k_combine(
+    const float2* __restrict__ in0, const float2* __restrict__ in1, const float2* __restrict__ in2,
+    float2* out, ColGeom g, const float2* __restrict__ tw, CombineSpec cs,
+    const float* __restrict__ amp) {
+  constexpr int W = cols_w(N), LD = N + 1, T = cols_threads(N, X_FWD);
+  constexpr int E = (W * N + T - 1) / T;
+  __shared__ float2 lds[W * LD];
+  __shared__ float2 twl[N / 2];
+  const uint32_t nblk = (uint32_t)g.nchunk * g.nplanes;
+  const uint32_t bid = xcd_remap(blockIdx.x, nblk);
+  const int p = bid / g.nchunk;
+  const int c0 = (bid - p * g.nchunk) * W;
+  const int pfreq = signed_freq(p, N);
+  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
+  float2 acc[E];
+#pragma unroll
+  for (int b = 0; b < E; ++b) acc[b] = make_float2(0.f, 0.f);
+  const float2* ins[3] = {in0, in1, in2};
+  for (int q = 0; q < cs.nin; ++q) {
+    const float2* src = ins[q] + p * g.plane_stride + c0;
+    for (int i = threadIdx.x; i < N * W; i += T) {
+      const int e = i / W, c = i - e * W;
+      lds[c * LD + e] = src[e * g.elem_stride + c];
+    }
+    __syncthreads();
+    lds_fft<N, W, LD, T, 1, 1>(lds, twl);
+#pragma unroll
+    for (int b = 0; b < E; ++b) {
+      const int i = threadIdx.x + b * T;
+      if ((W * N) % T == 0 || i < N * W) {
+        const int c = i / N, e = i - c * N;
+        const int nx = signed_freq(e, N), nz = c0 + c;
+        float2 m = multiplier(cs.kind[q], cs.green, cs.ca[q], cs.cb[q], cs.scale, nx, pfreq, nz, N,
+                              amp, 0);
+        if (cs.use_amp) {
+          const float2 a = multiplier(0, 0, 0, 0, 0.f, nx, pfreq, nz, N, amp, 1);
+          m = make_float2(m.x * a.x, m.y * a.x);
+        }
+        acc[b] = cadd(acc[b], cmul(m, lds[c * LD + e]));
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < E; ++b) {
+    const int i = threadIdx.x + b * T;
+    if ((W * N) % T == 0 || i < N * W) {
+      const int c = i / N, e = i - c * N;
+      lds[c * LD + e] = acc[b];
+    }
+  }
+  __syncthreads();
+  lds_fft<N, W, LD, T, 1, 0>(lds, twl);
+  float2* dst = out + p * g.plane_stride + c0;
+  for (int i = threadIdx.x; i < N * W; i += T) {
+    const int e = i / W, c = i - e * W;
+    const float2 v = lds[c * LD + e];
+    if (cs.accumulate) {
+      const float2 o = dst[e * g.elem_stride + c];
+      dst[e * g.elem_stride + c] = cadd(o, v);
+    } else {
+      dst[e * g.elem_stride + c] = v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -537,6 +610,28 @@ void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s) {
   float2* outs[3] = {a.out[0], a.out[1], a.out[2]};
   switch (n) {
 #define X(NN) case NN: cols_n<NN>(a.mode, 0, a.in, outs, 1, 0, tw.get(NN), a.mult, a.comp_a, a.comp_b, a.scale, a.amp, s); break;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: break;
+  }
+}
+
+namespace {
+template <int N>
+void combine_n(const float2* const in[3], float2* out, const CombineSpec& cs, const float* amp,
+               const float2* tw, hipStream_t s) {
+  constexpr int W = cols_w(N);
+  const ColGeom g = geom(N, W, 0);
+  dim3 grid((unsigned)(g.nchunk * g.nplanes), 1);
+  hipLaunchKernelGGL(k_combine<N>, grid, dim3(cols_threads(N, X_FWD)), 0, s, in[0], in[1], in[2], out,
+                     g, tw, cs, amp);
+}
+}  // namespace
+
+void fft_combine_x(const float2* const in[3], float2* out, int n, const CombineSpec& cs,
+                   const float* amp, const TwiddleSet& tw, hipStream_t s) {
+  switch (n) {
+#define X(NN) case NN: combine_n<NN>(in, out, cs, amp, tw.get(NN), s); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;

@@ -125,6 +125,30 @@ class ColaSim:
     def fft3d(self, mesh: torch.Tensor, n: int, inverse=False):
         self._chk(self.lib.cola_fft3d(self.ctx, n, _ptr(mesh), int(inverse)), "fft3d")
 
+    # -- adjoint (reverse mode) -------------------------------------------
+    def step_adjoint(self, a0, a1, a_v0, disp0, dbar, vbar, psi1bar, psi2bar):
+        """Cotangents (dbar, vbar) at a1 -> at a0 in place; psi bars accumulate."""
+        self._chk(self.lib.cola_step_adjoint(self.ctx, a0, a1, a_v0, _ptr(disp0), _ptr(dbar), _ptr(vbar),
+                                             _ptr(psi1bar), _ptr(psi2bar)), "step_adjoint")
+
+    def density_adjoint(self, disp, delta_bar, dbar):
+        """dbar += d<delta_bar, density(disp)>/d disp."""
+        self._chk(self.lib.cola_density_adjoint(self.ctx, _ptr(disp), _ptr(delta_bar), _ptr(dbar)),
+                  "density_adjoint")
+
+    def pk_adjoint(self, disp, edges, cbar, dbar, ngrid=None):
+        """dbar += d(sum_b cbar_b P_b)/d disp."""
+        edges = np.ascontiguousarray(edges, np.float64)
+        cbar = np.ascontiguousarray(cbar, np.float64)
+        self._chk(self.lib.cola_pk_adjoint(self.ctx, _ptr(disp), ngrid or self.nmesh, dptr(edges),
+                                           len(edges) - 1, dptr(cbar), _ptr(dbar)), "pk_adjoint")
+
+    def init_adjoint(self, noise, dbar0, psi1bar, psi2bar):
+        out = torch.empty_like(noise)
+        self._chk(self.lib.cola_init_2lpt_adjoint(self.ctx, _ptr(noise), _ptr(dbar0), _ptr(psi1bar),
+                                                  _ptr(psi2bar), _ptr(out)), "init_2lpt_adjoint")
+        return out
+
     def stage_times(self):
         """Per-stage (ms total, launches) since the last call (needs COLA_F_STAGE_TIMERS)."""
         ms = np.zeros(len(_lib.STAGES))

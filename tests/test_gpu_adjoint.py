@@ -1,0 +1,170 @@
+"""GPU adjoint against the FP64 oracle adjoint (finite-difference configuration
+16^3 particles / 32^3 mesh / 37.5 Mpc/h and the 32^3 / 64^3 small run)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint, cola, ic, pk, pm  # noqa: E402
+from paper_1507_05329_amd.inputs import bbks_table, seeded_normal, step_edges, white_noise  # noqa: E402
+
+NP, NM, L = 16, 32, 37.5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cosine(a, b):
+    return float(np.sum(a * b) / np.linalg.norm(a) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def table():
+    return bbks_table()
+
+
+@pytest.fixture(scope="module")
+def sim():
+    from paper_1507_05329_amd.sim import ColaSim
+    say("[gpu] adjoint ColaSim 16^3/32^3")
+    s = ColaSim(NP, NM, L)
+    yield s
+    s.close()
+
+
+def state_at(sim, table, nsteps):
+    w = white_noise(4, NP)
+    sim.init_from_noise(dev(w), *table)
+    e = step_edges()
+    for i in range(nsteps):
+        sim.step(e[i], e[i + 1])
+    st = sim.get_state()
+    return w, e, st
+
+
+def oracle_state(st):
+    s = L / NM
+    return cola.State(NP, NM, L, 0.27, -2.5, ic.lattice(NP, L), host(st["disp"]) * s, host(st["vres"]) * s,
+                      host(st["psi1"]) * s, host(st["psi2"]) * s, st["a_x"], st["a_v"])
+
+
+def test_step_adjoint_matches_oracle(sim, table):
+    say("[gpu] step adjoint")
+    _, e, st = state_at(sim, table, 3)
+    rng = np.random.default_rng(0)
+    db, vb = rng.standard_normal((2, 3, NP ** 3)).astype(np.float32)
+    o = oracle_state(st)
+    s = L / NM  # cotangents of mesh-unit quantities = Mpc/h cotangents * dx
+    od, ov, o1, o2 = adjoint.step_adjoint(o, e[4], db / s, vb / s)
+    dbar, vbar = dev(db), dev(vb)
+    p1, p2 = torch.zeros_like(dbar), torch.zeros_like(dbar)
+    sim.step_adjoint(e[3], e[4], st["a_v"], st["disp"], dbar, vbar, p1, p2)
+    for got, ref, name in ((dbar, od * s, "dbar"), (vbar, ov * s, "vbar"), (p1, o1 * s, "psi1bar"),
+                           (p2, o2 * s, "psi2bar")):
+        err = rel_l2(host(got), ref)
+        say(f"[gpu]   {name} rel-L2 {err:.2e}")
+        assert err < 1e-4 and cosine(host(got), ref) > 0.99999
+
+
+def test_density_adjoint_matches_oracle(sim, table):
+    _, _, st = state_at(sim, table, 10)
+    db = seeded_normal(3, (NM,) * 3)
+    out = torch.zeros_like(st["disp"])
+    sim.density_adjoint(st["disp"], dev(db), out)
+    pos = ic.lattice(NP, L) + host(st["disp"]) * (L / NM)
+    ref = adjoint.density_adjoint(pos, NM, L, db.astype(np.float64)) * (L / NM)
+    assert rel_l2(host(out), ref) < 1e-5
+
+
+def test_pk_adjoint_matches_oracle(sim, table):
+    _, _, st = state_at(sim, table, 10)
+    edges = pk.log_edges(L, NM, 8)
+    cb = np.random.default_rng(1).standard_normal(8)
+    out = torch.zeros_like(st["disp"])
+    sim.pk_adjoint(st["disp"], edges, cb, out)
+    pos = ic.lattice(NP, L) + host(st["disp"]) * (L / NM)
+    ref = adjoint.pk_adjoint(pos, L, NM, edges, cb) * (L / NM)
+    err = rel_l2(host(out), ref)
+    say(f"[gpu] pk adjoint rel-L2 {err:.2e}")
+    assert err < 1e-4
+
+
+def test_ic_adjoint_matches_oracle(sim, table):
+    w = white_noise(6, NP)
+    sim.init_from_noise(dev(w), *table)
+    rng = np.random.default_rng(2)
+    d0, p1, p2 = rng.standard_normal((3, 3, NP ** 3)).astype(np.float32)
+    got = sim.init_adjoint(dev(w), dev(d0), dev(p1), dev(p2))
+    s = L / NM
+    from oracle import cosmology as cosmo
+    ref = adjoint.ic_adjoint(w.astype(np.float64), L, *table,
+                             (p1 + cosmo.growth_D1(0.02, 0.27) * d0) / s,
+                             (p2 + cosmo.growth_D2(0.02, 0.27) * d0) / s)
+    err = rel_l2(host(got).ravel(), ref.ravel())
+    say(f"[gpu] IC adjoint rel-L2 {err:.2e}")
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("segment", [1, 4])
+def test_autograd_noise_gradient_matches_oracle(sim, table, segment):
+    # Differentiable configuration: loss = sum (delta_final - delta_target)^2,
+    # gradient w.r.t. the white noise, FD copy size.
+    from paper_1507_05329_amd.autograd import ColaDensity
+    say(f"[gpu] autograd run gradient, segment={segment}")
+    w = white_noise(4, NP)
+    target = seeded_normal(5, (NM,) * 3)
+    noise = dev(w).requires_grad_(True)
+    e = step_edges()
+    delta = ColaDensity.apply(noise, sim, *table, e, segment)
+    loss = ((delta - dev(target)) ** 2).sum()
+    loss.backward()
+    got = host(noise.grad)
+    s0 = cola.init_state(w.astype(np.float64), L, NM, *table)
+    cola.run(s0, e)
+    dref = pm.density_contrast(s0.positions(), NM, L)
+    dbar = adjoint.density_adjoint(s0.positions(), NM, L, 2.0 * (dref - target))
+    ref, _ = adjoint.run_adjoint(w.astype(np.float64), L, NM, *table, e, dbar)
+    err, cs = rel_l2(got.ravel(), ref.ravel()), cosine(got.ravel(), ref.ravel())
+    say(f"[gpu] noise gradient rel-L2 {err:.2e} cosine {cs:.6f}")
+    assert err < 1e-3 and cs > 0.9999
+
+
+def test_autograd_pk_gradient_matches_oracle(table):
+    from paper_1507_05329_amd.autograd import ColaPowerSpectrum
+    from paper_1507_05329_amd.sim import ColaSim
+    np_, nm, box = 32, 64, 100.0
+    s = ColaSim(np_, nm, box)
+    w = white_noise(5, np_)
+    e = step_edges()
+    kedges = pk.log_edges(box, nm, 10)
+    cb = seeded_normal(5, (10,)).astype(np.float64)
+    noise = dev(w).requires_grad_(True)
+    p = ColaPowerSpectrum.apply(noise, s, *table, e, kedges, None, 2)
+    (p * torch.from_numpy(cb)).sum().backward()
+    got = host(noise.grad)
+    s0 = cola.init_state(w.astype(np.float64), box, nm, *table)
+    cola.run(s0, e)
+    dbar = adjoint.pk_adjoint(s0.positions(), box, nm, kedges, cb)
+    ref, _ = adjoint.run_adjoint(w.astype(np.float64), box, nm, *table, e, dbar)
+    err, cs = rel_l2(got.ravel(), ref.ravel()), cosine(got.ravel(), ref.ravel())
+    say(f"[gpu] P(k) noise gradient rel-L2 {err:.2e} cosine {cs:.6f}")
+    s.close()
+    assert err < 1e-3 and cs > 0.9999
