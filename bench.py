@@ -49,6 +49,59 @@ def stage_bytes(np_side: int, nm: int) -> dict:
     }
 
 
+def batch_leg(steps, table, dev):
+    """The 96-mock uneven ensemble (32 x 48^3/96^3, 32 x 64^3/128^3,
+    32 x 96^3/192^3 particles/mesh, boxes 150/200/300 Mpc/h, distinct seeds):
+    K batched steps (one graph per step) against the same mocks stepped one
+    by one with plain contexts."""
+    import torch
+    from paper_1507_05329_amd.inputs import batch_configs, step_edges
+    from paper_1507_05329_amd.sim import ColaBatch, ColaSim
+    cfgs = batch_configs()
+    e = step_edges()
+    n_part = sum(c.n_particles for c in cfgs)
+    b = ColaBatch([dict(np=c.np_side, nmesh=c.nmesh, box=c.box) for c in cfgs], device=dev)
+    for m, c in zip(b.mocks, cfgs):
+        m.init_2lpt(c.seed, *table)
+    b.step(e[0], e[1])                      # warm-up; captures the graph
+    for m, c in zip(b.mocks, cfgs):
+        m.init_2lpt(c.seed, *table)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        b.step(e[i], e[i + 1])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    del b
+    sims = {}
+    t_seq = 0.0
+    for c in cfgs:
+        key = (c.np_side, c.nmesh, c.box)
+        if key not in sims:
+            sims[key] = ColaSim(c.np_side, c.nmesh, c.box, device=dev)
+            sims[key].init_2lpt(c.seed, *table)
+            sims[key].step(e[0], e[1])      # warm-up of this size
+        s = sims[key]
+        s.init_2lpt(c.seed, *table)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s.step(e[i], e[i + 1])
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+    for s in sims.values():
+        s.close()
+    return {"workload": "96 mocks: 32 x 48^3/96^3 (150 Mpc/h), 32 x 64^3/128^3 (200), "
+                        "32 x 96^3/192^3 (300), distinct seeds",
+            "mocks": len(cfgs), "particles": n_part, "steps": steps,
+            "value": n_part * steps / t_batch, "unit": "particle-updates/s",
+            "ms_per_step": t_batch / steps * 1e3,
+            "sequential_value": n_part * steps / t_seq,
+            "sequential_ms_per_step": t_seq / steps * 1e3,
+            "speedup": t_seq / t_batch}
+
+
 def cpu_baseline(cfg, table, seed):
     """One oracle step of the same workload on the host (FP64, NumPy/SciPy)."""
     from oracle import cola
@@ -73,6 +126,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="production")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (for HBM counter "
                          "calibration under rocprofv3) and exit")
@@ -123,6 +177,25 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = dt / args.steps * 1e3
     value = cfg.n_particles * args.steps / dt
+
+    # adjoint: reverse the same K steps from their stored start positions
+    sim.init_2lpt(cfg.seed, *table)
+    starts = []
+    for i in range(args.steps):
+        st = sim.get_state()
+        starts.append((st["disp"], st["a_v"]))
+        sim.step(e[i], e[i + 1])
+    dbar = torch.randn_like(starts[0][0])
+    vbar = torch.zeros_like(dbar)
+    p1b, p2b = torch.zeros_like(dbar), torch.zeros_like(dbar)
+    sim.step_adjoint(e[args.steps - 1], e[args.steps], starts[-1][1], starts[-1][0], dbar, vbar, p1b, p2b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in reversed(range(args.steps)):
+        sim.step_adjoint(e[i], e[i + 1], starts[i][1], starts[i][0], dbar, vbar, p1b, p2b)
+    torch.cuda.synchronize()
+    ms_adj = (time.perf_counter() - t0) / args.steps * 1e3
+    del starts
     sim.close()
     del sim
 
@@ -151,12 +224,16 @@ def main():
                 "step_bytes_alg": step_bytes,
                 "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    batched = None
+    if not args.no_batch:
+        batched = batch_leg(args.steps, bbks_table(), dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, table, cfg.seed)
 
     out = {
-        "metric": "particle-updates/s per COLA PM step (fwd)",
+        "metric": "particle-updates/s per COLA PM step (fwd; fwd+adjoint in fwd_adjoint)",
         "value": value,
         "unit": "particle-updates/s",
         "n_gpus": 1,
@@ -170,6 +247,10 @@ def main():
         "data": "synthetic (BBKS Gaussian random field, GPU Philox seed %d)" % cfg.seed,
         "config": {"workload": cfg.name, "np": cfg.np_side, "nmesh": cfg.nmesh, "box": cfg.box,
                    "nstep": cfg.nstep, "a": [cfg.a_init, cfg.a_final]},
+        "fwd_adjoint": {"value": cfg.n_particles / ((ms_step + ms_adj) * 1e-3),
+                        "unit": "particle-updates/s", "ms_adjoint_step": ms_adj,
+                        "adjoint_over_forward": ms_adj / ms_step},
+        "batched": batched,
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,

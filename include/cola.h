@@ -205,6 +205,49 @@ int cola_synchronize(cola_ctx* ctx);
 const char* cola_strerror(int code);
 const char* cola_last_error(const cola_ctx* ctx);
 
+/* ---- Batches of independent realisations (many mocks, e.g. the ensembles
+ * behind the covariance matrices of Sec. 3; the batching itself is this
+ * library's, not the paper's).
+ *
+ * A batch holds nmock contexts, one per entry of params[] (np and nmesh may
+ * differ between mocks).  Mocks that share (np, nmesh, omega_m, n_lpt,
+ * a_init) form a group whose workspaces sit at one fixed stride, so that
+ * every kernel of the step covers the whole group in one launch; box may
+ * differ within a group (the step works in mesh units).  The step launches
+ * of all groups are captured once, at the first cola_batch_step, into one
+ * HIP graph that reads the per-step scalars from device memory; every later
+ * step writes those scalars (one small kernel per group) and launches the
+ * graph.  A batched step runs the same kernels in the same order on the same
+ * data as cola_step on each mock alone, so its results are bitwise equal. */
+typedef struct cola_batch cola_batch;
+
+/* Workspace bytes for the batch (sum of the mocks' workspaces, 256-byte
+ * aligned each).  Errors as cola_workspace_query for any entry. */
+int cola_batch_workspace_query(const cola_params* params, int32_t nmock, size_t* bytes);
+
+/* Creates the batch in the caller's device workspace (256-byte aligned,
+ * >= the query; COLA_ENOMEM if smaller) on hip_stream.  The mocks'
+ * contexts are owned by the batch: use them through cola_batch_mock for
+ * initial conditions, outputs and single steps, never cola_destroy them.
+ * COLA_F_STAGE_TIMERS is refused (COLA_EINVAL): events are not captured. */
+int cola_batch_create(const cola_params* params, int32_t nmock, void* dev_workspace, size_t bytes,
+                      void* hip_stream, cola_batch** out);
+int cola_batch_destroy(cola_batch* batch);
+int32_t cola_batch_size(const cola_batch* batch);     /* number of mocks           */
+int32_t cola_batch_ngroups(const cola_batch* batch);  /* number of equal-size groups */
+/* Context of mock i (caller's order), or NULL when i is out of range. */
+cola_ctx* cola_batch_mock(cola_batch* batch, int32_t i);
+/* enable = 0: enqueue the step's launches directly instead of the graph
+ * (same kernels, same results; used to check graph replays). */
+int cola_batch_set_graph(cola_batch* batch, int32_t enable);
+/* One COLA step a0 -> a1 of every mock.  Every mock must hold a state at
+ * a_x = a0 (COLA_ESTATE otherwise) and the mocks of a group must share
+ * their velocity time a_v.  Asynchronous unless COLA_F_CHECK_FINITE is set
+ * for a mock. */
+int cola_batch_step(cola_batch* batch, double a0, double a1);
+int cola_batch_synchronize(cola_batch* batch);
+const char* cola_batch_last_error(const cola_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

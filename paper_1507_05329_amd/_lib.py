@@ -58,6 +58,16 @@ _SIGS = {
     "cola_pk_adjoint": (C.c_int, [_P, _P, _I, _DP, _I, _DP, _P]),
     "cola_init_2lpt_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "cola_synchronize": (C.c_int, [_P]),
+    "cola_batch_workspace_query": (C.c_int, [C.POINTER(cola_params), _I, C.POINTER(C.c_size_t)]),
+    "cola_batch_create": (C.c_int, [C.POINTER(cola_params), _I, _P, C.c_size_t, _P, C.POINTER(_P)]),
+    "cola_batch_destroy": (C.c_int, [_P]),
+    "cola_batch_size": (_I, [_P]),
+    "cola_batch_ngroups": (_I, [_P]),
+    "cola_batch_mock": (_P, [_P, _I]),
+    "cola_batch_set_graph": (C.c_int, [_P, _I]),
+    "cola_batch_step": (C.c_int, [_P, _D, _D]),
+    "cola_batch_synchronize": (C.c_int, [_P]),
+    "cola_batch_last_error": (C.c_char_p, [_P]),
     "cola_strerror": (C.c_char_p, [C.c_int]),
     "cola_last_error": (C.c_char_p, [_P]),
 }
@@ -95,10 +105,13 @@ class ColaError(RuntimeError):
         self.code = code
 
 
-def check(code, ctx=None, what=""):
+def check(code, ctx=None, what="", batch=None):
     if code != COLA_OK:
         lib = load()
-        detail = lib.cola_last_error(ctx).decode() if ctx else ""
+        if batch:
+            detail = lib.cola_batch_last_error(batch).decode()
+        else:
+            detail = lib.cola_last_error(ctx).decode() if ctx else ""
         raise ColaError(code, f"{what}: {lib.cola_strerror(code).decode()} {detail}".strip())
     return code
 

@@ -56,7 +56,7 @@ int hip_fail(cola_ctx* c, hipError_t e, const char* where) {
 
 struct Layout {
   size_t disp, vres, psi1, psi2, pkey, prank, perm, counts, offsets, scan, mesh, tw, amp,
-      pk_partial, pk_out, pk_edges, flag, fbar, pk_cbar, total;
+      pk_partial, pk_out, pk_edges, flag, fbar, pk_cbar, coef, total;
   long nbucket, mesh_stride, mesh_region, amp_len;
   int tw_cap;
 };
@@ -103,6 +103,7 @@ Layout layout(const cola_params* p) {
   L.flag = take(sizeof(uint32_t) * 64);
   L.fbar = take(3 * np3 * sizeof(float));
   L.pk_cbar = take((size_t)kMaxBins * sizeof(double));
+  L.coef = take(sizeof(StepCoef));
   L.total = o;
   return L;
 }
@@ -158,38 +159,46 @@ struct StageTimer {
 
 float2* ic_buf(cola_ctx* c, int i) { return c->meshbase + (size_t)i * mesh_complex_count(c->p.np); }
 
-// Tile sort of the current positions on an ng^3 grid.
-void tile_sort(cola_ctx* c, int ng, const float* disp) {
+// Tile sort of the current positions on an ng^3 grid.  Batched form: nmock
+// contexts with identical layouts, mock b's workspace at byte offset b * mstride.
+void tile_sort(cola_ctx* c, int ng, const float* disp, int nmock = 1, long mstride = 0) {
   StageTimer t(c, COLA_STAGE_SORT);
   const float dscale = (float)((double)ng / (double)c->p.nmesh);
   const long nt = ng / 16;
   const long nb = 8 * nt * nt * nt;
-  launch_fill_u32(c->counts, nb + 1, 0u, c->stream);
-  launch_bin_count(disp, c->p.np, ng, dscale, c->counts, c->pkey, c->prank, c->stream);
-  launch_exclusive_scan(c->counts, c->offsets, nb, c->scan_scratch, c->stream);
-  launch_scatter(c->pkey, c->prank, c->offsets, c->np3, c->perm, c->stream);
+  launch_fill_u32(c->counts, nb + 1, 0u, c->stream, nmock, mstride);
+  launch_bin_count(disp, c->p.np, ng, dscale, c->counts, c->pkey, c->prank, c->stream, nmock, mstride);
+  launch_exclusive_scan(c->counts, c->offsets, nb, c->scan_scratch, c->stream, nmock, mstride);
+  launch_scatter(c->pkey, c->prank, c->offsets, c->np3, c->perm, c->stream, nmock, mstride);
 }
 
-void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast, const float* disp) {
+void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast, const float* disp,
+             int nmock = 1, long mstride = 0) {
   const float dscale = (float)((double)ng / (double)c->p.nmesh);
-  tile_sort(c, ng, disp);
+  tile_sort(c, ng, disp, nmock, mstride);
   StageTimer t(c, COLA_STAGE_DEPOSIT);
   launch_deposit(disp, c->perm, c->offsets, c->p.np, ng, dscale, out, row_stride, contrast,
-                 c->stream);
+                 c->stream, nmock, mstride);
 }
 
-// Deposit + FFT + Green x ik + inverse FFTs: the three force meshes in c->mesh[0..2].
-void force_meshes(cola_ctx* c, double alpha, const float* disp) {
+// Green's function scale: g_d = IDFT[i n_d gscale / |n|^2 DFT(delta)] in mesh
+// units, gscale = alpha nm / (2 pi nm^3).
+double green_scale(int nm, double alpha) { return alpha * nm / (2.0 * kPi) / ((double)nm * nm * nm); }
+
+// Deposit + FFT + Green x ik + inverse FFTs: the three force meshes in
+// c->mesh[0..2].  The Green scale is read from the device coefficients
+// c->coef (set by set_coef before this call).
+void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 0) {
   const int nm = c->p.nmesh;
   const long rs = 2 * padded_cols(nm);
-  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1, disp);
+  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1, disp, nmock, mstride);
   {
     StageTimer t(c, COLA_STAGE_FFT_Z);
-    fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream);
+    fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream, nmock, mstride);
   }
   {
     StageTimer t(c, COLA_STAGE_FFT_Y);
-    fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream);
+    fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream, nmock, mstride);
   }
   XPassArgs a;
   a.in = c->mesh[0];
@@ -197,20 +206,32 @@ void force_meshes(cola_ctx* c, double alpha, const float* disp) {
   a.out[1] = c->mesh[1];
   a.out[2] = c->mesh[2];
   a.mode = X_FWD_GREEN3;
-  // g_d = IDFT[i n_d alpha nm / (2 pi |n|^2) DFT(delta)] / nm^3, in mesh units.
-  a.scale = (float)(alpha * nm / (2.0 * kPi) / ((double)nm * nm * nm));
+  a.coef = c->coef;
+  a.nmock = nmock;
+  a.mstride = mstride;
   {
     StageTimer t(c, COLA_STAGE_FFT_X);
     fft_x(a, nm, c->tw, c->stream);
   }
   {
     StageTimer t(c, COLA_STAGE_IFFT_Y);
-    fft_y(c->mesh[0], nm, 3, c->mesh_stride, 1, c->tw, c->stream);
+    fft_y(c->mesh[0], nm, 3, c->mesh_stride, 1, c->tw, c->stream, nmock, mstride);
   }
   {
     StageTimer t(c, COLA_STAGE_IFFT_Z);
-    fft_c2r_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream);
+    fft_c2r_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream, nmock, mstride);
   }
+}
+
+// The whole PM step on the device (no host decisions, no host reads): the
+// sequence a batch captures into one graph.  Uses the coefficients in c->coef.
+void step_launches(cola_ctx* c, int nmock, long mstride) {
+  force_meshes(c, c->disp, nmock, mstride);
+  const long rs = 2 * padded_cols(c->p.nmesh);
+  StageTimer t(c, COLA_STAGE_KICKDRIFT);
+  launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
+                            reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
+                            c->psi2, c->p.np, c->p.nmesh, c->coef, nullptr, c->stream, nmock, mstride);
 }
 
 bool same_a(double a, double b) { return std::fabs(a - b) <= 1e-12 * (std::fabs(a) > 1 ? std::fabs(a) : 1.0); }
@@ -230,6 +251,21 @@ void step_scalars(const cola_params* p, double a_x, double a_v, double a1, doubl
   o[7] = ah;
   o[8] = d1b;
   o[9] = d2b;
+}
+
+// Device coefficients of the step a_x -> a1 (velocity at a_v); s[10] as step_scalars.
+StepCoef make_coef(const cola_params* p, double a_x, double a_v, double a1, double* s) {
+  step_scalars(p, a_x, a_v, a1, s);
+  const double alpha = s[0], D1 = s[1], D2 = s[2], K = s[5], I = s[6];
+  StepCoef v{};
+  v.kd.K = (float)K;
+  v.kd.c1 = (float)(K * alpha * D1);
+  v.kd.c2 = (float)(K * alpha * (D2 - D1 * D1));
+  v.kd.I = (float)I;
+  v.kd.e1 = (float)s[3];
+  v.kd.e2 = (float)s[4];
+  v.gscale = (float)green_scale(p->nmesh, alpha);
+  return v;
 }
 
 int check_finite(cola_ctx* c) {
@@ -392,6 +428,7 @@ int cola_create(const cola_params* p, void* ws, size_t bytes, void* stream, cola
   c->flag = (uint32_t*)(c->ws + L.flag);
   c->fbar = (float*)(c->ws + L.fbar);
   c->pk_cbar = (double*)(c->ws + L.pk_cbar);
+  c->coef = (StepCoef*)(c->ws + L.coef);
   int r = ensure_twiddles(c, p->nmesh);
   if (r == COLA_OK) r = ensure_twiddles(c, p->np);
   if (r != COLA_OK) {
@@ -445,23 +482,8 @@ int cola_step(cola_ctx* c, double a0, double a1) {
   if (!same_a(a0, c->a_x)) return fail(c, COLA_ESTATE, "a0 differs from the current position time");
   if (!(a1 > a0) || !std::isfinite(a1)) return fail(c, COLA_EINVAL, "a1 must exceed a0");
   double s[10];
-  step_scalars(&c->p, c->a_x, c->a_v, a1, s);
-  const double alpha = s[0], D1 = s[1], D2 = s[2], K = s[5], I = s[6];
-  KickDrift kd;
-  kd.K = (float)K;
-  kd.c1 = (float)(K * alpha * D1);
-  kd.c2 = (float)(K * alpha * (D2 - D1 * D1));
-  kd.I = (float)I;
-  kd.e1 = (float)s[3];
-  kd.e2 = (float)s[4];
-  force_meshes(c, alpha, c->disp);
-  const long rs = 2 * padded_cols(c->p.nmesh);
-  {
-    StageTimer t(c, COLA_STAGE_KICKDRIFT);
-    launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
-                              reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
-                              c->psi2, c->p.np, c->p.nmesh, kd, nullptr, c->stream);
-  }
+  launch_set_coef(c->coef, make_coef(&c->p, c->a_x, c->a_v, a1, s), 1, 0, c->stream);
+  step_launches(c, 1, 0);
   LAUNCH_CHECK(c, "cola_step");
   c->a_v = s[7];
   c->a_x = a1;
@@ -471,13 +493,14 @@ int cola_step(cola_ctx* c, double a0, double a1) {
 int cola_force(cola_ctx* c, float* out) {
   if (!c || !out) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
-  const double alpha = 1.5 * c->p.omega_m / c->a_x;
-  force_meshes(c, alpha, c->disp);
-  KickDrift kd{};
+  StepCoef v{};
+  v.gscale = (float)green_scale(c->p.nmesh, 1.5 * c->p.omega_m / c->a_x);
+  launch_set_coef(c->coef, v, 1, 0, c->stream);
+  force_meshes(c, c->disp);
   const long rs = 2 * padded_cols(c->p.nmesh);
   launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
                             reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
-                            c->psi2, c->p.np, c->p.nmesh, kd, out, c->stream);
+                            c->psi2, c->p.np, c->p.nmesh, c->coef, out, c->stream);
   LAUNCH_CHECK(c, "cola_force");
   return COLA_OK;
 }
@@ -570,19 +593,14 @@ int cola_step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const floa
   if (!(a0 > 0) || !(a1 > a0) || !(a_v0 > 0) || !std::isfinite(a1))
     return fail(c, COLA_EINVAL, "scale factors must satisfy 0 < a0 < a1, a_v0 > 0");
   double s[10];
-  step_scalars(&c->p, a0, a_v0, a1, s);
-  const double alpha = s[0], D1 = s[1], D2 = s[2], K = s[5], I = s[6];
-  KickDrift kd;
-  kd.K = (float)K;
-  kd.c1 = (float)(K * alpha * D1);
-  kd.c2 = (float)(K * alpha * (D2 - D1 * D1));
-  kd.I = (float)I;
-  kd.e1 = (float)s[3];
-  kd.e2 = (float)s[4];
+  const StepCoef coef = make_coef(&c->p, a0, a_v0, a1, s);
+  const KickDrift kd = coef.kd;
+  const double alpha = s[0];
   const int np = c->p.np, nm = c->p.nmesh;
   const long rs = 2 * padded_cols(nm);
   // forward force meshes at the checkpointed positions (also sorts them)
-  force_meshes(c, alpha, disp0);
+  launch_set_coef(c->coef, coef, 1, 0, c->stream);
+  force_meshes(c, disp0);
   float* g[3];
   for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<float*>(c->mesh[d]);
   // reverse kick/drift and the readout weight gradient; Fbar -> c->fbar
@@ -597,7 +615,7 @@ int cola_step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const floa
   CombineSpec cs;
   cs.nin = 3;
   cs.green = 1;
-  const double gscale = alpha * nm / (2.0 * kPi) / ((double)nm * nm * nm);
+  const double gscale = green_scale(nm, alpha);
   const double cratio = (double)nm * nm * nm / (double)c->np3;
   cs.scale = (float)(-gscale * cratio);
   const float2* ins[3] = {c->mesh[0], c->mesh[1], c->mesh[2]};
@@ -795,5 +813,248 @@ const char* cola_strerror(int code) {
 }
 
 const char* cola_last_error(const cola_ctx* c) { return c ? c->err.c_str() : ""; }
+
+// ---------------------------------------------------------------------------
+// Batches of independent realisations.
+//
+// Mocks with equal (np, nmesh, omega_m, n_lpt, a_init) form a group; the
+// contexts of a group sit at a fixed byte stride in the workspace, so each
+// launch of the step covers the whole group (grid z = mock) and a group costs
+// the same kernel launches as one mock.  The launches of all groups are
+// captured once into a HIP graph that reads the per-step scalars from device
+// memory, so a step is one small coefficient write per group plus one graph
+// launch.
+
+}  // extern "C"
+
+struct cola_batch {
+  struct Group {
+    std::vector<int> idx;   // caller's mock indices, workspace order
+    long mstride = 0;
+    cola_ctx* first = nullptr;
+  };
+  hipStream_t stream = nullptr;     // caller's stream
+  hipStream_t cap = nullptr;        // capture stream
+  std::vector<cola_ctx*> mocks;     // caller's order
+  std::vector<Group> groups;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int use_graph = 1;
+  std::string err;
+};
+
+namespace {
+
+bool same_group(const cola_params& a, const cola_params& b) {
+  return a.np == b.np && a.nmesh == b.nmesh && a.omega_m == b.omega_m && a.n_lpt == b.n_lpt &&
+         a.a_init == b.a_init;
+}
+
+// Groups in first-appearance order; returns the workspace layout.
+size_t batch_plan(const cola_params* p, int n, std::vector<cola_batch::Group>* groups,
+                  std::vector<size_t>* offset) {
+  groups->clear();
+  offset->assign(n, 0);
+  std::vector<int> gid(n, -1);
+  std::vector<cola_params> key;
+  for (int i = 0; i < n; ++i) {
+    for (size_t g = 0; g < key.size(); ++g)
+      if (same_group(key[g], p[i])) { gid[i] = (int)g; break; }
+    if (gid[i] < 0) {
+      gid[i] = (int)key.size();
+      key.push_back(p[i]);
+      groups->emplace_back();
+    }
+    (*groups)[gid[i]].idx.push_back(i);
+  }
+  size_t o = 0;
+  for (size_t g = 0; g < groups->size(); ++g) {
+    cola_batch::Group& G = (*groups)[g];
+    G.mstride = (long)align256(layout(&p[G.idx[0]]).total);
+    for (int i : G.idx) {
+      (*offset)[i] = o;
+      o += (size_t)G.mstride;
+    }
+  }
+  return o;
+}
+
+int batch_fail(cola_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+void batch_free(cola_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->cap) hipStreamDestroy(b->cap);
+  for (cola_ctx* c : b->mocks)
+    if (c) cola_destroy(c);
+  delete b;
+}
+
+void enqueue_batch_step(cola_batch* b, hipStream_t s) {
+  for (cola_batch::Group& G : b->groups) {
+    cola_ctx* c = G.first;
+    const hipStream_t keep = c->stream;
+    c->stream = s;
+    step_launches(c, (int)G.idx.size(), G.mstride);
+    c->stream = keep;
+  }
+}
+
+// Captures the step launches of every group into one graph on the capture stream.
+int build_graph(cola_batch* b) {
+  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return batch_fail(b, COLA_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
+  enqueue_batch_step(b, b->cap);
+  const hipError_t el = hipGetLastError();
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap, &g);
+  if (el != hipSuccess || e != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return batch_fail(b, COLA_EHIP, std::string("capture: ") + hipGetErrorString(el != hipSuccess ? el : e));
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return batch_fail(b, COLA_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+  }
+  b->graph = g;
+  b->exec = x;
+  return COLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cola_batch_workspace_query(const cola_params* params, int32_t nmock, size_t* bytes) {
+  if (!params || nmock < 1 || !bytes) return COLA_EINVAL;
+  for (int i = 0; i < nmock; ++i) {
+    const int v = validate(&params[i]);
+    if (v != COLA_OK) return v;
+  }
+  std::vector<cola_batch::Group> groups;
+  std::vector<size_t> off;
+  *bytes = batch_plan(params, nmock, &groups, &off);
+  return COLA_OK;
+}
+
+int cola_batch_create(const cola_params* params, int32_t nmock, void* ws, size_t bytes, void* stream,
+                      cola_batch** out) {
+  if (!out) return COLA_EINVAL;
+  *out = nullptr;
+  if (!params || nmock < 1) return COLA_EINVAL;
+  for (int i = 0; i < nmock; ++i) {
+    const int v = validate(&params[i]);
+    if (v != COLA_OK) return v;
+    if (params[i].flags & COLA_F_STAGE_TIMERS) return COLA_EINVAL;  // events do not go into graphs
+  }
+  if (!ws || ((uintptr_t)ws & 255)) return COLA_EINVAL;
+  cola_batch* b = new (std::nothrow) cola_batch();
+  if (!b) return COLA_ENOMEM;
+  std::vector<size_t> off;
+  const size_t need = batch_plan(params, nmock, &b->groups, &off);
+  if (bytes < need) {
+    delete b;
+    return COLA_ENOMEM;
+  }
+  b->stream = (hipStream_t)stream;
+  b->mocks.assign(nmock, nullptr);
+  for (int i = 0; i < nmock; ++i) {
+    const size_t sz = layout(&params[i]).total;
+    const int r = cola_create(&params[i], (char*)ws + off[i], sz, stream, &b->mocks[i]);
+    if (r != COLA_OK) {
+      batch_free(b);
+      return r;
+    }
+  }
+  for (cola_batch::Group& G : b->groups) G.first = b->mocks[G.idx[0]];
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    b->cap = nullptr;
+    b->use_graph = 0;
+  }
+  *out = b;
+  return COLA_OK;
+}
+
+int cola_batch_destroy(cola_batch* b) {
+  if (!b) return COLA_EINVAL;
+  batch_free(b);
+  return COLA_OK;
+}
+
+int32_t cola_batch_size(const cola_batch* b) { return b ? (int32_t)b->mocks.size() : 0; }
+
+int32_t cola_batch_ngroups(const cola_batch* b) { return b ? (int32_t)b->groups.size() : 0; }
+
+cola_ctx* cola_batch_mock(cola_batch* b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->mocks.size()) return nullptr;
+  return b->mocks[i];
+}
+
+int cola_batch_set_graph(cola_batch* b, int32_t enable) {
+  if (!b) return COLA_EINVAL;
+  if (enable && !b->cap) return batch_fail(b, COLA_EHIP, "no capture stream");
+  b->use_graph = enable ? 1 : 0;
+  return COLA_OK;
+}
+
+int cola_batch_step(cola_batch* b, double a0, double a1) {
+  if (!b) return COLA_EINVAL;
+  if (!(a1 > a0) || !std::isfinite(a1)) return batch_fail(b, COLA_EINVAL, "a1 must exceed a0");
+  for (cola_ctx* c : b->mocks) {
+    if (!c->have_state) return batch_fail(b, COLA_ESTATE, "a mock has no initial conditions");
+    if (!same_a(a0, c->a_x)) return batch_fail(b, COLA_ESTATE, "a0 differs from a mock's position time");
+  }
+  for (cola_batch::Group& G : b->groups) {
+    const cola_ctx* c0 = G.first;
+    for (int i : G.idx)
+      if (!same_a(b->mocks[i]->a_v, c0->a_v))
+        return batch_fail(b, COLA_ESTATE, "mocks of a group must share the velocity time");
+  }
+  double s[10];
+  for (cola_batch::Group& G : b->groups) {
+    cola_ctx* c = G.first;
+    launch_set_coef(c->coef, make_coef(&c->p, c->a_x, c->a_v, a1, s), (int)G.idx.size(), G.mstride,
+                    b->stream);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return batch_fail(b, COLA_EHIP, std::string("coefficients: ") + hipGetErrorString(e));
+  if (b->use_graph) {
+    if (!b->exec) {
+      const int r = build_graph(b);
+      if (r != COLA_OK) return r;
+    }
+    e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) return batch_fail(b, COLA_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+  } else {
+    enqueue_batch_step(b, b->stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return batch_fail(b, COLA_EHIP, std::string("batch step: ") + hipGetErrorString(e));
+  }
+  for (cola_ctx* c : b->mocks) {
+    step_scalars(&c->p, c->a_x, c->a_v, a1, s);
+    c->a_v = s[7];
+    c->a_x = a1;
+  }
+  for (cola_ctx* c : b->mocks) {
+    const int r = check_finite(c);
+    if (r != COLA_OK) return batch_fail(b, r, c->err);
+  }
+  return COLA_OK;
+}
+
+int cola_batch_synchronize(cola_batch* b) {
+  if (!b) return COLA_EINVAL;
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return batch_fail(b, COLA_EHIP, hipGetErrorString(e));
+  return COLA_OK;
+}
+
+const char* cola_batch_last_error(const cola_batch* b) { return b ? b->err.c_str() : ""; }
+
 
 }  // extern "C"

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace cola {
 
@@ -65,6 +66,15 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
   if (xcd < full) base = xcd * per;
   else base = full * per + (xcd - full) * (per - 1);
   return base + local;
+}
+
+// Mock index of a batched launch is blockIdx.z; every per-mock array of a
+// batch sits at the same offset inside equal per-mock workspace blocks, so a
+// single byte stride locates mock b's copy of any array.
+template <class T>
+__device__ __forceinline__ T* mock_ptr(T* p, long mstride) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (long)blockIdx.z * mstride);
 }
 
 }  // namespace cola

@@ -49,21 +49,34 @@ double interp_pk(double k, const double* kt, const double* pt, int nk);
 // ---------------------------------------------------------------------------
 // Kernel launchers (all asynchronous on `s`).
 // Tile sort of particles by the 8^3 tile of their home cell (k_sort.hip).
-void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
+// Batched launches: nmock mocks, arrays of mock b at byte offset b * mstride.
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, int nmock = 1, long mstride = 0);
 void launch_bin_count(const float* disp, int np, int nm, float dscale, uint32_t* counts,
-                      uint32_t* pkey, uint32_t* prank, hipStream_t s);
+                      uint32_t* pkey, uint32_t* prank, hipStream_t s, int nmock = 1, long mstride = 0);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, long n,
-                           uint32_t* scratch, hipStream_t s);
+                           uint32_t* scratch, hipStream_t s, int nmock = 1, long mstride = 0);
 void launch_scatter(const uint32_t* pkey, const uint32_t* prank, const uint32_t* off,
-                    long np3, uint32_t* perm, hipStream_t s);
+                    long np3, uint32_t* perm, hipStream_t s, int nmock = 1, long mstride = 0);
 // Deterministic CIC gather (k_deposit.hip).
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off,
                     int np, int nm, float dscale, float* out, long row_stride, int contrast,
-                    hipStream_t s);
+                    hipStream_t s, int nmock = 1, long mstride = 0);
 // Three weighted deposits at once (readout transpose): out[q] += sum_p wt[q][p] w_s(p).
 void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,
                               int nm, const float* wt, float* out, long row_stride,
                               long mesh_stride_floats, hipStream_t s);
+// Per-step scalars of the kick/drift and the Green pass.
+struct KickDrift {
+  float K, c1, c2;     // v += K F - c1 Psi1 - c2 Psi2
+  float I, e1, e2;     // d += I v + e1 Psi1 + e2 Psi2
+};
+// Per-step scalars read by the step kernels from device memory (so a
+// captured graph of the step stays valid from step to step).
+struct StepCoef {
+  KickDrift kd;
+  float gscale;        // Green's function scale alpha nm / (2 pi nm^3)
+  float pad;
+};
 // FFT passes (k_fft.hip).
 enum XMode { X_FWD = 0, X_FWD_GREEN3 = 1, X_FWD_AMP = 2, X_MULT_INV = 3, X_INV = 4 };
 enum MultKind { M_NONE = 0, M_GRAD = 1, M_HESS = 2 };
@@ -75,6 +88,9 @@ struct XPassArgs {
   int comp_a = 0, comp_b = 0;   // gradient axis / Hessian axes
   float scale = 1.f;            // multiplier scale
   const float* amp = nullptr;   // amplitude by integer |n|^2 (X_FWD_AMP)
+  const StepCoef* coef = nullptr;  // X_FWD_GREEN3: scale read from coef->gscale
+  int nmock = 1;                // batched mocks (blockIdx.z) ...
+  long mstride = 0;             // ... at this byte stride
 };
 // Spectral combination pass (adjoint): out = IDFT_x[sum_q m_q DFT_x(in_q)].
 struct CombineSpec {
@@ -90,20 +106,20 @@ void fft_combine_x(const float2* const in[3], float2* out, int n, const CombineS
                    const float* amp, const TwiddleSet& tw, hipStream_t s);
 void fft3d_forward(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
 void fft3d_inverse(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
-void fft_r2c_z(float2* mesh, int n, int nplanes_mesh, long mesh_stride, const TwiddleSet& tw, hipStream_t s);
-void fft_c2r_z(float2* mesh, int n, int nmesh_batch, long mesh_stride, const TwiddleSet& tw, hipStream_t s);
+void fft_r2c_z(float2* mesh, int n, int nplanes_mesh, long mesh_stride, const TwiddleSet& tw,
+               hipStream_t s, int nmock = 1, long mstride = 0);
+void fft_c2r_z(float2* mesh, int n, int nmesh_batch, long mesh_stride, const TwiddleSet& tw,
+               hipStream_t s, int nmock = 1, long mstride = 0);
 void fft_y(float2* mesh, int n, int nmesh_batch, long mesh_stride, int inverse,
-           const TwiddleSet& tw, hipStream_t s);
+           const TwiddleSet& tw, hipStream_t s, int nmock = 1, long mstride = 0);
 void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s);
 // Force readout + kick/drift (k_particles.hip).
-struct KickDrift {
-  float K, c1, c2;     // v += K F - c1 Psi1 - c2 Psi2
-  float I, e1, e2;     // d += I v + e1 Psi1 + e2 Psi2
-};
+void launch_set_coef(StepCoef* dst, const StepCoef& v, int nmock, long mstride, hipStream_t s);
 void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2,
                                long row_stride, float* disp, float* vres,
                                const float* psi1, const float* psi2, int np, int nm,
-                               const KickDrift& kd, float* force_out, hipStream_t s);
+                               const StepCoef* coef, float* force_out, hipStream_t s,
+                               int nmock = 1, long mstride = 0);
 // Initial conditions (k_ic.hip).
 void launch_philox_noise(uint64_t seed, int np, float* out, long row_stride, hipStream_t s);
 void launch_copy_to_mesh(const float* src, int n, float* mesh, long row_stride, hipStream_t s);
@@ -175,6 +191,7 @@ struct cola_ctx {
   double* pk_edges = nullptr;
   uint32_t* flag = nullptr;
   float* fbar = nullptr;        // adjoint scratch, 3 * np3
+  cola::StepCoef* coef = nullptr;  // per-step scalars (device)
   double* pk_cbar = nullptr;    // P(k) loss cotangents (adjoint)
   // stage timers (COLA_F_STAGE_TIMERS): pairs of events per recorded stage
   std::vector<hipEvent_t> ev_pool;

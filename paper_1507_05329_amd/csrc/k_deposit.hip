@@ -342,8 +342,14 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
                                                  const uint32_t* __restrict__ off, int np, int nm,
                                                  float dscale, long np3, float* __restrict__ out,
                                                  long row_stride, long mesh_stride, int contrast,
-                                                 float cinv, const float* __restrict__ wt) {
+                                                 float cinv, const float* __restrict__ wt,
+                                                 long mstride) {
   __shared__ DepShared<NC> sh;
+  disp = mock_ptr(disp, mstride);
+  perm = mock_ptr(perm, mstride);
+  off = mock_ptr(off, mstride);
+  out = mock_ptr(out, mstride);
+  if (wt) wt = mock_ptr(wt, mstride);
   constexpr uint32_t kCap = DepShared<NC>::kCap;
   const int nt = nm / kTile;
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -433,13 +439,15 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
 }
 
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off, int np, int nm,
-                    float dscale, float* out, long row_stride, int contrast, hipStream_t s) {
+                    float dscale, float* out, long row_stride, int contrast, hipStream_t s,
+                    int nmock, long mstride) {
   const long np3 = (long)np * np * np;
   const int nt = nm / kTile;
   const long ntiles = (long)nt * nt * nt;
   const float cinv = (float)((double)nm * nm * nm / (double)np3);
-  hipLaunchKernelGGL(k_deposit<1>, dim3((unsigned)ntiles), dim3(kDT), 0, s, disp, perm, off, np, nm,
-                     dscale, np3, out, row_stride, 0L, contrast, cinv, nullptr);
+  hipLaunchKernelGGL(k_deposit<1>, dim3((unsigned)ntiles, 1, (unsigned)nmock), dim3(kDT), 0, s, disp,
+                     perm, off, np, nm, dscale, np3, out, row_stride, 0L, contrast, cinv, nullptr,
+                     mstride);
 }
 
 void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,
@@ -449,7 +457,7 @@ void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uin
   const int nt = nm / kTile;
   const long ntiles = (long)nt * nt * nt;
   hipLaunchKernelGGL(k_deposit<3>, dim3((unsigned)ntiles), dim3(kDT), 0, s, disp, perm, off, np, nm,
-                     1.0f, np3, out, row_stride, mesh_stride_floats, 0, 1.0f, wt);
+                     1.0f, np3, out, row_stride, mesh_stride_floats, 0, 1.0f, wt, 0L);
 }
 
 }  // namespace cola

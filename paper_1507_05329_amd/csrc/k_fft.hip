@@ -195,8 +195,10 @@ __device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* 
 // z pass: rows of N reals (row stride `cols` complex).  NL rows per workgroup.
 template <int N>
 __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z(
-    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw) {
+    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
+    long mstride) {
   constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
+  mesh = mock_ptr(mesh, mstride);
   __shared__ float2 lds[NL * LD];
   __shared__ float2 twl[N / 2];
   float2* base = mesh + blockIdx.y * mesh_stride;
@@ -228,8 +230,10 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z
 // Inverse z pass: half spectrum (H+1 values) -> N reals, unnormalised.
 template <int N>
 __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z(
-    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw) {
+    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
+    long mstride) {
   constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
+  mesh = mock_ptr(mesh, mstride);
   __shared__ float2 lds[NL * LD];
   __shared__ float2 twl[N / 2];
   float2* base = mesh + blockIdx.y * mesh_stride;
@@ -320,7 +324,15 @@ template <int N, int MODE>
 __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
     const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
     ColGeom g, const float2* __restrict__ tw, int mult, int ca, int cb, float scale,
-    const float* __restrict__ amp, int y_is_plane_freq) {
+    const float* __restrict__ amp, int y_is_plane_freq, const StepCoef* __restrict__ coef,
+    long mstride) {
+  in = mock_ptr(in, mstride);
+  out0 = mock_ptr(out0, mstride);
+  if constexpr (MODE == X_FWD_GREEN3) {
+    out1 = mock_ptr(out1, mstride);
+    out2 = mock_ptr(out2, mstride);
+    if (coef) scale = mock_ptr(coef, mstride)->gscale;
+  }
   constexpr int W = cols_w(N), LD = N + 1, T = cols_threads(N, MODE);
   constexpr int E = (W * N + T - 1) / T;
   __shared__ float2 lds[W * LD];
@@ -516,48 +528,53 @@ ColGeom geom(int n, int w, int axis) {
 }
 
 template <int N>
-void r2c_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s) {
+void r2c_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s, int nmock,
+           long mstride) {
   constexpr int NL = rows_nl(N / 2), T = threads_for(NL * (N / 2));
   const long nrows = (long)N * N;
-  dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch);
-  hipLaunchKernelGGL(k_r2c_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw);
+  dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch, (unsigned)nmock);
+  hipLaunchKernelGGL(k_r2c_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw,
+                     mstride);
 }
 
 template <int N>
-void c2r_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s) {
+void c2r_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s, int nmock,
+           long mstride) {
   constexpr int NL = rows_nl(N / 2), T = threads_for(NL * (N / 2));
   const long nrows = (long)N * N;
-  dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch);
-  hipLaunchKernelGGL(k_c2r_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw);
+  dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch, (unsigned)nmock);
+  hipLaunchKernelGGL(k_c2r_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw,
+                     mstride);
 }
 
 template <int N>
 void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbatch, long mesh_stride,
-            const float2* tw, int mult, int ca, int cb, float scale, const float* amp, hipStream_t s) {
+            const float2* tw, int mult, int ca, int cb, float scale, const float* amp, hipStream_t s,
+            const StepCoef* coef = nullptr, int nmock = 1, long mstride = 0) {
   constexpr int W = cols_w(N);
   const ColGeom g = geom(N, W, axis);
-  dim3 grid((unsigned)(g.nchunk * g.nplanes), (unsigned)nbatch);
+  dim3 grid((unsigned)(g.nchunk * g.nplanes), (unsigned)nbatch, (unsigned)nmock);
   const int yf = axis == 0 ? 1 : 0;
   switch (mode) {
     case X_FWD:
       hipLaunchKernelGGL((k_cols<N, X_FWD>), grid, dim3(cols_threads(N, X_FWD)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf);
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
       break;
     case X_INV:
       hipLaunchKernelGGL((k_cols<N, X_INV>), grid, dim3(cols_threads(N, X_INV)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf);
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
       break;
     case X_FWD_AMP:
       hipLaunchKernelGGL((k_cols<N, X_FWD_AMP>), grid, dim3(cols_threads(N, X_FWD_AMP)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, 0, 0, 0, 1.f, amp, yf);
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, amp, yf, nullptr, mstride);
       break;
     case X_MULT_INV:
       hipLaunchKernelGGL((k_cols<N, X_MULT_INV>), grid, dim3(cols_threads(N, X_MULT_INV)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, mult, ca, cb, scale, nullptr, yf);
+                         mesh_stride, g, tw, mult, ca, cb, scale, nullptr, yf, nullptr, mstride);
       break;
     case X_FWD_GREEN3:
       hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN3>), grid, dim3(cols_threads(N, X_FWD_GREEN3)), 0, s, in, out[0], out[1], out[2],
-                         mesh_stride, g, tw, M_GRAD, 0, 0, scale, nullptr, yf);
+                         mesh_stride, g, tw, M_GRAD, 0, 0, scale, nullptr, yf, coef, mstride);
       break;
   }
 }
@@ -576,18 +593,20 @@ bool fft_size_supported(int n) {
   }
 }
 
-void fft_r2c_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleSet& tw, hipStream_t s) {
+void fft_r2c_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleSet& tw, hipStream_t s,
+               int nmock, long mstride) {
   switch (n) {
-#define X(NN) case NN: r2c_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s); break;
+#define X(NN) case NN: r2c_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s, nmock, mstride); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;
   }
 }
 
-void fft_c2r_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleSet& tw, hipStream_t s) {
+void fft_c2r_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleSet& tw, hipStream_t s,
+               int nmock, long mstride) {
   switch (n) {
-#define X(NN) case NN: c2r_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s); break;
+#define X(NN) case NN: c2r_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s, nmock, mstride); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;
@@ -595,11 +614,11 @@ void fft_c2r_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleS
 }
 
 void fft_y(float2* mesh, int n, int nbatch, long mesh_stride, int inverse, const TwiddleSet& tw,
-           hipStream_t s) {
+           hipStream_t s, int nmock, long mstride) {
   float2* outs[3] = {mesh, nullptr, nullptr};
   const int mode = inverse ? X_INV : X_FWD;
   switch (n) {
-#define X(NN) case NN: cols_n<NN>(mode, 1, mesh, outs, nbatch, mesh_stride, tw.get(NN), 0, 0, 0, 1.f, nullptr, s); break;
+#define X(NN) case NN: cols_n<NN>(mode, 1, mesh, outs, nbatch, mesh_stride, tw.get(NN), 0, 0, 0, 1.f, nullptr, s, nullptr, nmock, mstride); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;
@@ -609,7 +628,7 @@ void fft_y(float2* mesh, int n, int nbatch, long mesh_stride, int inverse, const
 void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s) {
   float2* outs[3] = {a.out[0], a.out[1], a.out[2]};
   switch (n) {
-#define X(NN) case NN: cols_n<NN>(a.mode, 0, a.in, outs, 1, 0, tw.get(NN), a.mult, a.comp_a, a.comp_b, a.scale, a.amp, s); break;
+#define X(NN) case NN: cols_n<NN>(a.mode, 0, a.in, outs, 1, 0, tw.get(NN), a.mult, a.comp_a, a.comp_b, a.scale, a.amp, s, a.coef, a.nmock, a.mstride); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;

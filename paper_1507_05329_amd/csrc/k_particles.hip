@@ -17,9 +17,17 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
     const float* __restrict__ g0, const float* __restrict__ g1, const float* __restrict__ g2,
     long row_stride, float* __restrict__ disp, float* __restrict__ vres,
     const float* __restrict__ psi1, const float* __restrict__ psi2, int np, int nm, long np3,
-    KickDrift kd, float* __restrict__ force_out) {
+    const StepCoef* __restrict__ coef, float* __restrict__ force_out, long mstride) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= np3) return;
+  g0 = mock_ptr(g0, mstride);
+  g1 = mock_ptr(g1, mstride);
+  g2 = mock_ptr(g2, mstride);
+  disp = mock_ptr(disp, mstride);
+  vres = mock_ptr(vres, mstride);
+  psi1 = mock_ptr(psi1, mstride);
+  psi2 = mock_ptr(psi2, mstride);
+  if (force_out) force_out = mock_ptr(force_out, mstride);
   int c[3];
   float f[3];
   const float dscale = 1.0f;
@@ -43,6 +51,7 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
     for (int d = 0; d < 3; ++d) force_out[d * np3 + i] = F[d];
     return;
   }
+  const KickDrift kd = mock_ptr(coef, mstride)->kd;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const long j = d * np3 + i;
@@ -55,11 +64,18 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
 
 void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2, long row_stride,
                                float* disp, float* vres, const float* psi1, const float* psi2,
-                               int np, int nm, const KickDrift& kd, float* force_out,
-                               hipStream_t s) {
+                               int np, int nm, const StepCoef* coef, float* force_out,
+                               hipStream_t s, int nmock, long mstride) {
   const long np3 = (long)np * np * np;
-  hipLaunchKernelGGL(k_readout_kick_drift, dim3((unsigned)((np3 + 255) / 256)), dim3(256), 0, s,
-                     g0, g1, g2, row_stride, disp, vres, psi1, psi2, np, nm, np3, kd, force_out);
+  hipLaunchKernelGGL(k_readout_kick_drift, dim3((unsigned)((np3 + 255) / 256), 1, (unsigned)nmock),
+                     dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2, np, nm, np3, coef,
+                     force_out, mstride);
+}
+
+__global__ void k_set_coef(StepCoef* dst, StepCoef v, long mstride) { *mock_ptr(dst, mstride) = v; }
+
+void launch_set_coef(StepCoef* dst, const StepCoef& v, int nmock, long mstride, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_coef, dim3(1, 1, (unsigned)nmock), dim3(1), 0, s, dst, v, mstride);
 }
 
 __global__ void k_check_finite(const float* __restrict__ x, long n, uint32_t* flag) {

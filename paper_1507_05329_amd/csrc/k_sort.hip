@@ -6,22 +6,28 @@
 
 namespace cola {
 
-__global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v) {
+__global__ void k_fill_u32(uint32_t* __restrict__ p, long n, uint32_t v, long mstride) {
+  p = mock_ptr(p, mstride);
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     p[i] = v;
 }
 
-void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s) {
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s, int nmock, long mstride) {
   if (n <= 0) return;
   long blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks, 1, (unsigned)nmock), dim3(256), 0, s, p, n, v,
+                     mstride);
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ disp, int np, int nm,
                                                    float dscale, long np3, uint32_t* __restrict__ counts,
                                                    uint32_t* __restrict__ pkey,
-                                                   uint32_t* __restrict__ prank) {
+                                                   uint32_t* __restrict__ prank, long mstride) {
+  disp = mock_ptr(disp, mstride);
+  counts = mock_ptr(counts, mstride);
+  pkey = mock_ptr(pkey, mstride);
+  prank = mock_ptr(prank, mstride);
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= np3) return;  // np3 is a multiple of 64 for every supported size: whole waves exit
   int c[3];
@@ -48,10 +54,10 @@ __global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ dis
 }
 
 void launch_bin_count(const float* disp, int np, int nm, float dscale, uint32_t* counts,
-                      uint32_t* pkey, uint32_t* prank, hipStream_t s) {
+                      uint32_t* pkey, uint32_t* prank, hipStream_t s, int nmock, long mstride) {
   const long np3 = (long)np * np * np;
-  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((np3 + 255) / 256)), dim3(256), 0, s, disp, np,
-                     nm, dscale, np3, counts, pkey, prank);
+  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)((np3 + 255) / 256), 1, (unsigned)nmock), dim3(256), 0,
+                     s, disp, np, nm, dscale, np3, counts, pkey, prank, mstride);
 }
 
 // ---------------------------------------------------------------------------
@@ -78,8 +84,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 }
 
 __global__ __launch_bounds__(kScanT) void k_scan_reduce(const uint32_t* __restrict__ in, long n,
-                                                        uint32_t* __restrict__ bsum) {
+                                                        uint32_t* __restrict__ bsum, long mstride) {
   __shared__ uint32_t sh[kScanT];
+  in = mock_ptr(in, mstride);
+  bsum = mock_ptr(bsum, mstride);
   const long base = blockIdx.x * kScanChunk;
   uint32_t acc = 0;
   for (int j = 0; j < kScanPer; ++j) {
@@ -92,8 +100,10 @@ __global__ __launch_bounds__(kScanT) void k_scan_reduce(const uint32_t* __restri
 }
 
 // Scans nb <= kScanT*kScanPer*... block sums in place with one workgroup.
-__global__ __launch_bounds__(kScanT) void k_scan_blocksums(uint32_t* __restrict__ bsum, long nb) {
+__global__ __launch_bounds__(kScanT) void k_scan_blocksums(uint32_t* __restrict__ bsum, long nb,
+                                                           long mstride) {
   __shared__ uint32_t sh[kScanT];
+  bsum = mock_ptr(bsum, mstride);
   uint32_t carry = 0;
   for (long base = 0; base < nb; base += kScanT * (long)kScanPer) {
     uint32_t v[kScanPer];
@@ -116,8 +126,11 @@ __global__ __launch_bounds__(kScanT) void k_scan_blocksums(uint32_t* __restrict_
 
 __global__ __launch_bounds__(kScanT) void k_scan_apply(const uint32_t* __restrict__ in, long n,
                                                        const uint32_t* __restrict__ bsum,
-                                                       uint32_t* __restrict__ out) {
+                                                       uint32_t* __restrict__ out, long mstride) {
   __shared__ uint32_t sh[kScanT];
+  in = mock_ptr(in, mstride);
+  bsum = mock_ptr(bsum, mstride);
+  out = mock_ptr(out, mstride);
   const long base = blockIdx.x * kScanChunk + (long)threadIdx.x * kScanPer;
   uint32_t v[kScanPer];
   uint32_t loc = 0;
@@ -138,26 +151,32 @@ __global__ __launch_bounds__(kScanT) void k_scan_apply(const uint32_t* __restric
 }
 
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, long n, uint32_t* scratch,
-                           hipStream_t s) {
+                           hipStream_t s, int nmock, long mstride) {
   const long nb = (n + kScanChunk - 1) / kScanChunk;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanT), 0, s, in, n, scratch);
-  hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(kScanT), 0, s, scratch, nb);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanT), 0, s, in, n, scratch, out);
+  const unsigned z = (unsigned)nmock;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb, 1, z), dim3(kScanT), 0, s, in, n, scratch, mstride);
+  hipLaunchKernelGGL(k_scan_blocksums, dim3(1, 1, z), dim3(kScanT), 0, s, scratch, nb, mstride);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb, 1, z), dim3(kScanT), 0, s, in, n, scratch, out,
+                     mstride);
 }
 
 __global__ __launch_bounds__(256) void k_scatter(const uint32_t* __restrict__ pkey,
                                                  const uint32_t* __restrict__ prank,
                                                  const uint32_t* __restrict__ off, long np3,
-                                                 uint32_t* __restrict__ perm) {
+                                                 uint32_t* __restrict__ perm, long mstride) {
+  pkey = mock_ptr(pkey, mstride);
+  prank = mock_ptr(prank, mstride);
+  off = mock_ptr(off, mstride);
+  perm = mock_ptr(perm, mstride);
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= np3) return;
   perm[off[pkey[i]] + prank[i]] = (uint32_t)i;
 }
 
 void launch_scatter(const uint32_t* pkey, const uint32_t* prank, const uint32_t* off, long np3,
-                    uint32_t* perm, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((np3 + 255) / 256)), dim3(256), 0, s, pkey, prank,
-                     off, np3, perm);
+                    uint32_t* perm, hipStream_t s, int nmock, long mstride) {
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((np3 + 255) / 256), 1, (unsigned)nmock), dim3(256), 0, s,
+                     pkey, prank, off, np3, perm, mstride);
 }
 
 }  // namespace cola

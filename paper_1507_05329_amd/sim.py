@@ -19,6 +19,14 @@ def _ptr(t: torch.Tensor):
     return C.c_void_p(t.data_ptr())
 
 
+def make_params(np_side, nmesh, box, omega_m=0.27, n_lpt=-2.5, a_init=0.02, flags=0):
+    lib = _lib.load()
+    p = cola_params()
+    lib.cola_params_default(C.byref(p), np_side, nmesh, box)
+    p.omega_m, p.n_lpt, p.a_init, p.flags = omega_m, n_lpt, a_init, flags
+    return p
+
+
 class ColaSim:
     """One COLA realisation on one GPU.
 
@@ -29,9 +37,8 @@ class ColaSim:
     def __init__(self, np_side, nmesh, box, omega_m=0.27, n_lpt=-2.5, a_init=0.02,
                  flags=0, device="cuda", stream=None):
         self.lib = _lib.load()
-        p = cola_params()
-        self.lib.cola_params_default(C.byref(p), np_side, nmesh, box)
-        p.omega_m, p.n_lpt, p.a_init, p.flags = omega_m, n_lpt, a_init, flags
+        self._owned = True
+        p = make_params(np_side, nmesh, box, omega_m, n_lpt, a_init, flags)
         self.params = p
         nbytes = C.c_size_t()
         check(self.lib.cola_workspace_query(C.byref(p), C.byref(nbytes)), what="workspace_query")
@@ -46,10 +53,22 @@ class ColaSim:
         self.np_side, self.nmesh, self.box = np_side, nmesh, box
         self.n_particles = np_side ** 3
 
+    @classmethod
+    def _view(cls, lib, ctx, params, device, stream, owner):
+        """A context owned by a batch (not destroyed by close())."""
+        self = cls.__new__(cls)
+        self.lib, self.ctx, self.params = lib, C.c_void_p(ctx), params
+        self._owned = False
+        self._owner = owner
+        self.device, self.stream = device, stream
+        self.np_side, self.nmesh, self.box = params.np, params.nmesh, params.box
+        self.n_particles = params.np ** 3
+        return self
+
     def close(self):
-        if self.ctx:
+        if self.ctx and self._owned:
             self.lib.cola_destroy(self.ctx)
-            self.ctx = None
+        self.ctx = None
 
     def __del__(self):
         try:
@@ -159,6 +178,71 @@ class ColaSim:
 
     def synchronize(self):
         self._chk(self.lib.cola_synchronize(self.ctx), "synchronize")
+
+
+class ColaBatch:
+    """Many independent realisations stepped together (libcola batch).
+
+    ``specs`` is a list of dicts with keys np, nmesh, box and optionally
+    omega_m, n_lpt, a_init, flags.  ``mocks[i]`` is a ColaSim view of mock i
+    for initial conditions, outputs and single steps.
+    """
+
+    def __init__(self, specs, device="cuda", stream=None, graph=True):
+        self.lib = _lib.load()
+        n = len(specs)
+        arr = (cola_params * n)()
+        for i, sp in enumerate(specs):
+            arr[i] = make_params(sp["np"], sp["nmesh"], sp["box"], sp.get("omega_m", 0.27),
+                                 sp.get("n_lpt", -2.5), sp.get("a_init", 0.02), sp.get("flags", 0))
+        self.params = arr
+        nbytes = C.c_size_t()
+        check(self.lib.cola_batch_workspace_query(arr, n, C.byref(nbytes)), what="batch_workspace_query")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = C.c_void_p()
+        check(self.lib.cola_batch_create(arr, n, _ptr(self.workspace), nbytes.value,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(b)),
+              what="batch_create")
+        self.batch = b
+        self.mocks = [ColaSim._view(self.lib, self.lib.cola_batch_mock(b, i), arr[i], self.device,
+                                    self.stream, self) for i in range(n)]
+        self.set_graph(graph)
+
+    def __len__(self):
+        return len(self.mocks)
+
+    @property
+    def ngroups(self):
+        return int(self.lib.cola_batch_ngroups(self.batch))
+
+    def set_graph(self, enable: bool):
+        check(self.lib.cola_batch_set_graph(self.batch, int(bool(enable))), what="batch_set_graph",
+              batch=self.batch)
+
+    def step(self, a0: float, a1: float):
+        check(self.lib.cola_batch_step(self.batch, a0, a1), what="batch_step", batch=self.batch)
+
+    def run(self, edges):
+        for a0, a1 in zip(edges[:-1], edges[1:]):
+            self.step(a0, a1)
+
+    def synchronize(self):
+        check(self.lib.cola_batch_synchronize(self.batch), what="batch_synchronize", batch=self.batch)
+
+    def close(self):
+        if getattr(self, "batch", None):
+            for m in self.mocks:
+                m.ctx = None
+            self.lib.cola_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def padded_cols(n: int) -> int:

@@ -104,3 +104,54 @@ def test_strerror_codes():
     lib = _lib.load()
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.cola_strerror(code)
+
+
+def batch_params(specs):
+    lib = _lib.load()
+    arr = (_lib.cola_params * len(specs))()
+    for i, (n, m, box) in enumerate(specs):
+        lib.cola_params_default(C.byref(arr[i]), n, m, box)
+    return lib, arr
+
+
+def test_batch_workspace_is_sum_of_mock_workspaces():
+    specs = [(48, 96, 150.0), (64, 128, 200.0), (48, 96, 170.0), (96, 192, 300.0), (64, 128, 210.0)]
+    lib, arr = batch_params(specs)
+    total = C.c_size_t()
+    assert lib.cola_batch_workspace_query(arr, len(specs), C.byref(total)) == 0
+    want = 0
+    for i in range(len(specs)):
+        n = C.c_size_t()
+        assert lib.cola_workspace_query(C.byref(arr[i]), C.byref(n)) == 0
+        want += (n.value + 255) // 256 * 256
+    assert total.value == want
+    # the full 96-mock ensemble (32 mocks of each size) fits comfortably in HBM
+    from paper_1507_05329_amd.inputs import batch_configs
+    cfgs = batch_configs()
+    lib, arr = batch_params([(c.np_side, c.nmesh, c.box) for c in cfgs])
+    assert lib.cola_batch_workspace_query(arr, len(cfgs), C.byref(total)) == 0
+    assert len(cfgs) == 96 and total.value < 40e9
+
+
+def test_batch_create_validation_before_device_access():
+    lib, arr = batch_params([(32, 64, 100.0), (48, 96, 150.0)])
+    total = C.c_size_t()
+    assert lib.cola_batch_workspace_query(arr, 2, C.byref(total)) == 0
+    b = C.c_void_p()
+    assert lib.cola_batch_create(arr, 2, C.c_void_p(256), total.value - 1, None, C.byref(b)) == _lib.COLA_ENOMEM
+    assert lib.cola_batch_create(arr, 2, C.c_void_p(257), total.value, None, C.byref(b)) == _lib.COLA_EINVAL
+    assert lib.cola_batch_create(arr, 0, C.c_void_p(256), total.value, None, C.byref(b)) == _lib.COLA_EINVAL
+    arr[1].flags = _lib.COLA_F_STAGE_TIMERS
+    assert lib.cola_batch_create(arr, 2, C.c_void_p(256), total.value, None, C.byref(b)) == _lib.COLA_EINVAL
+    arr[1].flags = 0
+    arr[1].nmesh = 100
+    assert lib.cola_batch_workspace_query(arr, 2, C.byref(total)) == _lib.COLA_EUNSUPPORTED
+    assert lib.cola_batch_mock(None, 0) is None
+    assert lib.cola_batch_size(None) == 0
+
+
+def test_largest_single_gpu_workspace_fits_hbm():
+    lib, p = params(1024, 2048, 1200.0)
+    n = C.c_size_t()
+    assert lib.cola_workspace_query(C.byref(p), C.byref(n)) == 0
+    assert n.value < 250e9
