@@ -35,11 +35,17 @@ constexpr int radix_at(int n, int s) {
 constexpr int nstage(int n) { int s = 0; while (radix_at(n, s)) ++s; return s; }
 constexpr int ns_before(int n, int s) { int p = 1; for (int i = 0; i < s; ++i) p *= radix_at(n, i); return p; }
 
+// LDS line layout: element e of a line sits at pe(e) = e + e/32 (one pad
+// slot after every 32), so the stride-R writes of a Stockham stage spread
+// over the banks; lines are lds_ld(n) apart (odd, for the column loads).
+constexpr int lds_ld(int n) { return n + n / 32 + 1; }
+__device__ __forceinline__ int pe(int e) { return e + (e >> 5); }
+
 // Launch shapes: at most 80 KB of LDS per workgroup, 256 threads below
 // 8192 staged complex values, 512 at 8192.
 constexpr int kLdsLimit = 80 * 1024;
-constexpr int cols_w(int n) { int w = 16; while (w > 1 && w * (n + 1) * 8 + n * 4 > kLdsLimit) w /= 2; return w; }
-constexpr int rows_nl(int h) { int nl = 16; while (nl > 1 && nl * (h + 1) * 8 + h * 8 > kLdsLimit) nl /= 2; return nl; }
+constexpr int cols_w(int n) { int w = 16; while (w > 1 && w * lds_ld(n) * 8 + n * 4 > kLdsLimit) w /= 2; return w; }
+constexpr int rows_nl(int h) { int nl = 16; while (nl > 1 && nl * lds_ld(h) * 8 + h * 8 > kLdsLimit) nl /= 2; return nl; }
 constexpr int threads_for(int elems) { return elems >= 8192 ? 512 : 256; }
 // The fused Green's-function pass keeps the forward spectrum in registers
 // across its three inverse transforms: spread it over 512 threads.
@@ -142,7 +148,8 @@ __device__ __forceinline__ float2 tw_get(const float2* __restrict__ twl, int m) 
 // Stages S.. of a length-N transform of NL lines (line l at buf[l * LD]), T
 // threads, twiddle table stride TWS, FWD = 1 forward / 0 inverse.
 template <int N, int NL, int LD, int T, int TWS, int FWD, int S>
-__device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float2* __restrict__ tw,
+                                           int tid) {
   if constexpr (S < nstage(N)) {
     constexpr int R = radix_at(N, S), NS = ns_before(N, S);
     constexpr int NBL = N / R, NBF = NBL * NL, KB = (NBF + T - 1) / T;
@@ -151,12 +158,12 @@ __device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float
     float2 v[KB][R];
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
-      const int t = threadIdx.x + b * T;
+      const int t = tid + b * T;
       if (NBF % T == 0 || t < NBF) {
         const int l = t / NBL, j = t - l * NBL;
-        const float2* src = buf + l * LD + j;
+        const float2* src = buf + l * LD;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b][r] = src[r * NBL];
+        for (int r = 0; r < R; ++r) v[b][r] = src[pe(j + r * NBL)];
         if constexpr (NS > 1) {
           const int k = j % NS;
 #pragma unroll
@@ -172,23 +179,65 @@ __device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
-      const int t = threadIdx.x + b * T;
+      const int t = tid + b * T;
       if (NBF % T == 0 || t < NBF) {
         const int l = t / NBL, j = t - l * NBL;
         const int k = j % NS;
-        float2* dst = buf + l * LD + (j - k) * R + k;
+        float2* dst = buf + l * LD;
+        const int o = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[r * NS] = v[b][r];
+        for (int r = 0; r < R; ++r) dst[pe(o + r * NS)] = v[b][r];
       }
     }
     __syncthreads();
-    fft_stages<N, NL, LD, T, TWS, FWD, S + 1>(buf, tw);
+    fft_stages<N, NL, LD, T, TWS, FWD, S + 1>(buf, tw, tid);
   }
 }
 
+// tid: the thread's index (threadIdx.x; a caller inside a loop passes a
+// value the compiler cannot treat as loop-invariant, so that the stages'
+// address arithmetic is not hoisted out of the loop and kept live).
 template <int N, int NL, int LD, int T, int TWS, int FWD>
-__device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* __restrict__ tw) {
-  fft_stages<N, NL, LD, T, TWS, FWD, 0>(buf, tw);
+__device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* __restrict__ tw,
+                                        int tid = threadIdx.x) {
+  fft_stages<N, NL, LD, T, TWS, FWD, 0>(buf, tw, tid);
+}
+
+// Global -> LDS copies with every load of a thread issued before the first
+// LDS store, so each wave keeps all of its loads in flight.
+template <int NT, int T>
+__device__ __forceinline__ void load_twiddles(float2* __restrict__ twl, const float2* __restrict__ tw) {
+  constexpr int K = (NT + T - 1) / T;
+  float2 t[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const int i = threadIdx.x + b * T;
+    if (NT % T == 0 || i < NT) t[b] = tw[i];
+  }
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const int i = threadIdx.x + b * T;
+    if (NT % T == 0 || i < NT) twl[i] = t[b];
+  }
+}
+
+// W adjacent columns of N elements (element stride es) into LDS lines.
+template <int N, int W, int LD, int T>
+__device__ __forceinline__ void load_cols(float2* __restrict__ lds, const float2* __restrict__ src, long es) {
+  constexpr int K = (N * W + T - 1) / T;
+  float2 t[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const int i = threadIdx.x + b * T;
+    const int e = i / W, c = i - e * W;
+    if ((N * W) % T == 0 || i < N * W) t[b] = src[e * es + c];
+  }
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const int i = threadIdx.x + b * T;
+    const int e = i / W, c = i - e * W;
+    if ((N * W) % T == 0 || i < N * W) lds[c * LD + pe(e)] = t[b];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -197,16 +246,28 @@ template <int N>
 __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z(
     float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
     long mstride) {
-  constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
+  constexpr int H = N / 2, LD = lds_ld(H), NL = rows_nl(H), T = threads_for(NL * H);
+  constexpr int LE = (NL * H + T - 1) / T;
   mesh = mock_ptr(mesh, mstride);
   __shared__ float2 lds[NL * LD];
   __shared__ float2 twl[N / 2];
   float2* base = mesh + blockIdx.y * mesh_stride;
   const long r0 = (long)blockIdx.x * NL;
-  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
-  for (int i = threadIdx.x; i < NL * H; i += T) {
-    const int l = i / H, j = i - l * H;
-    if (r0 + l < nrows) lds[l * LD + j] = base[(r0 + l) * cols + j];
+  load_twiddles<N / 2, T>(twl, tw);
+  {
+    float2 t[LE];
+#pragma unroll
+    for (int b = 0; b < LE; ++b) {
+      const int i = threadIdx.x + b * T;
+      const int l = i / H, j = i - l * H;
+      if (((NL * H) % T == 0 || i < NL * H) && r0 + l < nrows) t[b] = base[(r0 + l) * cols + j];
+    }
+#pragma unroll
+    for (int b = 0; b < LE; ++b) {
+      const int i = threadIdx.x + b * T;
+      const int l = i / H, j = i - l * H;
+      if (((NL * H) % T == 0 || i < NL * H) && r0 + l < nrows) lds[l * LD + pe(j)] = t[b];
+    }
   }
   __syncthreads();
   lds_fft<H, NL, LD, T, 2, 1>(lds, twl);
@@ -216,8 +277,8 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z
     if (r0 + l >= nrows) continue;
     float2 x = make_float2(0.f, 0.f);
     if (k <= H) {
-      const float2 a = lds[l * LD + (k == H ? 0 : k)];
-      float2 b = lds[l * LD + (k == 0 ? 0 : H - k)];
+      const float2 a = lds[l * LD + pe(k == H ? 0 : k)];
+      float2 b = lds[l * LD + pe(k == 0 ? 0 : H - k)];
       b.y = -b.y;
       const float2 e = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
       const float2 o = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
@@ -232,16 +293,29 @@ template <int N>
 __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z(
     float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
     long mstride) {
-  constexpr int H = N / 2, LD = H + 1, NL = rows_nl(H), T = threads_for(NL * H);
+  constexpr int H = N / 2, LD = lds_ld(H), NL = rows_nl(H), T = threads_for(NL * H);
+  constexpr int NV = NL * (H + 1), LE = (NV + T - 1) / T;
   mesh = mock_ptr(mesh, mstride);
   __shared__ float2 lds[NL * LD];
   __shared__ float2 twl[N / 2];
   float2* base = mesh + blockIdx.y * mesh_stride;
   const long r0 = (long)blockIdx.x * NL;
-  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
-  for (int i = threadIdx.x; i < NL * (H + 1); i += T) {
-    const int l = i / (H + 1), j = i - l * (H + 1);
-    lds[l * LD + j] = r0 + l < nrows ? base[(r0 + l) * cols + j] : make_float2(0.f, 0.f);
+  load_twiddles<N / 2, T>(twl, tw);
+  {
+    float2 t[LE];
+#pragma unroll
+    for (int b = 0; b < LE; ++b) {
+      const int i = threadIdx.x + b * T;
+      const int l = i / (H + 1), j = i - l * (H + 1);
+      t[b] = make_float2(0.f, 0.f);
+      if ((NV % T == 0 || i < NV) && r0 + l < nrows) t[b] = base[(r0 + l) * cols + j];
+    }
+#pragma unroll
+    for (int b = 0; b < LE; ++b) {
+      const int i = threadIdx.x + b * T;
+      const int l = i / (H + 1), j = i - l * (H + 1);
+      if (NV % T == 0 || i < NV) lds[l * LD + pe(j)] = t[b];
+    }
   }
   __syncthreads();
   // Z'_k = (X_k + conj X_{h-k}) + i (X_k - conj X_{h-k}) exp(+2 pi i k / n), k < h.
@@ -250,7 +324,7 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z
   for (int i = threadIdx.x; i < NL * HP; i += T) {
     const int l = i / HP, k = i - l * HP;
     const int k2 = H - k;
-    const float2 xa = lds[l * LD + k], xb = lds[l * LD + k2];
+    const float2 xa = lds[l * LD + pe(k)], xb = lds[l * LD + pe(k2)];
     float2 za, zb;
     {
       const float2 cb = make_float2(xb.x, -xb.y);
@@ -268,14 +342,14 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z
       const float2 o = cmul(csub(xb, ca), w);
       zb = cadd(e, make_float2(-o.y, o.x));
     }
-    lds[l * LD + k] = za;
-    if (k2 != k && k2 != H) lds[l * LD + k2] = zb;
+    lds[l * LD + pe(k)] = za;
+    if (k2 != k && k2 != H) lds[l * LD + pe(k2)] = zb;
   }
   __syncthreads();
   lds_fft<H, NL, LD, T, 2, 0>(lds, twl);
   for (int i = threadIdx.x; i < NL * H; i += T) {
     const int l = i / H, j = i - l * H;
-    if (r0 + l < nrows) base[(r0 + l) * cols + j] = lds[l * LD + j];
+    if (r0 + l < nrows) base[(r0 + l) * cols + j] = lds[l * LD + pe(j)];
   }
 }
 
@@ -302,26 +376,27 @@ __device__ __forceinline__ float2 multiplier(int kind, int green, int ca, int cb
   const int n2 = nx * nx + ny * ny + nz * nz;
   if (n2 == 0) return make_float2(0.f, 0.f);
   const bool nyq = ax == h || ay == h || nz == h;
-  const int nv[3] = {nx, ny, nz};
   if (is_amp) {
     if (nyq) return make_float2(0.f, 0.f);
     return make_float2(amp[n2], 0.f);
   }
   if (kind == M_GRAD) {
-    const int na = nv[ca];
+    const int na = ca == 0 ? nx : (ca == 1 ? ny : nz);
     const int aa = na < 0 ? -na : na;
     if (green ? (aa == h) : nyq) return make_float2(0.f, 0.f);
     return make_float2(0.f, scale * (float)na / (float)n2);
   }
   if (kind == M_HESS) {
     if (nyq) return make_float2(0.f, 0.f);
-    return make_float2(scale * (float)nv[ca] * (float)nv[cb] / (float)n2, 0.f);
+    const int na = ca == 0 ? nx : (ca == 1 ? ny : nz);
+    const int nb = cb == 0 ? nx : (cb == 1 ? ny : nz);
+    return make_float2(scale * (float)na * (float)nb / (float)n2, 0.f);
   }
   return make_float2(1.f, 0.f);
 }
 
 template <int N, int MODE>
-__global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
+__global__ __launch_bounds__(cols_threads(N, MODE), MODE == X_FWD_GREEN3 ? 4 : 1) void k_cols(
     const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
     ColGeom g, const float2* __restrict__ tw, int mult, int ca, int cb, float scale,
     const float* __restrict__ amp, int y_is_plane_freq, const StepCoef* __restrict__ coef,
@@ -333,7 +408,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
     out2 = mock_ptr(out2, mstride);
     if (coef) scale = mock_ptr(coef, mstride)->gscale;
   }
-  constexpr int W = cols_w(N), LD = N + 1, T = cols_threads(N, MODE);
+  constexpr int W = cols_w(N), LD = lds_ld(N), T = cols_threads(N, MODE);
   constexpr int E = (W * N + T - 1) / T;
   __shared__ float2 lds[W * LD];
   __shared__ float2 twl[N / 2];
@@ -344,11 +419,8 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
   const long mofs = (long)blockIdx.y * mesh_stride;
   const float2* src = in + mofs + p * g.plane_stride + c0;
   // load: consecutive threads take consecutive columns
-  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
-  for (int i = threadIdx.x; i < N * W; i += T) {
-    const int e = i / W, c = i - e * W;
-    lds[c * LD + e] = src[e * g.elem_stride + c];
-  }
+  load_twiddles<N / 2, T>(twl, tw);
+  load_cols<N, W, LD, T>(lds, src, g.elem_stride);
   __syncthreads();
   const int pfreq = y_is_plane_freq ? signed_freq(p, N) : 0;
 
@@ -359,14 +431,14 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
     for (int i = threadIdx.x; i < N * W; i += T) {
       const int c = i / N, e = i - c * N;
       const float2 m = multiplier(0, 0, 0, 0, 0.f, signed_freq(e, N), pfreq, c0 + c, N, amp, 1);
-      lds[c * LD + e] = cmul(lds[c * LD + e], m);
+      lds[c * LD + pe(e)] = cmul(lds[c * LD + pe(e)], m);
     }
     __syncthreads();
   } else if constexpr (MODE == X_MULT_INV) {
     for (int i = threadIdx.x; i < N * W; i += T) {
       const int c = i / N, e = i - c * N;
       const float2 m = multiplier(mult, 0, ca, cb, scale, signed_freq(e, N), pfreq, c0 + c, N, amp, 0);
-      lds[c * LD + e] = cmul(lds[c * LD + e], m);
+      lds[c * LD + pe(e)] = cmul(lds[c * LD + pe(e)], m);
     }
     __syncthreads();
     lds_fft<N, W, LD, T, 1, 0>(lds, twl);
@@ -376,7 +448,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
     float2* dst = out0 + mofs + p * g.plane_stride + c0;
     for (int i = threadIdx.x; i < N * W; i += T) {
       const int e = i / W, c = i - e * W;
-      dst[e * g.elem_stride + c] = lds[c * LD + e];
+      dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
     }
   } else {
     // PM: forward along x gives S = DFT[delta]; with phi = scale S / |n|^2,
@@ -394,10 +466,10 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
         const int nx = signed_freq(e, N), nz = c0 + c;
         const int n2 = nx * nx + pfreq * pfreq + nz * nz;
         const float inv = (n2 == 0 || nz > N / 2) ? 0.f : scale / (float)n2;
-        const float2 v = lds[c * LD + e];
+        const float2 v = lds[c * LD + pe(e)];
         phi[b] = make_float2(inv * v.x, inv * v.y);
         const float kx = (nx == N / 2 || nx == -N / 2) ? 0.f : (float)nx;
-        lds[c * LD + e] = make_float2(-kx * phi[b].y, kx * phi[b].x);  // i n_x phi
+        lds[c * LD + pe(e)] = make_float2(-kx * phi[b].y, kx * phi[b].x);  // i n_x phi
       }
     }
     __syncthreads();
@@ -406,7 +478,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
       float2* dst = out0 + p * g.plane_stride + c0;
       for (int i = threadIdx.x; i < N * W; i += T) {
         const int e = i / W, c = i - e * W;
-        dst[e * g.elem_stride + c] = lds[c * LD + e];
+        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
       }
     }
     __syncthreads();
@@ -415,7 +487,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
       const int i = threadIdx.x + b * T;
       if ((W * N) % T == 0 || i < N * W) {
         const int c = i / N, e = i - c * N;
-        lds[c * LD + e] = phi[b];
+        lds[c * LD + pe(e)] = phi[b];
       }
     }
     __syncthreads();
@@ -427,7 +499,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
       for (int i = threadIdx.x; i < N * W; i += T) {
         const int e = i / W, c = i - e * W;
         const float kz = (c0 + c >= N / 2) ? 0.f : (float)(c0 + c);
-        const float2 v = lds[c * LD + e];
+        const float2 v = lds[c * LD + pe(e)];
         dy[e * g.elem_stride + c] = make_float2(-ky * v.y, ky * v.x);
         dz[e * g.elem_stride + c] = make_float2(-kz * v.y, kz * v.x);
       }
@@ -442,11 +514,13 @@ __global__ __launch_bounds__(cols_threads(N, MODE)) void k_cols(
 // to out instead of overwriting it.  Used by the adjoint (transposed Green's
 // function and transposed 2LPT maps).
 template <int N>
-__global__ __launch_bounds__(cols_threads(N, X_FWD)) void k_combine(
+__global__ __launch_bounds__(cols_threads(N, X_FWD_GREEN3)) void k_combine(
     const float2* __restrict__ in0, const float2* __restrict__ in1, const float2* __restrict__ in2,
     float2* out, ColGeom g, const float2* __restrict__ tw, CombineSpec cs,
     const float* __restrict__ amp) {
-  constexpr int W = cols_w(N), LD = N + 1, T = cols_threads(N, X_FWD);
+  // the accumulator lives in registers across the inputs: spread it over
+  // as many threads as the Green's-function pass
+  constexpr int W = cols_w(N), LD = lds_ld(N), T = cols_threads(N, X_FWD_GREEN3);
   constexpr int E = (W * N + T - 1) / T;
   __shared__ float2 lds[W * LD];
   __shared__ float2 twl[N / 2];
@@ -455,32 +529,54 @@ __global__ __launch_bounds__(cols_threads(N, X_FWD)) void k_combine(
   const int p = bid / g.nchunk;
   const int c0 = (bid - p * g.nchunk) * W;
   const int pfreq = signed_freq(p, N);
-  for (int i = threadIdx.x; i < N / 2; i += T) twl[i] = tw[i];
+  load_twiddles<N / 2, T>(twl, tw);
+  // per-element scale / |n|^2 (times the amplitude), shared by the inputs
   float2 acc[E];
+  float rw[E];
+  const int h = N / 2;
 #pragma unroll
-  for (int b = 0; b < E; ++b) acc[b] = make_float2(0.f, 0.f);
+  for (int b = 0; b < E; ++b) {
+    acc[b] = make_float2(0.f, 0.f);
+    rw[b] = 0.f;
+    const int i = threadIdx.x + b * T;
+    if ((W * N) % T == 0 || i < N * W) {
+      const int c = i / N, e = i - c * N;
+      const int nx = signed_freq(e, N), nz = c0 + c;
+      const int n2 = nx * nx + pfreq * pfreq + nz * nz;
+      const bool nyq = nx == h || nx == -h || pfreq == h || pfreq == -h || nz == h;
+      if (n2 != 0 && nz <= h && !(cs.use_amp && nyq))
+        rw[b] = cs.scale / (float)n2 * (cs.use_amp ? amp[n2] : 1.f);
+    }
+  }
   const float2* ins[3] = {in0, in1, in2};
+#pragma unroll 1
   for (int q = 0; q < cs.nin; ++q) {
     const float2* src = ins[q] + p * g.plane_stride + c0;
-    for (int i = threadIdx.x; i < N * W; i += T) {
-      const int e = i / W, c = i - e * W;
-      lds[c * LD + e] = src[e * g.elem_stride + c];
-    }
+    load_cols<N, W, LD, T>(lds, src, g.elem_stride);
     __syncthreads();
-    lds_fft<N, W, LD, T, 1, 1>(lds, twl);
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    lds_fft<N, W, LD, T, 1, 1>(lds, twl, tid);
+    const int kind = cs.kind[q], ca = cs.ca[q], cb = cs.cb[q];
 #pragma unroll
     for (int b = 0; b < E; ++b) {
       const int i = threadIdx.x + b * T;
       if ((W * N) % T == 0 || i < N * W) {
         const int c = i / N, e = i - c * N;
         const int nx = signed_freq(e, N), nz = c0 + c;
-        float2 m = multiplier(cs.kind[q], cs.green, cs.ca[q], cs.cb[q], cs.scale, nx, pfreq, nz, N,
-                              amp, 0);
-        if (cs.use_amp) {
-          const float2 a = multiplier(0, 0, 0, 0, 0.f, nx, pfreq, nz, N, amp, 1);
-          m = make_float2(m.x * a.x, m.y * a.x);
+        const int na = ca == 0 ? nx : (ca == 1 ? pfreq : nz);
+        const bool nyq = nx == h || nx == -h || pfreq == h || pfreq == -h || nz == h;
+        const float2 x = lds[c * LD + pe(e)];
+        if (kind == M_GRAD) {
+          // i n_a rw; zero on the axis' own Nyquist plane (Green) or any Nyquist index
+          const bool z = cs.green ? (na == h || na == -h) : nyq;
+          const float f = z ? 0.f : (float)na * rw[b];
+          acc[b] = cadd(acc[b], make_float2(-f * x.y, f * x.x));
+        } else {
+          const int nb = cb == 0 ? nx : (cb == 1 ? pfreq : nz);
+          const float f = nyq ? 0.f : (float)na * (float)nb * rw[b];
+          acc[b] = cadd(acc[b], make_float2(f * x.x, f * x.y));
         }
-        acc[b] = cadd(acc[b], cmul(m, lds[c * LD + e]));
       }
     }
     __syncthreads();
@@ -490,7 +586,7 @@ __global__ __launch_bounds__(cols_threads(N, X_FWD)) void k_combine(
     const int i = threadIdx.x + b * T;
     if ((W * N) % T == 0 || i < N * W) {
       const int c = i / N, e = i - c * N;
-      lds[c * LD + e] = acc[b];
+      lds[c * LD + pe(e)] = acc[b];
     }
   }
   __syncthreads();
@@ -498,7 +594,7 @@ __global__ __launch_bounds__(cols_threads(N, X_FWD)) void k_combine(
   float2* dst = out + p * g.plane_stride + c0;
   for (int i = threadIdx.x; i < N * W; i += T) {
     const int e = i / W, c = i - e * W;
-    const float2 v = lds[c * LD + e];
+    const float2 v = lds[c * LD + pe(e)];
     if (cs.accumulate) {
       const float2 o = dst[e * g.elem_stride + c];
       dst[e * g.elem_stride + c] = cadd(o, v);
@@ -642,7 +738,7 @@ void combine_n(const float2* const in[3], float2* out, const CombineSpec& cs, co
   constexpr int W = cols_w(N);
   const ColGeom g = geom(N, W, 0);
   dim3 grid((unsigned)(g.nchunk * g.nplanes), 1);
-  hipLaunchKernelGGL(k_combine<N>, grid, dim3(cols_threads(N, X_FWD)), 0, s, in[0], in[1], in[2], out,
+  hipLaunchKernelGGL(k_combine<N>, grid, dim3(cols_threads(N, X_FWD_GREEN3)), 0, s, in[0], in[1], in[2], out,
                      g, tw, cs, amp);
 }
 }  // namespace
