@@ -23,9 +23,9 @@ __device__ __forceinline__ void home_cell(const float* __restrict__ disp, long n
   const uint32_t li[3] = {id / (unp * unp), (id / unp) % unp, id % unp};
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const long t = (long)li[e] * nm;
-    const int qi = (int)(t / np);
-    const int rem = (int)(t - (long)qi * np);
+    const uint32_t t = li[e] * (uint32_t)nm;       // < 2048 * 2048: no overflow
+    const int qi = (int)(t / unp);
+    const int rem = (int)(t - (uint32_t)qi * unp);
     const float qf = __fdiv_rn((float)(2 * rem - np), (float)(2 * np));
     const float u = __fadd_rn(qf, __fmul_rn(disp[e * np3 + id], dscale));
     const float fl = floorf(u);

@@ -44,6 +44,8 @@ struct DepShared {
   uint16_t run[kCap + 1];                 // start of each run of equal cell
   uint32_t scan[kDT / 64];
   uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
+  uint32_t seg_pre[kMaxSeg];              // particles in the segments before
+  uint32_t seg_total;
   int nseg;
   int nrun;
   uint32_t count;
@@ -64,31 +66,51 @@ __device__ __forceinline__ uint32_t key_slot(uint64_t k) { return (uint32_t)k & 
 
 // filter: 0 = all, 1 = region x index == fv, 2 = region cell == fv.
 // Returns the number of matching particles (keys stored only when <= kCap).
+// The segments are one index space of seg_total particles; a thread takes
+// kG of them per round, issuing all their loads before using any.
+constexpr int kG = 2;
 template <int NC>
 __device__ uint32_t gather_keys(DepShared<NC>& sh, const float* __restrict__ disp,
                                 const uint32_t* __restrict__ perm, long np3, int np, int nm,
                                 float dscale, const int t0[3], int filter, int fv) {
   if (threadIdx.x == 0) sh.count = 0;
   __syncthreads();
-  for (int s = 0; s < sh.nseg; ++s) {
-    const uint32_t start = sh.seg_start[s], len = sh.seg_len[s];
-    for (uint32_t j = threadIdx.x; j < len; j += kDT) {
-      const uint32_t id = perm[start + j];
-      int c[3];
-      float f[3];
-      home_cell(disp, np3, id, np, nm, dscale, c, f);
-      const int rx = region_coord(c[0], t0[0], nm), ry = region_coord(c[1], t0[1], nm),
-                rz = region_coord(c[2], t0[2], nm);
+  const uint32_t total = sh.seg_total;
+  const int nseg = sh.nseg;
+  for (uint32_t base = 0; base < total; base += kG * kDT) {
+    uint32_t ids[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const uint32_t x = base + g * kDT + threadIdx.x;
+      ids[g] = 0xffffffffu;
+      if (x < total) {
+        int sg = 0;  // last segment with seg_pre <= x
+#pragma unroll
+        for (int step = kMaxSeg / 2; step > 0; step >>= 1)
+          if (sg + step < nseg && sh.seg_pre[sg + step] <= x) sg += step;
+        ids[g] = perm[sh.seg_start[sg] + (x - sh.seg_pre[sg])];
+      }
+    }
+    int c[kG][3];
+    float f[kG][3];
+#pragma unroll
+    for (int g = 0; g < kG; ++g)
+      if (ids[g] != 0xffffffffu) home_cell(disp, np3, ids[g], np, nm, dscale, c[g], f[g]);
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      if (ids[g] == 0xffffffffu) continue;
+      const int rx = region_coord(c[g][0], t0[0], nm), ry = region_coord(c[g][1], t0[1], nm),
+                rz = region_coord(c[g][2], t0[2], nm);
       const bool inside = rx < kReg && ry < kReg && rz < kReg;
       const int lc = (rx * kReg + ry) * kReg + rz;
       const bool pass = inside && (filter == 0 || (filter == 1 && rx == fv) || (filter == 2 && lc == fv));
       if (pass) {
         const uint32_t slot = atomicAdd(&sh.count, 1u);
         if (slot < (uint32_t)DepShared<NC>::kCap) {
-          sh.keys[slot] = ((uint64_t)lc << (kIdBits + kSlotBits)) | ((uint64_t)id << kSlotBits) | slot;
-          sh.fx[slot] = f[0];
-          sh.fy[slot] = f[1];
-          sh.fz[slot] = f[2];
+          sh.keys[slot] = ((uint64_t)lc << (kIdBits + kSlotBits)) | ((uint64_t)ids[g] << kSlotBits) | slot;
+          sh.fx[slot] = f[g][0];
+          sh.fy[slot] = f[g][1];
+          sh.fz[slot] = f[g][2];
         }
       }
     }
@@ -388,13 +410,17 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   __syncthreads();
   if (threadIdx.x == 0) {
     int ns = 0;
+    uint32_t tot = 0;
     for (int q = 0; q < kMaxSeg; ++q)
       if (sh.seg_len[q] > 0) {
         sh.seg_start[ns] = sh.seg_start[q];
         sh.seg_len[ns] = sh.seg_len[q];
+        sh.seg_pre[ns] = tot;
+        tot += sh.seg_len[q];
         ++ns;
       }
     sh.nseg = ns;
+    sh.seg_total = tot;
   }
   __syncthreads();
 

@@ -194,6 +194,14 @@ __device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float
   }
 }
 
+// threadIdx.x through an empty asm: the compiler cannot prove two such
+// values equal, so address arithmetic derived from them is not shared.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // tid: the thread's index (threadIdx.x; a caller inside a loop passes a
 // value the compiler cannot treat as loop-invariant, so that the stages'
 // address arithmetic is not hoisted out of the loop and kept live).
@@ -240,6 +248,35 @@ __device__ __forceinline__ void load_cols(float2* __restrict__ lds, const float2
   }
 }
 
+// LDS lines -> W adjacent columns, in chunks of kCh values per thread (the
+// LDS reads of a chunk before its stores; the empty asm keeps the compiler
+// from hoisting later chunks and raising the register count).
+constexpr int kCh = 6;
+template <int N, int W, int LD, int T>
+__device__ __forceinline__ void store_cols(float2* __restrict__ dst, long es, const float2* __restrict__ lds) {
+  constexpr int K = (N * W + T - 1) / T;
+#pragma unroll
+  for (int b0 = 0; b0 < K; b0 += kCh) {
+    float2 t[kCh];
+#pragma unroll
+    for (int q = 0; q < kCh; ++q) {
+      const int i = threadIdx.x + (b0 + q) * T;
+      const int e = i / W, c = i - e * W;
+      if (b0 + q < K && ((N * W) % T == 0 || i < N * W)) t[q] = lds[c * LD + pe(e)];
+    }
+#pragma unroll
+    for (int q = 0; q < kCh; ++q) {
+      const int i = threadIdx.x + (b0 + q) * T;
+      const int e = i / W, c = i - e * W;
+      if (b0 + q < K && ((N * W) % T == 0 || i < N * W)) dst[e * es + c] = t[q];
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
+// Padded complex row length (compile-time copy of padded_cols).
+constexpr int pcols(int n) { return ((n / 2 + 1) + 15) / 16 * 16; }
+
 // ---------------------------------------------------------------------------
 // z pass: rows of N reals (row stride `cols` complex).  NL rows per workgroup.
 template <int N>
@@ -272,19 +309,27 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z
   __syncthreads();
   lds_fft<H, NL, LD, T, 2, 1>(lds, twl);
   // split step: X_k = E_k + W_n^k O_k, E = (Z_k + conj Z_{h-k})/2, O = -i (Z_k - conj Z_{h-k})/2
-  for (int i = threadIdx.x; i < NL * cols; i += T) {
-    const int l = i / cols, k = i - l * cols;
-    if (r0 + l >= nrows) continue;
-    float2 x = make_float2(0.f, 0.f);
-    if (k <= H) {
+  constexpr int COLS = pcols(N), NO = NL * COLS, KO = (NO + T - 1) / T;
+  float2 xs[KO];
+#pragma unroll
+  for (int q = 0; q < KO; ++q) {
+    const int i = threadIdx.x + q * T;
+    const int l = i / COLS, k = i - l * COLS;
+    xs[q] = make_float2(0.f, 0.f);
+    if ((NO % T == 0 || i < NO) && k <= H) {
       const float2 a = lds[l * LD + pe(k == H ? 0 : k)];
       float2 b = lds[l * LD + pe(k == 0 ? 0 : H - k)];
       b.y = -b.y;
       const float2 e = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
       const float2 o = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
-      x = cadd(e, cmul(tw_get<N>(twl, k), o));
+      xs[q] = cadd(e, cmul(tw_get<N>(twl, k), o));
     }
-    base[(r0 + l) * cols + k] = x;
+  }
+#pragma unroll
+  for (int q = 0; q < KO; ++q) {
+    const int i = threadIdx.x + q * T;
+    const int l = i / COLS, k = i - l * COLS;
+    if ((NO % T == 0 || i < NO) && r0 + l < nrows) base[(r0 + l) * COLS + k] = xs[q];
   }
 }
 
@@ -347,9 +392,21 @@ __global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z
   }
   __syncthreads();
   lds_fft<H, NL, LD, T, 2, 0>(lds, twl);
-  for (int i = threadIdx.x; i < NL * H; i += T) {
-    const int l = i / H, j = i - l * H;
-    if (r0 + l < nrows) base[(r0 + l) * cols + j] = lds[l * LD + pe(j)];
+  {
+    constexpr int KO = (NL * H + T - 1) / T;
+    float2 t[KO];
+#pragma unroll
+    for (int q = 0; q < KO; ++q) {
+      const int i = threadIdx.x + q * T;
+      const int l = i / H, j = i - l * H;
+      if ((NL * H) % T == 0 || i < NL * H) t[q] = lds[l * LD + pe(j)];
+    }
+#pragma unroll
+    for (int q = 0; q < KO; ++q) {
+      const int i = threadIdx.x + q * T;
+      const int l = i / H, j = i - l * H;
+      if (((NL * H) % T == 0 || i < NL * H) && r0 + l < nrows) base[(r0 + l) * cols + j] = t[q];
+    }
   }
 }
 
@@ -445,11 +502,7 @@ __global__ __launch_bounds__(cols_threads(N, MODE), MODE == X_FWD_GREEN3 ? 4 : 1
   }
 
   if constexpr (MODE != X_FWD_GREEN3) {
-    float2* dst = out0 + mofs + p * g.plane_stride + c0;
-    for (int i = threadIdx.x; i < N * W; i += T) {
-      const int e = i / W, c = i - e * W;
-      dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
-    }
+    store_cols<N, W, LD, T>(out0 + mofs + p * g.plane_stride + c0, g.elem_stride, lds);
   } else {
     // PM: forward along x gives S = DFT[delta]; with phi = scale S / |n|^2,
     //   g_x = IDFT_x[i n_x phi]  (n_x on its Nyquist index -> 0),
@@ -554,9 +607,7 @@ __global__ __launch_bounds__(cols_threads(N, X_FWD_GREEN3)) void k_combine(
     const float2* src = ins[q] + p * g.plane_stride + c0;
     load_cols<N, W, LD, T>(lds, src, g.elem_stride);
     __syncthreads();
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    lds_fft<N, W, LD, T, 1, 1>(lds, twl, tid);
+    lds_fft<N, W, LD, T, 1, 1>(lds, twl, opaque_tid());
     const int kind = cs.kind[q], ca = cs.ca[q], cb = cs.cb[q];
 #pragma unroll
     for (int b = 0; b < E; ++b) {
