@@ -23,7 +23,6 @@
 
 namespace cola {
 
-constexpr int kDT = 512;                  // threads per workgroup
 constexpr int kTile = 16;                 // nodes per tile side
 constexpr int kReg = kTile + 1;           // region side (tile + lower layer)
 constexpr int kNReg = kReg * kReg * kReg;
@@ -35,21 +34,22 @@ static_assert(kNReg < (1 << (64 - kIdBits - kSlotBits)), "cell field");
 // NC = 1: unit masses (density).  NC = 3: three weighted deposits at once
 // (the transpose of the three-component CIC readout); weights are read by
 // particle id from global memory.
-template <int NC>
+// NC deposits, CAP particles held in LDS at once (power of two), DT threads.
+template <int NC, int CAP, int DT>
 struct DepShared {
-  static constexpr int kCap = NC == 1 ? 2048 : 1024;  // particles in LDS at once (power of two)
+  static constexpr int kNC = NC, kCap = CAP, kT = DT;
   uint64_t keys[kCap];                    // cell << 41 | id << 11 | slot
   float fx[kCap], fy[kCap], fz[kCap];
   float rho[NC][kTile * kTile * kTile];
   uint16_t run[kCap + 1];                 // start of each run of equal cell
-  uint32_t scan[kDT / 64];
+  uint32_t scan[DT / 64];
   uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
   uint32_t seg_pre[kMaxSeg];              // particles in the segments before
   uint32_t seg_total;
   int nseg;
   int nrun;
   uint32_t count;
-  uint32_t red[kDT / 64];
+  uint32_t red[DT / 64];
   float acc8[8 * NC];
 };
 
@@ -69,10 +69,11 @@ __device__ __forceinline__ uint32_t key_slot(uint64_t k) { return (uint32_t)k & 
 // The segments are one index space of seg_total particles; a thread takes
 // kG of them per round, issuing all their loads before using any.
 constexpr int kG = 2;
-template <int NC>
-__device__ uint32_t gather_keys(DepShared<NC>& sh, const float* __restrict__ disp,
+template <class S>
+__device__ uint32_t gather_keys(S& sh, const float* __restrict__ disp,
                                 const uint32_t* __restrict__ perm, long np3, int np, int nm,
                                 float dscale, const int t0[3], int filter, int fv) {
+  constexpr int kDT = S::kT;
   if (threadIdx.x == 0) sh.count = 0;
   __syncthreads();
   const uint32_t total = sh.seg_total;
@@ -106,7 +107,7 @@ __device__ uint32_t gather_keys(DepShared<NC>& sh, const float* __restrict__ dis
       const bool pass = inside && (filter == 0 || (filter == 1 && rx == fv) || (filter == 2 && lc == fv));
       if (pass) {
         const uint32_t slot = atomicAdd(&sh.count, 1u);
-        if (slot < (uint32_t)DepShared<NC>::kCap) {
+        if (slot < (uint32_t)S::kCap) {
           sh.keys[slot] = ((uint64_t)lc << (kIdBits + kSlotBits)) | ((uint64_t)ids[g] << kSlotBits) | slot;
           sh.fx[slot] = f[g][0];
           sh.fy[slot] = f[g][1];
@@ -116,15 +117,19 @@ __device__ uint32_t gather_keys(DepShared<NC>& sh, const float* __restrict__ dis
     }
   }
   __syncthreads();
-  return sh.count;
+  const uint32_t n = sh.count;
+  // every thread has its copy before a later call's thread 0 resets count
+  __syncthreads();
+  return n;
 }
 
 // Bitonic sort of keys[0, n) ascending (padding with ~0).  Each active
 // thread holds E = p2/kDT (>= 1) consecutive keys in registers; compare-
 // exchange partners closer than 64 E are reached through registers or lane
 // shuffles, farther ones through LDS (two barriers per such stage).
-template <int E, int NC>
-__device__ void bitonic_regs(DepShared<NC>& sh, uint32_t p2) {
+template <int E, class S>
+__device__ void bitonic_regs(S& sh, uint32_t p2) {
+  constexpr int kDT = S::kT;
   const uint32_t tid = threadIdx.x;
   const bool act = tid * E < p2;
   uint64_t v[E];
@@ -184,22 +189,24 @@ __device__ void bitonic_regs(DepShared<NC>& sh, uint32_t p2) {
   __syncthreads();
 }
 
-template <int NC>
-__device__ void sort_keys(DepShared<NC>& sh, uint32_t n) {
+template <class S>
+__device__ void sort_keys(S& sh, uint32_t n) {
+  constexpr int kDT = S::kT;
   uint32_t p2 = 64;
   while (p2 < n) p2 <<= 1;
   for (uint32_t j = n + threadIdx.x; j < p2; j += kDT) sh.keys[j] = ~0ull;
   __syncthreads();
   if (p2 <= (uint32_t)kDT) bitonic_regs<1>(sh, p2);
   else if (p2 <= 2u * kDT) bitonic_regs<2>(sh, p2);
-  else if constexpr (DepShared<NC>::kCap >= 4 * kDT) bitonic_regs<4>(sh, p2);
+  else if constexpr (S::kCap >= 4 * kDT) bitonic_regs<4>(sh, p2);
 }
 
 // Ordered list of run starts (runs of equal cell in the sorted keys):
 // wave-level scan of start flags, one barrier for the wave totals.
-template <int NC>
-__device__ void find_runs(DepShared<NC>& sh, uint32_t n) {
-  constexpr int kPer = DepShared<NC>::kCap / kDT;
+template <class S>
+__device__ void find_runs(S& sh, uint32_t n) {
+  constexpr int kDT = S::kT;
+  constexpr int kPer = S::kCap / kDT;
   uint32_t flags = 0, cnt = 0;
   const uint32_t base = threadIdx.x * kPer;
 #pragma unroll
@@ -236,8 +243,9 @@ __device__ void find_runs(DepShared<NC>& sh, uint32_t n) {
 }
 
 // Adds the 8 partial sums of region cell lc to its tile nodes for offset k.
-template <int NC>
-__device__ __forceinline__ void add_partial(DepShared<NC>& sh, int lc, int k, const float* acc) {
+template <class S>
+__device__ __forceinline__ void add_partial(S& sh, int lc, int k, const float* acc) {
+  constexpr int NC = S::kNC;
   const int rx = lc / (kReg * kReg), ry = (lc / kReg) % kReg, rz = lc % kReg;
   const int nx = rx + ((k >> 2) & 1) - 1, ny = ry + ((k >> 1) & 1) - 1, nz = rz + (k & 1) - 1;
   if (nx >= 0 && nx < kTile && ny >= 0 && ny < kTile && nz >= 0 && nz < kTile) {
@@ -253,10 +261,11 @@ __device__ __forceinline__ void add_partial(DepShared<NC>& sh, int lc, int k, co
 // the node accumulation in 8 phases k = 7 .. 0.  In phase k every node gets
 // at most one contribution (from cell n - s_k), so the phases fix the order
 // (ascending source cell) whatever the assignment of runs to threads.
-template <int NC>
-__device__ void accumulate_sorted(DepShared<NC>& sh, uint32_t n, const float* __restrict__ wt,
+template <class S>
+__device__ void accumulate_sorted(S& sh, uint32_t n, const float* __restrict__ wt,
                                   long np3) {
-  constexpr int kRuns = DepShared<NC>::kCap / kDT;  // runs per thread (nrun <= n <= kCap)
+  constexpr int NC = S::kNC, kDT = S::kT;
+  constexpr int kRuns = S::kCap / kDT;  // runs per thread (nrun <= n <= kCap)
   find_runs(sh, n);
   const int nrun = sh.nrun;
   float acc[kRuns][8][NC];
@@ -305,11 +314,12 @@ __device__ void accumulate_sorted(DepShared<NC>& sh, uint32_t n, const float* __
 
 // A cell with more than kCap particles: its weights added in ascending id by
 // repeated workgroup-wide minimum search (slow; extreme clustering only).
-template <int NC>
-__device__ void accumulate_select(DepShared<NC>& sh, const float* __restrict__ disp,
+template <class S>
+__device__ void accumulate_select(S& sh, const float* __restrict__ disp,
                                   const uint32_t* __restrict__ perm, long np3, int np, int nm,
                                   float dscale, const int t0[3], int lc_target,
                                   const float* __restrict__ wt) {
+  constexpr int NC = S::kNC, kDT = S::kT;
   if (threadIdx.x < 8 * NC) sh.acc8[threadIdx.x] = 0.0f;
   uint32_t last = 0;
   bool first = true;
@@ -358,7 +368,7 @@ __device__ void accumulate_select(DepShared<NC>& sh, const float* __restrict__ d
   }
 }
 
-template <int NC>
+template <int NC, int CAP, int kDT>
 __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
                                                  const uint32_t* __restrict__ perm,
                                                  const uint32_t* __restrict__ off, int np, int nm,
@@ -366,13 +376,13 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
                                                  long row_stride, long mesh_stride, int contrast,
                                                  float cinv, const float* __restrict__ wt,
                                                  long mstride) {
-  __shared__ DepShared<NC> sh;
+  __shared__ DepShared<NC, CAP, kDT> sh;
   disp = mock_ptr(disp, mstride);
   perm = mock_ptr(perm, mstride);
   off = mock_ptr(off, mstride);
   out = mock_ptr(out, mstride);
   if (wt) wt = mock_ptr(wt, mstride);
-  constexpr uint32_t kCap = DepShared<NC>::kCap;
+  constexpr uint32_t kCap = CAP;
   const int nt = nm / kTile;
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
@@ -464,6 +474,10 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   }
 }
 
+// Launch shape by mean occupancy: up to 256 particles per 16^3 tile (a mesh
+// 3x the particle grid has about 150) a 256-thread workgroup holding 1024
+// particles, so four tiles share a compute unit; denser grids 512 threads
+// and 2048 particles.  The result does not depend on the shape.
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off, int np, int nm,
                     float dscale, float* out, long row_stride, int contrast, hipStream_t s,
                     int nmock, long mstride) {
@@ -471,9 +485,13 @@ void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off
   const int nt = nm / kTile;
   const long ntiles = (long)nt * nt * nt;
   const float cinv = (float)((double)nm * nm * nm / (double)np3);
-  hipLaunchKernelGGL(k_deposit<1>, dim3((unsigned)ntiles, 1, (unsigned)nmock), dim3(kDT), 0, s, disp,
-                     perm, off, np, nm, dscale, np3, out, row_stride, 0L, contrast, cinv, nullptr,
-                     mstride);
+  const dim3 grid((unsigned)ntiles, 1, (unsigned)nmock);
+  if (np3 <= 256 * ntiles)
+    hipLaunchKernelGGL((k_deposit<1, 1024, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
+                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
+  else
+    hipLaunchKernelGGL((k_deposit<1, 2048, 512>), grid, dim3(512), 0, s, disp, perm, off, np, nm, dscale,
+                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
 }
 
 void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,
@@ -482,8 +500,8 @@ void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uin
   const long np3 = (long)np * np * np;
   const int nt = nm / kTile;
   const long ntiles = (long)nt * nt * nt;
-  hipLaunchKernelGGL(k_deposit<3>, dim3((unsigned)ntiles), dim3(kDT), 0, s, disp, perm, off, np, nm,
-                     1.0f, np3, out, row_stride, mesh_stride_floats, 0, 1.0f, wt, 0L);
+  hipLaunchKernelGGL((k_deposit<3, 1024, 512>), dim3((unsigned)ntiles), dim3(512), 0, s, disp, perm, off,
+                     np, nm, 1.0f, np3, out, row_stride, mesh_stride_floats, 0, 1.0f, wt, 0L);
 }
 
 }  // namespace cola

@@ -118,6 +118,36 @@ def test_density_bit_exact_clustered_overflow_paths(sim):
     assert got.tobytes() == ref.tobytes()
 
 
+@pytest.mark.parametrize("nm", [96, 128])
+def test_density_bit_exact_sparse_tiles(nm):
+    # 32^3 particles on a 96^3 / 128^3 mesh: at most 256 particles per 16^3
+    # tile on average, the compact workgroup shape (1024 particles in LDS).
+    # One cell with 1500 particles (ordered selection), a tile with 1500 more
+    # (slab path), a tile with 600 (fits), the rest random.
+    from paper_1507_05329_amd.sim import ColaSim
+    say(f"[gpu] density sparse tiles nm={nm}")
+    s = ColaSim(NP, nm, L)
+    try:
+        rng = np.random.default_rng(3)
+        base = ic.lattice(NP, L) * (nm / L) - 0.5
+        target = base + rng.standard_normal((3, NP ** 3)) * 1.5
+        target[:, :1500] = 30.0 + rng.uniform(0, 1, (3, 1500))
+        target[:, 1500:3000] = 34.0 + rng.uniform(0, 8.0, (3, 1500))
+        target[:, 3000:3600] = 50.0 + rng.uniform(0, 12.0, (3, 600))
+        disp = (target - base).astype(np.float32)
+        z = np.zeros((3, NP ** 3), np.float32)
+        s.set_state(to_dev(disp), to_dev(z), to_dev(z), to_dev(z), 0.5, 0.5)
+        got = s.density().cpu().numpy()
+        ref = cic_fp32.density(disp, NP, nm)
+        assert got.tobytes() == ref.tobytes()
+        disp = random_disp(4, 3.0)
+        s.set_state(to_dev(disp), to_dev(z), to_dev(z), to_dev(z), 0.5, 0.5)
+        got = s.density().cpu().numpy()
+        assert got.tobytes() == cic_fp32.density(disp, NP, nm).tobytes()
+    finally:
+        s.close()
+
+
 def test_density_matches_fp64_oracle(sim):
     disp = random_disp(2, 3.0)
     set_disp(sim, disp)
