@@ -49,6 +49,40 @@ def stage_bytes(np_side: int, nm: int) -> dict:
     }
 
 
+# Counter-measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by a plain copy of known size) for the production workload, with the
+# sha256 of the kernel sources they were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256p_768m.txt")
+STAGE_SOURCES = {
+    "sort": ["k_sort.hip"], "deposit": ["k_deposit.hip"], "fft_z": ["k_fft.hip"],
+    "fft_y": ["k_fft.hip"], "fft_x_green": ["k_fft.hip"], "ifft_y": ["k_fft.hip"],
+    "ifft_z": ["k_fft.hip"], "kick_drift": ["k_particles.hip"],
+}
+
+
+def measured_traffic(stage, workload):
+    """HBM bytes per launch of a stage from the committed counter summary, or
+    None when there is none for this workload or the kernel source changed."""
+    import hashlib
+    if workload != "production" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha, traffic = {}, {}
+    for line in open(TRAFFIC_FILE):
+        f = line.split()
+        if len(f) == 3 and f[0] == "sha256":
+            sha[f[1]] = f[2]
+        elif len(f) >= 3 and f[0] == "traffic":
+            traffic[f[1]] = int(f[2])
+    if stage not in traffic:
+        return None
+    csrc = os.path.join(ROOT, "paper_1507_05329_amd", "csrc")
+    for name in STAGE_SOURCES.get(stage, []) + ["cola_device.h"]:
+        h = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
+        if sha.get(name) != h:
+            return None
+    return traffic[stage]
+
+
 def batch_leg(steps, table, dev):
     """The 96-mock uneven ensemble (32 x 48^3/96^3, 32 x 64^3/128^3,
     32 x 96^3/192^3 particles/mesh, boxes 150/200/300 Mpc/h, distinct seeds):
@@ -102,6 +136,27 @@ def batch_leg(steps, table, dev):
             "speedup": t_seq / t_batch}
 
 
+def adjoint_leg(sim, cfg, table, e, steps):
+    """Average adjoint step (ms): reverse the K steps from their stored starts."""
+    import torch
+    sim.init_2lpt(cfg.seed, *table)
+    starts = []
+    for i in range(steps):
+        st = sim.get_state()
+        starts.append((st["disp"], st["a_v"]))
+        sim.step(e[i], e[i + 1])
+    dbar = torch.randn_like(starts[0][0])
+    vbar = torch.zeros_like(dbar)
+    p1b, p2b = torch.zeros_like(dbar), torch.zeros_like(dbar)
+    sim.step_adjoint(e[steps - 1], e[steps], starts[-1][1], starts[-1][0], dbar, vbar, p1b, p2b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in reversed(range(steps)):
+        sim.step_adjoint(e[i], e[i + 1], starts[i][1], starts[i][0], dbar, vbar, p1b, p2b)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
 def cpu_baseline(cfg, table, seed):
     """One oracle step of the same workload on the host (FP64, NumPy/SciPy)."""
     from oracle import cola
@@ -127,6 +182,7 @@ def main():
     ap.add_argument("--config", default="production")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (for HBM counter "
                          "calibration under rocprofv3) and exit")
@@ -179,23 +235,9 @@ def main():
     value = cfg.n_particles * args.steps / dt
 
     # adjoint: reverse the same K steps from their stored start positions
-    sim.init_2lpt(cfg.seed, *table)
-    starts = []
-    for i in range(args.steps):
-        st = sim.get_state()
-        starts.append((st["disp"], st["a_v"]))
-        sim.step(e[i], e[i + 1])
-    dbar = torch.randn_like(starts[0][0])
-    vbar = torch.zeros_like(dbar)
-    p1b, p2b = torch.zeros_like(dbar), torch.zeros_like(dbar)
-    sim.step_adjoint(e[args.steps - 1], e[args.steps], starts[-1][1], starts[-1][0], dbar, vbar, p1b, p2b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in reversed(range(args.steps)):
-        sim.step_adjoint(e[i], e[i + 1], starts[i][1], starts[i][0], dbar, vbar, p1b, p2b)
-    torch.cuda.synchronize()
-    ms_adj = (time.perf_counter() - t0) / args.steps * 1e3
-    del starts
+    ms_adj = None
+    if not args.no_adjoint:
+        ms_adj = adjoint_leg(sim, cfg, table, e, args.steps)
     sim.close()
     del sim
 
@@ -220,7 +262,9 @@ def main():
     dom_gbs = sb[dom] / (stages[dom]["ms"] * 1e-3) / 1e9
     step_bytes = sum(sb.values())
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom, args.config),
+                "bytes_alg": sb[dom],
                 "step_bytes_alg": step_bytes,
                 "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
@@ -247,9 +291,9 @@ def main():
         "data": "synthetic (BBKS Gaussian random field, GPU Philox seed %d)" % cfg.seed,
         "config": {"workload": cfg.name, "np": cfg.np_side, "nmesh": cfg.nmesh, "box": cfg.box,
                    "nstep": cfg.nstep, "a": [cfg.a_init, cfg.a_final]},
-        "fwd_adjoint": {"value": cfg.n_particles / ((ms_step + ms_adj) * 1e-3),
-                        "unit": "particle-updates/s", "ms_adjoint_step": ms_adj,
-                        "adjoint_over_forward": ms_adj / ms_step},
+        "fwd_adjoint": None if ms_adj is None else {
+            "value": cfg.n_particles / ((ms_step + ms_adj) * 1e-3), "unit": "particle-updates/s",
+            "ms_adjoint_step": ms_adj, "adjoint_over_forward": ms_adj / ms_step},
         "batched": batched,
         "stages": stages,
         "roofline": roofline,

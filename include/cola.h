@@ -240,6 +240,12 @@ cola_ctx* cola_batch_mock(cola_batch* batch, int32_t i);
 /* enable = 0: enqueue the step's launches directly instead of the graph
  * (same kernels, same results; used to check graph replays). */
 int cola_batch_set_graph(cola_batch* batch, int32_t enable);
+/* Mocks per launch: 0 (default) steps each group in one launch per kernel;
+ * bytes > 0 splits every group into consecutive chunks of
+ * max(1, bytes / per-mock workspace) mocks, launched one after the other in
+ * the same graph, so that a chunk's working set can stay in the GPU's
+ * last-level cache from kernel to kernel.  Results do not depend on it. */
+int cola_batch_set_chunk_bytes(cola_batch* batch, size_t bytes);
 /* One COLA step a0 -> a1 of every mock.  Every mock must hold a state at
  * a_x = a0 (COLA_ESTATE otherwise) and the mocks of a group must share
  * their velocity time a_v.  Asynchronous unless COLA_F_CHECK_FINITE is set

@@ -65,6 +65,7 @@ _SIGS = {
     "cola_batch_ngroups": (_I, [_P]),
     "cola_batch_mock": (_P, [_P, _I]),
     "cola_batch_set_graph": (C.c_int, [_P, _I]),
+    "cola_batch_set_chunk_bytes": (C.c_int, [_P, C.c_size_t]),
     "cola_batch_step": (C.c_int, [_P, _D, _D]),
     "cola_batch_synchronize": (C.c_int, [_P]),
     "cola_batch_last_error": (C.c_char_p, [_P]),

@@ -201,16 +201,16 @@ void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 
     fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream, nmock, mstride);
   }
   XPassArgs a;
-  a.in = c->mesh[0];
-  a.out[0] = c->mesh[0];
-  a.out[1] = c->mesh[1];
-  a.out[2] = c->mesh[2];
-  a.mode = X_FWD_GREEN3;
   a.coef = c->coef;
   a.nmock = nmock;
   a.mstride = mstride;
   {
     StageTimer t(c, COLA_STAGE_FFT_X);
+    a.in = c->mesh[0];
+    a.out[0] = c->mesh[0];
+    a.out[1] = c->mesh[1];
+    a.out[2] = c->mesh[2];
+    a.mode = X_FWD_GREEN3;
     fft_x(a, nm, c->tw, c->stream);
   }
   {
@@ -832,6 +832,7 @@ struct cola_batch {
     std::vector<int> idx;   // caller's mock indices, workspace order
     long mstride = 0;
     cola_ctx* first = nullptr;
+    int chunk = 0;          // mocks per launch (0: the whole group)
   };
   hipStream_t stream = nullptr;     // caller's stream
   hipStream_t cap = nullptr;        // capture stream
@@ -885,7 +886,10 @@ int batch_fail(cola_batch* b, int code, const std::string& msg) {
 }
 
 void batch_free(cola_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->exec) {
+    hipStreamSynchronize(b->stream);
+    hipGraphExecDestroy(b->exec);
+  }
   if (b->graph) hipGraphDestroy(b->graph);
   if (b->cap) hipStreamDestroy(b->cap);
   for (cola_ctx* c : b->mocks)
@@ -895,12 +899,26 @@ void batch_free(cola_batch* b) {
 
 void enqueue_batch_step(cola_batch* b, hipStream_t s) {
   for (cola_batch::Group& G : b->groups) {
-    cola_ctx* c = G.first;
-    const hipStream_t keep = c->stream;
-    c->stream = s;
-    step_launches(c, (int)G.idx.size(), G.mstride);
-    c->stream = keep;
+    const int n = (int)G.idx.size();
+    const int per = G.chunk > 0 ? G.chunk : n;
+    for (int i0 = 0; i0 < n; i0 += per) {
+      cola_ctx* c = b->mocks[G.idx[i0]];
+      const hipStream_t keep = c->stream;
+      c->stream = s;
+      step_launches(c, per < n - i0 ? per : n - i0, G.mstride);
+      c->stream = keep;
+    }
   }
+}
+
+void drop_graph(cola_batch* b) {
+  if (b->exec) {
+    hipStreamSynchronize(b->stream);  // no launch of the old graph still pending
+    hipGraphExecDestroy(b->exec);
+  }
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
 }
 
 // Captures the step launches of every group into one graph on the capture stream.
@@ -999,6 +1017,16 @@ int cola_batch_set_graph(cola_batch* b, int32_t enable) {
   if (!b) return COLA_EINVAL;
   if (enable && !b->cap) return batch_fail(b, COLA_EHIP, "no capture stream");
   b->use_graph = enable ? 1 : 0;
+  return COLA_OK;
+}
+
+int cola_batch_set_chunk_bytes(cola_batch* b, size_t bytes) {
+  if (!b) return COLA_EINVAL;
+  for (cola_batch::Group& G : b->groups) {
+    const size_t per = bytes / (size_t)G.mstride;
+    G.chunk = bytes == 0 ? 0 : (int)(per < 1 ? 1 : (per > G.idx.size() ? G.idx.size() : per));
+  }
+  drop_graph(b);
   return COLA_OK;
 }
 

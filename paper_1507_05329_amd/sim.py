@@ -221,6 +221,10 @@ class ColaBatch:
         check(self.lib.cola_batch_set_graph(self.batch, int(bool(enable))), what="batch_set_graph",
               batch=self.batch)
 
+    def set_chunk_bytes(self, nbytes: int):
+        check(self.lib.cola_batch_set_chunk_bytes(self.batch, int(nbytes)), what="batch_set_chunk_bytes",
+              batch=self.batch)
+
     def step(self, a0: float, a1: float):
         check(self.lib.cola_batch_step(self.batch, a0, a1), what="batch_step", batch=self.batch)
 
