@@ -42,8 +42,8 @@ def stage_bytes(np_side: int, nm: int) -> dict:
         "deposit": 16 * n_p + R,            # read perm + d, write delta
         "fft_z": R + C,                     # real in, half spectrum out
         "fft_y": 2 * C,
-        "fft_x_green": 4 * C,               # 1 read, 3 writes (three force components)
-        "ifft_y": 6 * C,                    # three meshes, read + write
+        "fft_x_green": 3 * C,               # 1 read, 2 writes (IDFT_x of i k_x phi and of phi)
+        "ifft_y": 5 * C,                    # g_x: read + write; phi: 1 read, 2 writes (g_y, g_z)
         "ifft_z": 3 * (C + R),              # three meshes, half spectrum in, real out
         "kick_drift": 72 * n_p + 3 * 4 * min(M, 8 * n_p),  # state r/w + CIC gathers
     }

@@ -53,8 +53,8 @@ extern "C" {
 #define COLA_STAGE_DEPOSIT   1  /* deterministic CIC gather                          */
 #define COLA_STAGE_FFT_Z     2  /* forward real-to-complex pass along z              */
 #define COLA_STAGE_FFT_Y     3  /* forward pass along y                              */
-#define COLA_STAGE_FFT_X     4  /* x pass: forward, Green's function x ik, inverse x3 */
-#define COLA_STAGE_IFFT_Y    5  /* inverse pass along y, 3 force meshes              */
+#define COLA_STAGE_FFT_X     4  /* x pass: forward, Green's function, 2 inverses     */
+#define COLA_STAGE_IFFT_Y    5  /* inverse y passes giving the 3 force components    */
 #define COLA_STAGE_IFFT_Z    6  /* inverse complex-to-real pass along z, 3 meshes    */
 #define COLA_STAGE_KICKDRIFT 7  /* CIC readout fused with kick and drift             */
 #define COLA_NSTAGE          8

@@ -2,8 +2,9 @@
 //
 // The PM step (Koda et al. 2015, Sec. 2.2-2.3) on one GPU:
 //   tile sort -> deterministic CIC deposit -> r2c FFT (z, y) ->
-//   x pass: forward FFT, Green's function x i k for the 3 axes, inverse FFT ->
-//   y and z inverse passes on the 3 force meshes -> CIC readout fused with the
+//   x pass: forward FFT, Green's function, inverse FFTs of i k_x phi and phi ->
+//   y pass: inverse of the first, inverses of i k_y and i k_z times the second ->
+//   z inverse passes on the 3 force meshes -> CIC readout fused with the
 //   COLA kick and drift (eqs. cola-kick, cola-drift; 2LPT terms of Sec. 2.1).
 #include <cmath>
 #include <cstdio>
@@ -186,8 +187,10 @@ void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast, con
 double green_scale(int nm, double alpha) { return alpha * nm / (2.0 * kPi) / ((double)nm * nm * nm); }
 
 // Deposit + FFT + Green x ik + inverse FFTs: the three force meshes in
-// c->mesh[0..2].  The Green scale is read from the device coefficients
-// c->coef (set by set_coef before this call).
+// c->mesh[0..2].  The x pass writes IDFT_x[i k_x phi] and IDFT_x[phi]; the
+// y pass turns the second into the y and z components (k_y and k_z are
+// constant along x, so phi needs only two inverse x transforms).  The Green
+// scale is read from the device coefficients c->coef (set by set_coef).
 void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 0) {
   const int nm = c->p.nmesh;
   const long rs = 2 * padded_cols(nm);
@@ -201,21 +204,21 @@ void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 
     fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream, nmock, mstride);
   }
   XPassArgs a;
+  a.in = c->mesh[0];
+  a.out[0] = c->mesh[0];
+  a.out[1] = c->mesh[1];
+  a.mode = X_FWD_GREEN;
   a.coef = c->coef;
   a.nmock = nmock;
   a.mstride = mstride;
   {
     StageTimer t(c, COLA_STAGE_FFT_X);
-    a.in = c->mesh[0];
-    a.out[0] = c->mesh[0];
-    a.out[1] = c->mesh[1];
-    a.out[2] = c->mesh[2];
-    a.mode = X_FWD_GREEN3;
     fft_x(a, nm, c->tw, c->stream);
   }
   {
     StageTimer t(c, COLA_STAGE_IFFT_Y);
-    fft_y(c->mesh[0], nm, 3, c->mesh_stride, 1, c->tw, c->stream, nmock, mstride);
+    fft_y(c->mesh[0], nm, 1, 0, 1, c->tw, c->stream, nmock, mstride);
+    fft_y_grad_yz(c->mesh[1], c->mesh[2], nm, c->tw, c->stream, nmock, mstride);
   }
   {
     StageTimer t(c, COLA_STAGE_IFFT_Z);

@@ -78,7 +78,10 @@ struct StepCoef {
   float pad;
 };
 // FFT passes (k_fft.hip).
-enum XMode { X_FWD = 0, X_FWD_GREEN3 = 1, X_FWD_AMP = 2, X_MULT_INV = 3, X_INV = 4 };
+// X_FWD_GREEN (x pass): forward, phi = Green's function x spectrum,
+// out[0] = IDFT_x[i n_x phi], out[1] = IDFT_x[phi].  X_INV_GRAD_YZ (y pass,
+// inverse) on that B: out[0] = IDFT_y[i n_y B], out[1] = IDFT_y[i n_z B].
+enum XMode { X_FWD = 0, X_FWD_GREEN = 1, X_FWD_AMP = 2, X_MULT_INV = 3, X_INV = 4, X_INV_GRAD_YZ = 5 };
 enum MultKind { M_NONE = 0, M_GRAD = 1, M_HESS = 2 };
 struct XPassArgs {
   const float2* in = nullptr;
@@ -88,7 +91,7 @@ struct XPassArgs {
   int comp_a = 0, comp_b = 0;   // gradient axis / Hessian axes
   float scale = 1.f;            // multiplier scale
   const float* amp = nullptr;   // amplitude by integer |n|^2 (X_FWD_AMP)
-  const StepCoef* coef = nullptr;  // X_FWD_GREEN3: scale read from coef->gscale
+  const StepCoef* coef = nullptr;  // X_FWD_GREEN: scale read from coef->gscale
   int nmock = 1;                // batched mocks (blockIdx.z) ...
   long mstride = 0;             // ... at this byte stride
 };
@@ -113,6 +116,9 @@ void fft_c2r_z(float2* mesh, int n, int nmesh_batch, long mesh_stride, const Twi
 void fft_y(float2* mesh, int n, int nmesh_batch, long mesh_stride, int inverse,
            const TwiddleSet& tw, hipStream_t s, int nmock = 1, long mstride = 0);
 void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s);
+// Inverse y pass of the PM gradients: b -> IDFT_y[i n_y b] in place, IDFT_y[i n_z b] -> gz.
+void fft_y_grad_yz(float2* b, float2* gz, int n, const TwiddleSet& tw, hipStream_t s, int nmock = 1,
+                   long mstride = 0);
 // Force readout + kick/drift (k_particles.hip).
 void launch_set_coef(StepCoef* dst, const StepCoef& v, int nmock, long mstride, hipStream_t s);
 void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2,

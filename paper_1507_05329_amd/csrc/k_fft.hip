@@ -48,10 +48,11 @@ constexpr int kLdsLimit = 80 * 1024;
 constexpr int cols_w(int n) { int w = 16; while (w > 1 && w * lds_ld(n) * 8 + n * 4 > kLdsLimit) w /= 2; return w; }
 constexpr int rows_nl(int h) { int nl = 16; while (nl > 1 && nl * lds_ld(h) * 8 + h * 8 > kLdsLimit) nl /= 2; return nl; }
 constexpr int threads_for(int elems) { return elems >= 4096 ? 512 : 256; }
-// The fused Green's-function pass keeps the forward spectrum in registers
-// across its three inverse transforms: spread it over 512 threads.
+// The two gradient passes keep a spectrum in registers across a transform:
+// spread it over 512 threads, and cap them at 128 VGPRs (4 waves per SIMD).
+constexpr bool holds_regs(int mode) { return mode == X_FWD_GREEN || mode == X_INV_GRAD_YZ; }
 constexpr int cols_threads(int n, int mode) {
-  return (mode == X_FWD_GREEN3 && cols_w(n) * n >= 4096) ? 512 : threads_for(cols_w(n) * n);
+  return (holds_regs(mode) && cols_w(n) * n >= 4096) ? 512 : threads_for(cols_w(n) * n);
 }
 
 bool make_plan(int n, FftPlan* plan) {
@@ -453,16 +454,15 @@ __device__ __forceinline__ float2 multiplier(int kind, int green, int ca, int cb
 }
 
 template <int N, int MODE>
-__global__ __launch_bounds__(cols_threads(N, MODE), MODE == X_FWD_GREEN3 ? 4 : 1) void k_cols(
+__global__ __launch_bounds__(cols_threads(N, MODE), holds_regs(MODE) ? 4 : 1) void k_cols(
     const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
     ColGeom g, const float2* __restrict__ tw, int mult, int ca, int cb, float scale,
     const float* __restrict__ amp, int y_is_plane_freq, const StepCoef* __restrict__ coef,
     long mstride) {
   in = mock_ptr(in, mstride);
   out0 = mock_ptr(out0, mstride);
-  if constexpr (MODE == X_FWD_GREEN3) {
-    out1 = mock_ptr(out1, mstride);
-    out2 = mock_ptr(out2, mstride);
+  if constexpr (MODE == X_FWD_GREEN || MODE == X_INV_GRAD_YZ) out1 = mock_ptr(out1, mstride);
+  if constexpr (MODE == X_FWD_GREEN) {
     if (coef) scale = mock_ptr(coef, mstride)->gscale;
   }
   constexpr int W = cols_w(N), LD = lds_ld(N), T = cols_threads(N, MODE);
@@ -501,14 +501,11 @@ __global__ __launch_bounds__(cols_threads(N, MODE), MODE == X_FWD_GREEN3 ? 4 : 1
     lds_fft<N, W, LD, T, 1, 0>(lds, twl);
   }
 
-  if constexpr (MODE != X_FWD_GREEN3) {
-    store_cols<N, W, LD, T>(out0 + mofs + p * g.plane_stride + c0, g.elem_stride, lds);
-  } else {
-    // PM: forward along x gives S = DFT[delta]; with phi = scale S / |n|^2,
-    //   g_x = IDFT_x[i n_x phi]  (n_x on its Nyquist index -> 0),
-    //   g_y = i n_y IDFT_x[phi], g_z = i n_z IDFT_x[phi]
-    // (n_y, n_z are constant along an x line: one inverse transform serves
-    // both; their Nyquist planes give zero).  Two inverse transforms.
+  if constexpr (MODE == X_FWD_GREEN) {
+    // PM, x pass: forward along x gives S = DFT[delta]; with phi = scale S / |n|^2
+    //   out0 = IDFT_x[i n_x phi]  (n_x on its Nyquist index -> 0)  -> g_x,
+    //   out1 = IDFT_x[phi]                                         -> g_y, g_z
+    // (n_y and n_z are constant along an x line; the y pass applies them).
     lds_fft<N, W, LD, T, 1, 1>(lds, twl);
     float2 phi[E];
 #pragma unroll
@@ -546,17 +543,57 @@ __global__ __launch_bounds__(cols_threads(N, MODE), MODE == X_FWD_GREEN3 ? 4 : 1
     __syncthreads();
     lds_fft<N, W, LD, T, 1, 0>(lds, twl);
     {
-      const float ky = (pfreq == N / 2 || pfreq == -N / 2) ? 0.f : (float)pfreq;
-      float2* dy = out1 + p * g.plane_stride + c0;
-      float2* dz = out2 + p * g.plane_stride + c0;
+      float2* dst = out1 + p * g.plane_stride + c0;
       for (int i = threadIdx.x; i < N * W; i += T) {
         const int e = i / W, c = i - e * W;
-        const float kz = (c0 + c >= N / 2) ? 0.f : (float)(c0 + c);
-        const float2 v = lds[c * LD + pe(e)];
-        dy[e * g.elem_stride + c] = make_float2(-ky * v.y, ky * v.x);
-        dz[e * g.elem_stride + c] = make_float2(-kz * v.y, kz * v.x);
+        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
       }
     }
+  } else if constexpr (MODE == X_INV_GRAD_YZ) {
+    // PM, inverse y pass of B = IDFT_x[phi]: out0 = IDFT_y[i n_y B], out1 =
+    // IDFT_y[i n_z B] (each component zeroed on its own Nyquist index).
+    float2 bv[E];
+#pragma unroll
+    for (int b = 0; b < E; ++b) {
+      const int i = threadIdx.x + b * T;
+      if ((W * N) % T == 0 || i < N * W) {
+        const int c = i / N, e = i - c * N;
+        const int ny = signed_freq(e, N);
+        const float ky = (ny == N / 2 || ny == -N / 2) ? 0.f : (float)ny;
+        bv[b] = lds[c * LD + pe(e)];
+        lds[c * LD + pe(e)] = make_float2(-ky * bv[b].y, ky * bv[b].x);  // i n_y B
+      }
+    }
+    __syncthreads();
+    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
+    {
+      float2* dst = out0 + p * g.plane_stride + c0;
+      for (int i = threadIdx.x; i < N * W; i += T) {
+        const int e = i / W, c = i - e * W;
+        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E; ++b) {
+      const int i = threadIdx.x + b * T;
+      if ((W * N) % T == 0 || i < N * W) {
+        const int c = i / N, e = i - c * N;
+        const float kz = (c0 + c >= N / 2) ? 0.f : (float)(c0 + c);
+        lds[c * LD + pe(e)] = make_float2(-kz * bv[b].y, kz * bv[b].x);  // i n_z B
+      }
+    }
+    __syncthreads();
+    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
+    {
+      float2* dst = out1 + p * g.plane_stride + c0;
+      for (int i = threadIdx.x; i < N * W; i += T) {
+        const int e = i / W, c = i - e * W;
+        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
+      }
+    }
+  } else {
+    store_cols<N, W, LD, T>(out0 + mofs + p * g.plane_stride + c0, g.elem_stride, lds);
   }
 }
 
@@ -567,13 +604,13 @@ __global__ __launch_bounds__(cols_threads(N, MODE), MODE == X_FWD_GREEN3 ? 4 : 1
 // to out instead of overwriting it.  Used by the adjoint (transposed Green's
 // function and transposed 2LPT maps).
 template <int N>
-__global__ __launch_bounds__(cols_threads(N, X_FWD_GREEN3)) void k_combine(
+__global__ __launch_bounds__(cols_threads(N, X_FWD_GREEN)) void k_combine(
     const float2* __restrict__ in0, const float2* __restrict__ in1, const float2* __restrict__ in2,
     float2* out, ColGeom g, const float2* __restrict__ tw, CombineSpec cs,
     const float* __restrict__ amp) {
   // the accumulator lives in registers across the inputs: spread it over
   // as many threads as the Green's-function pass
-  constexpr int W = cols_w(N), LD = lds_ld(N), T = cols_threads(N, X_FWD_GREEN3);
+  constexpr int W = cols_w(N), LD = lds_ld(N), T = cols_threads(N, X_FWD_GREEN);
   constexpr int E = (W * N + T - 1) / T;
   __shared__ float2 lds[W * LD];
   __shared__ float2 twl[N / 2];
@@ -719,9 +756,13 @@ void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbat
       hipLaunchKernelGGL((k_cols<N, X_MULT_INV>), grid, dim3(cols_threads(N, X_MULT_INV)), 0, s, in, out[0], nullptr, nullptr,
                          mesh_stride, g, tw, mult, ca, cb, scale, nullptr, yf, nullptr, mstride);
       break;
-    case X_FWD_GREEN3:
-      hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN3>), grid, dim3(cols_threads(N, X_FWD_GREEN3)), 0, s, in, out[0], out[1], out[2],
+    case X_FWD_GREEN:
+      hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN>), grid, dim3(cols_threads(N, X_FWD_GREEN)), 0, s, in, out[0], out[1], nullptr,
                          mesh_stride, g, tw, M_GRAD, 0, 0, scale, nullptr, yf, coef, mstride);
+      break;
+    case X_INV_GRAD_YZ:
+      hipLaunchKernelGGL((k_cols<N, X_INV_GRAD_YZ>), grid, dim3(cols_threads(N, X_INV_GRAD_YZ)), 0, s, in, out[0], out[1], nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
       break;
   }
 }
@@ -772,6 +813,17 @@ void fft_y(float2* mesh, int n, int nbatch, long mesh_stride, int inverse, const
   }
 }
 
+void fft_y_grad_yz(float2* b, float2* gz, int n, const TwiddleSet& tw, hipStream_t s, int nmock,
+                   long mstride) {
+  float2* outs[3] = {b, gz, nullptr};
+  switch (n) {
+#define X(NN) case NN: cols_n<NN>(X_INV_GRAD_YZ, 1, b, outs, 1, 0, tw.get(NN), 0, 0, 0, 1.f, nullptr, s, nullptr, nmock, mstride); break;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: break;
+  }
+}
+
 void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s) {
   float2* outs[3] = {a.out[0], a.out[1], a.out[2]};
   switch (n) {
@@ -789,7 +841,7 @@ void combine_n(const float2* const in[3], float2* out, const CombineSpec& cs, co
   constexpr int W = cols_w(N);
   const ColGeom g = geom(N, W, 0);
   dim3 grid((unsigned)(g.nchunk * g.nplanes), 1);
-  hipLaunchKernelGGL(k_combine<N>, grid, dim3(cols_threads(N, X_FWD_GREEN3)), 0, s, in[0], in[1], in[2], out,
+  hipLaunchKernelGGL(k_combine<N>, grid, dim3(cols_threads(N, X_FWD_GREEN)), 0, s, in[0], in[1], in[2], out,
                      g, tw, cs, amp);
 }
 }  // namespace
