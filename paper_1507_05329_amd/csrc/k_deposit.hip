@@ -12,8 +12,9 @@
 // source-cell order, in 8 phases (offset k = 7 .. 0) that are each
 // conflict-free (distinct cells -> distinct nodes).  The result is independent of launch
 // order, atomics and the order inside the buckets.  Regions holding more
-// particles than fit in LDS are processed by x-slab, then by single cell,
-// then by an ordered selection, keeping the same order.
+// particles than fit in LDS are processed in contiguous ranges of their
+// cells (halved until they fit), a single overfull cell by an ordered
+// selection, keeping the same order.
 #include "cola_device.h"
 #include "cola_internal.h"
 
@@ -64,7 +65,7 @@ __device__ __forceinline__ uint32_t key_cell(uint64_t k) { return (uint32_t)(k >
 __device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)(k >> kSlotBits) & ((1u << kIdBits) - 1u); }
 __device__ __forceinline__ uint32_t key_slot(uint64_t k) { return (uint32_t)k & ((1u << kSlotBits) - 1u); }
 
-// filter: 0 = all, 1 = region x index == fv, 2 = region cell == fv.
+// Takes the particles whose region cell lies in [lo, hi).
 // Returns the number of matching particles (keys stored only when <= kCap).
 // The segments are one index space of seg_total particles; a thread takes
 // kG of them per round, issuing all their loads before using any.
@@ -72,7 +73,7 @@ constexpr int kG = 2;
 template <class S>
 __device__ uint32_t gather_keys(S& sh, const float* __restrict__ disp,
                                 const uint32_t* __restrict__ perm, long np3, int np, int nm,
-                                float dscale, const int t0[3], int filter, int fv) {
+                                float dscale, const int t0[3], int lo, int hi) {
   constexpr int kDT = S::kT;
   if (threadIdx.x == 0) sh.count = 0;
   __syncthreads();
@@ -104,7 +105,7 @@ __device__ uint32_t gather_keys(S& sh, const float* __restrict__ disp,
                 rz = region_coord(c[g][2], t0[2], nm);
       const bool inside = rx < kReg && ry < kReg && rz < kReg;
       const int lc = (rx * kReg + ry) * kReg + rz;
-      const bool pass = inside && (filter == 0 || (filter == 1 && rx == fv) || (filter == 2 && lc == fv));
+      const bool pass = inside && lc >= lo && lc < hi;
       if (pass) {
         const uint32_t slot = atomicAdd(&sh.count, 1u);
         if (slot < (uint32_t)S::kCap) {
@@ -434,33 +435,28 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   }
   __syncthreads();
 
-  uint32_t n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 0, 0);
-  if (n <= kCap) {
-    if (n > 0) {
-      sort_keys(sh, n);
-      accumulate_sorted(sh, n, wt, np3);
-    }
-  } else {
-    for (int slab = 0; slab < kReg; ++slab) {
-      n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 1, slab);
-      if (n == 0) continue;
-      if (n <= kCap) {
+  // The region's cells in contiguous ranges [lo, hi) of the cell index,
+  // taken in increasing order; a range holding more than kCap particles is
+  // halved.  A node's contributions then still arrive in ascending source
+  // cell, i.e. descending offset k (k = 7 comes from the lowest cell), across
+  // ranges as within one.  A single cell above kCap: ordered selection.
+  int lo = 0, hi = kNReg;
+  uint32_t n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, lo, hi);
+  for (;;) {
+    if (n <= kCap || hi - lo == 1) {
+      if (n > kCap) {
+        accumulate_select(sh, disp, perm, np3, np, nm, dscale, t0, lo, wt);
+      } else if (n > 0) {
         sort_keys(sh, n);
         accumulate_sorted(sh, n, wt, np3);
-        continue;
       }
-      for (int cc = 0; cc < kReg * kReg; ++cc) {
-        const int lc = slab * kReg * kReg + cc;
-        n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, 2, lc);
-        if (n == 0) continue;
-        if (n <= kCap) {
-          sort_keys(sh, n);
-          accumulate_sorted(sh, n, wt, np3);
-        } else {
-          accumulate_select(sh, disp, perm, np3, np, nm, dscale, t0, lc, wt);
-        }
-      }
+      if (hi == kNReg) break;
+      lo = hi;
+      hi = kNReg;
+    } else {
+      hi = lo + (hi - lo) / 2;
     }
+    n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, lo, hi);
   }
 
   for (int nn = threadIdx.x; nn < kTile * kTile * kTile; nn += kDT) {
@@ -474,10 +470,11 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   }
 }
 
-// Launch shape by mean occupancy: up to 256 particles per 16^3 tile (a mesh
-// 3x the particle grid has about 150) a 256-thread workgroup holding 1024
-// particles, so four tiles share a compute unit; denser grids 512 threads
-// and 2048 particles.  The result does not depend on the shape.
+// 256 threads and 1024 particles in LDS (39 KB): four tiles share a compute
+// unit.  Measured against 512 threads / 2048 particles (62 KB, two tiles per
+// unit): equal on meshes 3x the particle grid (about 150 particles per tile),
+// 6-13% faster on meshes 2x the grid (about 500 per tile), where more regions
+// take the range-splitting path.  The result does not depend on the shape.
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off, int np, int nm,
                     float dscale, float* out, long row_stride, int contrast, hipStream_t s,
                     int nmock, long mstride) {
@@ -486,12 +483,8 @@ void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off
   const long ntiles = (long)nt * nt * nt;
   const float cinv = (float)((double)nm * nm * nm / (double)np3);
   const dim3 grid((unsigned)ntiles, 1, (unsigned)nmock);
-  if (np3 <= 256 * ntiles)
-    hipLaunchKernelGGL((k_deposit<1, 1024, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
-                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
-  else
-    hipLaunchKernelGGL((k_deposit<1, 2048, 512>), grid, dim3(512), 0, s, disp, perm, off, np, nm, dscale,
-                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
+  hipLaunchKernelGGL((k_deposit<1, 1024, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
+                     np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
 }
 
 void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,

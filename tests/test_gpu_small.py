@@ -103,7 +103,7 @@ def test_density_bit_exact_against_fp32_replay(sim):
 
 def test_density_bit_exact_clustered_overflow_paths(sim):
     # 3000 particles in one cell (ordered-selection path) and 3000 more spread
-    # over the same tile (slab path), the rest random.
+    # over the same tile (cell-range splitting), the rest random.
     say("[gpu] density clustered")
     rng = np.random.default_rng(1)
     base = lattice_mesh_units() - 0.5                    # node coordinate of the lattice point
@@ -120,10 +120,10 @@ def test_density_bit_exact_clustered_overflow_paths(sim):
 
 @pytest.mark.parametrize("nm", [96, 128])
 def test_density_bit_exact_sparse_tiles(nm):
-    # 32^3 particles on a 96^3 / 128^3 mesh: at most 256 particles per 16^3
-    # tile on average, the compact workgroup shape (1024 particles in LDS).
-    # One cell with 1500 particles (ordered selection), a tile with 1500 more
-    # (slab path), a tile with 600 (fits), the rest random.
+    # 32^3 particles on a 96^3 / 128^3 mesh (about 150 / 64 particles per
+    # 16^3 tile).  One cell with 1500 particles (more than the 1024 held in
+    # LDS: ordered selection), a tile with 1500 more (cell ranges halved until
+    # they fit), a tile with 600 (fits), the rest random.
     from paper_1507_05329_amd.sim import ColaSim
     say(f"[gpu] density sparse tiles nm={nm}")
     s = ColaSim(NP, nm, L)
