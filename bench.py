@@ -43,7 +43,8 @@ def stage_bytes(np_side: int, nm: int) -> dict:
         "fft_z": R + C,                     # real in, half spectrum out
         "fft_y": 2 * C,
         "fft_x_green": 3 * C,               # 1 read, 2 writes (IDFT_x of i k_x phi and of phi)
-        "ifft_y": 5 * C,                    # g_x: read + write; phi: 1 read, 2 writes (g_y, g_z)
+        "ifft_y": 2 * C,                    # g_x: read + write
+        "ifft_y_grad": 3 * C,               # IDFT_x[phi]: 1 read, 2 writes (g_y, g_z)
         "ifft_z": 3 * (C + R),              # three meshes, half spectrum in, real out
         "kick_drift": 72 * n_p + 3 * 4 * min(M, 8 * n_p),  # state r/w + CIC gathers
     }
@@ -56,7 +57,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256p_768m.txt")
 STAGE_SOURCES = {
     "sort": ["k_sort.hip"], "deposit": ["k_deposit.hip"], "fft_z": ["k_fft.hip"],
     "fft_y": ["k_fft.hip"], "fft_x_green": ["k_fft.hip"], "ifft_y": ["k_fft.hip"],
-    "ifft_z": ["k_fft.hip"], "kick_drift": ["k_particles.hip"],
+    "ifft_z": ["k_fft.hip"], "ifft_y_grad": ["k_fft.hip"], "kick_drift": ["k_particles.hip"],
 }
 
 

@@ -54,10 +54,11 @@ extern "C" {
 #define COLA_STAGE_FFT_Z     2  /* forward real-to-complex pass along z              */
 #define COLA_STAGE_FFT_Y     3  /* forward pass along y                              */
 #define COLA_STAGE_FFT_X     4  /* x pass: forward, Green's function, 2 inverses     */
-#define COLA_STAGE_IFFT_Y    5  /* inverse y passes giving the 3 force components    */
+#define COLA_STAGE_IFFT_Y    5  /* inverse y pass of the x force component           */
 #define COLA_STAGE_IFFT_Z    6  /* inverse complex-to-real pass along z, 3 meshes    */
 #define COLA_STAGE_KICKDRIFT 7  /* CIC readout fused with kick and drift             */
-#define COLA_NSTAGE          8
+#define COLA_STAGE_IFFT_Y_GRAD 8  /* inverse y pass giving the y and z components    */
+#define COLA_NSTAGE          9
 
 typedef struct cola_ctx cola_ctx;
 

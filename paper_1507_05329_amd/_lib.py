@@ -22,7 +22,8 @@ COLA_EHIP = -5
 COLA_ENONFINITE = -6
 COLA_F_CHECK_FINITE = 1
 COLA_F_STAGE_TIMERS = 2
-STAGES = ["sort", "deposit", "fft_z", "fft_y", "fft_x_green", "ifft_y", "ifft_z", "kick_drift"]
+STAGES = ["sort", "deposit", "fft_z", "fft_y", "fft_x_green", "ifft_y", "ifft_z", "kick_drift",
+          "ifft_y_grad"]
 
 
 class cola_params(C.Structure):

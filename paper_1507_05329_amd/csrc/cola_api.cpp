@@ -218,6 +218,9 @@ void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 
   {
     StageTimer t(c, COLA_STAGE_IFFT_Y);
     fft_y(c->mesh[0], nm, 1, 0, 1, c->tw, c->stream, nmock, mstride);
+  }
+  {
+    StageTimer t(c, COLA_STAGE_IFFT_Y_GRAD);
     fft_y_grad_yz(c->mesh[1], c->mesh[2], nm, c->tw, c->stream, nmock, mstride);
   }
   {
