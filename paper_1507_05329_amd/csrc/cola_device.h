@@ -68,6 +68,24 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
   return base + local;
 }
 
+// Particle of thread t (0..255) in block b of a particle-parallel launch of
+// np^3 / 256 blocks: blocks tile the lattice in sub-cubes of 2 x 4 x 32 ids
+// (4 x 4 x 16 when np is not a multiple of 32; every supported np is a
+// multiple of 16), k fastest inside a block and across blocks.  Particles of
+// one block stay close in space as they cluster, so they share the mesh
+// lines they read; rows of 32 (16) consecutive ids keep the state arrays'
+// accesses in whole cache lines.
+__device__ __forceinline__ long subcube_particle(uint32_t b, int t, int np) {
+  const int lk = (np & 31) == 0 ? 5 : 4;           // ids along k per block row: 32 or 16
+  const int si = 256 >> (lk + 2);                   // block depth along i: 2 or 4
+  const uint32_t nbk = (uint32_t)np >> lk, nbj = (uint32_t)np >> 2;
+  const uint32_t bk = b % nbk, bj = (b / nbk) % nbj, bi = b / (nbk * nbj);
+  const int k = (int)bk * (1 << lk) + (t & ((1 << lk) - 1));
+  const int j = (int)bj * 4 + ((t >> lk) & 3);
+  const int i = (int)bi * si + (t >> (lk + 2));
+  return ((long)i * np + j) * np + k;
+}
+
 // Mock index of a batched launch is blockIdx.z; every per-mock array of a
 // batch sits at the same offset inside equal per-mock workspace blocks, so a
 // single byte stride locates mock b's copy of any array.

@@ -37,8 +37,8 @@ __global__ __launch_bounds__(256) void k_adj_readout_kick(
     const float* __restrict__ g2, long row_stride, int np, int nm, long np3, KickDrift kd,
     float* __restrict__ dbar, float* __restrict__ vbar, float* __restrict__ p1bar,
     float* __restrict__ p2bar, float* __restrict__ fbar) {
-  // consecutive particle columns share mesh rows: keep neighbouring blocks on one XCD (L2)
-  const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  // particles of a block share mesh lines; neighbouring blocks stay on one XCD (L2)
+  const long i = subcube_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
   if (i >= np3) return;
   float F[3];
 #pragma unroll
@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256) void k_adj_deposit_grad(const float* __restric
                                                           long row_stride, int np, int ng,
                                                           float dscale, long np3, float coef,
                                                           float* __restrict__ dbar) {
-  // consecutive particle columns share mesh rows: keep neighbouring blocks on one XCD (L2)
-  const long i = (long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  // particles of a block share mesh lines; neighbouring blocks stay on one XCD (L2)
+  const long i = subcube_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
   if (i >= np3) return;
   int c[3];
   float f[3];
