@@ -218,8 +218,9 @@ const char* cola_last_error(const cola_ctx* ctx);
  * of all groups are captured once, at the first cola_batch_step, into one
  * HIP graph that reads the per-step scalars from device memory; every later
  * step writes those scalars (one small kernel per group) and launches the
- * graph.  A batched step runs the same kernels in the same order on the same
- * data as cola_step on each mock alone, so its results are bitwise equal. */
+ * graph, in which the groups are parallel branches.  A batched step runs
+ * the same kernels in the same order on the same data as cola_step on each
+ * mock alone, so its results are bitwise equal. */
 typedef struct cola_batch cola_batch;
 
 /* Workspace bytes for the batch (sum of the mocks' workspaces, 256-byte

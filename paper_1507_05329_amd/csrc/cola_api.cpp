@@ -827,9 +827,9 @@ const char* cola_last_error(const cola_ctx* c) { return c ? c->err.c_str() : "";
 // contexts of a group sit at a fixed byte stride in the workspace, so each
 // launch of the step covers the whole group (grid z = mock) and a group costs
 // the same kernel launches as one mock.  The launches of all groups are
-// captured once into a HIP graph that reads the per-step scalars from device
-// memory, so a step is one small coefficient write per group plus one graph
-// launch.
+// captured once into a HIP graph, one parallel branch per group (independent
+// data), that reads the per-step scalars from device memory, so a step is
+// one small coefficient write per group plus one graph launch.
 
 }  // extern "C"
 
@@ -842,6 +842,8 @@ struct cola_batch {
   };
   hipStream_t stream = nullptr;     // caller's stream
   hipStream_t cap = nullptr;        // capture stream
+  std::vector<hipStream_t> branch;  // one more capture stream per further group
+  std::vector<hipEvent_t> ev;       // fork event, then one join event per branch
   std::vector<cola_ctx*> mocks;     // caller's order
   std::vector<Group> groups;
   hipGraph_t graph = nullptr;
@@ -898,23 +900,41 @@ void batch_free(cola_batch* b) {
   }
   if (b->graph) hipGraphDestroy(b->graph);
   if (b->cap) hipStreamDestroy(b->cap);
+  for (hipStream_t t : b->branch) hipStreamDestroy(t);
+  for (hipEvent_t e : b->ev) hipEventDestroy(e);
   for (cola_ctx* c : b->mocks)
     if (c) cola_destroy(c);
   delete b;
 }
 
-void enqueue_batch_step(cola_batch* b, hipStream_t s) {
-  for (cola_batch::Group& G : b->groups) {
-    const int n = (int)G.idx.size();
-    const int per = G.chunk > 0 ? G.chunk : n;
-    for (int i0 = 0; i0 < n; i0 += per) {
-      cola_ctx* c = b->mocks[G.idx[i0]];
-      const hipStream_t keep = c->stream;
-      c->stream = s;
-      step_launches(c, per < n - i0 ? per : n - i0, G.mstride);
-      c->stream = keep;
-    }
+void enqueue_group(cola_batch* b, cola_batch::Group& G, hipStream_t s) {
+  const int n = (int)G.idx.size();
+  const int per = G.chunk > 0 ? G.chunk : n;
+  for (int i0 = 0; i0 < n; i0 += per) {
+    cola_ctx* c = b->mocks[G.idx[i0]];
+    const hipStream_t keep = c->stream;
+    c->stream = s;
+    step_launches(c, per < n - i0 ? per : n - i0, G.mstride);
+    c->stream = keep;
   }
+}
+
+// The groups one after the other on s, or (parallel) group 0 on s and group
+// g on branch stream g-1, forked from and joined back into s by events.
+void enqueue_batch_step(cola_batch* b, hipStream_t s, bool parallel) {
+  const size_t ng = b->groups.size();
+  if (!parallel || ng < 2 || b->branch.size() + 1 < ng) {
+    for (cola_batch::Group& G : b->groups) enqueue_group(b, G, s);
+    return;
+  }
+  hipEventRecord(b->ev[0], s);
+  for (size_t g = 1; g < ng; ++g) {
+    hipStreamWaitEvent(b->branch[g - 1], b->ev[0], 0);
+    enqueue_group(b, b->groups[g], b->branch[g - 1]);
+    hipEventRecord(b->ev[g], b->branch[g - 1]);
+  }
+  enqueue_group(b, b->groups[0], s);
+  for (size_t g = 1; g < ng; ++g) hipStreamWaitEvent(s, b->ev[g], 0);
 }
 
 void drop_graph(cola_batch* b) {
@@ -931,7 +951,7 @@ void drop_graph(cola_batch* b) {
 int build_graph(cola_batch* b) {
   hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return batch_fail(b, COLA_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
-  enqueue_batch_step(b, b->cap);
+  enqueue_batch_step(b, b->cap, true);
   const hipError_t el = hipGetLastError();
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->cap, &g);
@@ -1000,6 +1020,23 @@ int cola_batch_create(const cola_params* params, int32_t nmock, void* ws, size_t
     b->cap = nullptr;
     b->use_graph = 0;
   }
+  // branch streams and events for the groups' parallel branches in the graph
+  // (default priority); without them the graph runs the groups in sequence
+  bool ok = true;
+  for (size_t g = 0; ok && g < b->groups.size(); ++g) {
+    hipEvent_t e;
+    ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (ok) b->ev.push_back(e);
+    if (ok && g > 0) {
+      hipStream_t t;
+      ok = hipStreamCreateWithFlags(&t, hipStreamNonBlocking) == hipSuccess;
+      if (ok) b->branch.push_back(t);
+    }
+  }
+  if (!ok) {
+    for (hipStream_t t : b->branch) hipStreamDestroy(t);
+    b->branch.clear();
+  }
   *out = b;
   return COLA_OK;
 }
@@ -1065,7 +1102,7 @@ int cola_batch_step(cola_batch* b, double a0, double a1) {
     e = hipGraphLaunch(b->exec, b->stream);
     if (e != hipSuccess) return batch_fail(b, COLA_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
   } else {
-    enqueue_batch_step(b, b->stream);
+    enqueue_batch_step(b, b->stream, false);
     e = hipGetLastError();
     if (e != hipSuccess) return batch_fail(b, COLA_EHIP, std::string("batch step: ") + hipGetErrorString(e));
   }
