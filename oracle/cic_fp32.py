@@ -42,11 +42,13 @@ def _axis_terms(np_side: int, nm: int):
     return qi, qf
 
 
-def home_cells(disp: np.ndarray, np_side: int, nm: int):
-    """disp: (3, Np^3) float32 in mesh cells.  Returns cells (3, Np) int64, f (3, Np) f32."""
+def home_cells(disp: np.ndarray, np_side: int, nm: int, pid=None):
+    """disp: (3, n) float32 in mesh cells of particles pid (default: all,
+    n = Np^3).  Returns cells (3, n) int64, f (3, n) f32."""
     disp = np.asarray(disp, dtype=F32)
     qi, qf = _axis_terms(np_side, nm)
-    pid = np.arange(np_side ** 3, dtype=np.int64)
+    if pid is None:
+        pid = np.arange(np_side ** 3, dtype=np.int64)
     lat = [pid // (np_side * np_side), (pid // np_side) % np_side, pid % np_side]
     cells, fr = [], []
     for e in range(3):
@@ -124,3 +126,58 @@ def density_at_nodes(disp, np_side: int, nm: int, nodes: np.ndarray, contrast=Tr
         c_inv = F32(nm ** 3 / np_side ** 3)
         out = (out * c_inv).astype(F32) - F32(1.0)
     return out
+
+
+def density_at_nodes_chunked(disp, np_side: int, nm: int, nodes, contrast=True, chunk=1 << 26,
+                             progress=None):
+    """``density_at_nodes`` for particle counts too large to hold every
+    temporary at once: particles are scanned in id order, ``chunk`` at a
+    time, keeping only those whose home cell feeds one of the nodes; the
+    kept ones (still in ascending id) then go through the same replay.
+    ``progress(done, total)`` is called after every chunk when given."""
+    nodes = np.asarray(nodes, dtype=np.int64)
+    feed = set()
+    for n in nodes:
+        for k in range(8):
+            s = np.array([(k >> 2) & 1, (k >> 1) & 1, k & 1])
+            c = np.mod(n - s, nm)
+            feed.add(int((c[0] * nm + c[1]) * nm + c[2]))
+    feed = np.array(sorted(feed), dtype=np.int64)
+    n_all = disp.shape[1]
+    keep_id, keep_cells, keep_f = [], [], []
+    for a in range(0, n_all, chunk):
+        b = min(n_all, a + chunk)
+        pid = np.arange(a, b, dtype=np.int64)
+        cells, f = home_cells(disp[:, a:b], np_side, nm, pid)
+        flat = (cells[0] * nm + cells[1]) * nm + cells[2]
+        pos = np.minimum(np.searchsorted(feed, flat), len(feed) - 1)
+        m = feed[pos] == flat
+        keep_id.append(pid[m])
+        keep_cells.append(cells[:, m])
+        keep_f.append(f[:, m])
+        if progress is not None:
+            progress(b, n_all)
+    cells = np.concatenate(keep_cells, axis=1)
+    f = np.concatenate(keep_f, axis=1)
+    w = weights(f)
+    flat = (cells[0] * nm + cells[1]) * nm + cells[2]
+    order = np.argsort(flat, kind="stable")      # ids ascend within a cell
+    fs = flat[order]
+    out = np.empty(len(nodes), dtype=F32)
+    for j, n in enumerate(nodes):
+        rho = F32(0.0)
+        for k in range(7, -1, -1):
+            s = np.array([(k >> 2) & 1, (k >> 1) & 1, k & 1])
+            c = np.mod(n - s, nm)
+            cf = (c[0] * nm + c[1]) * nm + c[2]
+            lo, hi = np.searchsorted(fs, cf, "left"), np.searchsorted(fs, cf, "right")
+            part = F32(0.0)
+            for q in order[lo:hi]:
+                part = F32(part + w[k, q])
+            rho = F32(rho + part)
+        out[j] = rho
+    if contrast:
+        c_inv = F32(nm ** 3 / np_side ** 3)
+        out = (out * c_inv).astype(F32) - F32(1.0)
+    return out
+

@@ -97,3 +97,50 @@ class ColaPowerSpectrum(torch.autograd.Function):
         vbar = torch.zeros_like(dbar)
         wbar = _backward(sim, noise.contiguous(), ctx.edges, ctx.saved, ctx.segment, dbar, vbar)
         return wbar, None, None, None, None, None, None, None
+
+
+def pk_noise_gradient(sim: ColaSim, noise, k, pk, edges, kedges, cbar, ngrid=None, every=None):
+    """d(sum_b cbar_b P_b) / d(noise) for P(k) of the final particles, in the
+    least device memory: one position buffer, the four cotangent arrays and
+    a (displacement, velocity) checkpoint every ``every`` steps (None: none;
+    the initial conditions are rebuilt from the noise instead).  Each step's
+    start positions are recomputed from the nearest earlier checkpoint; the
+    step is deterministic, so they equal the forward's bit for bit.
+    Returns (gradient, P(k) of the forward run)."""
+    kedges = np.asarray(kedges, np.float64)
+    nstep = len(edges) - 1
+    every = nstep if every is None else max(1, int(every))
+    noise = noise.detach().contiguous()
+    ckpt = {}
+
+    def restart(i0):
+        """The state at the start of step i0, from the nearest earlier checkpoint."""
+        base = max([j for j in ckpt if j <= i0], default=0)
+        if base == 0:
+            sim.init_from_noise(noise, k, pk)
+        else:
+            d, v, ax, av = ckpt[base]
+            sim.set_state(d, v, None, None, ax, av)
+        for i in range(base, i0):
+            sim.step(edges[i], edges[i + 1])
+
+    sim.init_from_noise(noise, k, pk)
+    for i in range(nstep):
+        if i > 0 and i % every == 0:
+            st = sim.get_state(("disp", "vres"))
+            ckpt[i] = (st["disp"], st["vres"], st["a_x"], st["a_v"])
+        sim.step(edges[i], edges[i + 1])
+    _, p, n = sim.pk(kedges, ngrid)
+    pos = sim.get_state(("disp",))["disp"]
+    dbar = torch.zeros_like(pos)
+    sim.pk_adjoint(pos, kedges, np.where(n > 0, np.asarray(cbar, np.float64), 0.0), dbar, ngrid)
+    vbar = torch.zeros_like(dbar)
+    p1b = torch.zeros_like(dbar)
+    p2b = torch.zeros_like(dbar)
+    for i in reversed(range(nstep)):
+        restart(i)
+        st = sim.get_state(("disp",), out={"disp": pos})
+        sim.step_adjoint(edges[i], edges[i + 1], st["a_v"], pos, dbar, vbar, p1b, p2b)
+    del pos, vbar
+    return sim.init_adjoint(noise, dbar, p1b, p2b), np.where(n > 0, p, 0.0)
+

@@ -130,16 +130,25 @@ class ColaSim:
                                    nm.ctypes.data_as(C.POINTER(C.c_int64))), "pk")
         return km, p, nm
 
-    def get_state(self):
-        d, v, p1, p2 = (self.particles() for _ in range(4))
+    def get_state(self, which=("disp", "vres", "psi1", "psi2"), out=None):
+        """Copies of the named state arrays (new tensors, or the ones in ``out``)
+        and the times a_x, a_v."""
+        names = ("disp", "vres", "psi1", "psi2")
+        out = dict(out or {})
+        for n in which:
+            if n not in out:
+                out[n] = self.particles()
+        ptrs = [_ptr(out[n]) if n in which else None for n in names]
         ax, av = C.c_double(), C.c_double()
-        self._chk(self.lib.cola_get_state(self.ctx, _ptr(d), _ptr(v), _ptr(p1), _ptr(p2),
-                                          C.byref(ax), C.byref(av)), "get_state")
-        return dict(disp=d, vres=v, psi1=p1, psi2=p2, a_x=ax.value, a_v=av.value)
+        self._chk(self.lib.cola_get_state(self.ctx, *ptrs, C.byref(ax), C.byref(av)), "get_state")
+        res = {n: out[n] for n in which}
+        res.update(a_x=ax.value, a_v=av.value)
+        return res
 
     def set_state(self, disp, vres, psi1, psi2, a_x, a_v):
-        self._chk(self.lib.cola_set_state(self.ctx, _ptr(disp), _ptr(vres), _ptr(psi1), _ptr(psi2),
-                                          a_x, a_v), "set_state")
+        """Arrays given as None keep the context's (every array on the first call)."""
+        p = [None if t is None else _ptr(t) for t in (disp, vres, psi1, psi2)]
+        self._chk(self.lib.cola_set_state(self.ctx, *p, a_x, a_v), "set_state")
 
     def fft3d(self, mesh: torch.Tensor, n: int, inverse=False):
         self._chk(self.lib.cola_fft3d(self.ctx, n, _ptr(mesh), int(inverse)), "fft3d")

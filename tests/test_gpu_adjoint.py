@@ -168,3 +168,26 @@ def test_autograd_pk_gradient_matches_oracle(table):
     say(f"[gpu] P(k) noise gradient rel-L2 {err:.2e} cosine {cs:.6f}")
     s.close()
     assert err < 1e-3 and cs > 0.9999
+
+
+def test_lean_pk_gradient_equals_checkpointed_autograd(table):
+    # The recompute-from-the-start driver (used where memory is short) gives
+    # the checkpointed autograd's gradient bit for bit: the forward steps it
+    # replays are deterministic.
+    from paper_1507_05329_amd.autograd import ColaPowerSpectrum, pk_noise_gradient
+    from paper_1507_05329_amd.sim import ColaSim
+    np_, nm, box = 32, 64, 100.0
+    s = ColaSim(np_, nm, box)
+    e = step_edges()
+    kedges = pk.log_edges(box, nm, 10)
+    cb = seeded_normal(7, (10,)).astype(np.float64)
+    w = dev(white_noise(9, np_))
+    say("[gpu] lean P(k) gradient")
+    g0, p0 = pk_noise_gradient(s, w, *table, e, kedges, cb)
+    g3, p3 = pk_noise_gradient(s, w, *table, e, kedges, cb, every=3)
+    noise = w.clone().requires_grad_(True)
+    p = ColaPowerSpectrum.apply(noise, s, *table, e, kedges, None, 2)
+    (p * torch.from_numpy(cb)).sum().backward()
+    s.close()
+    assert np.array_equal(p0, p.detach().numpy()) and np.array_equal(p3, p0)
+    assert torch.equal(g0, noise.grad) and torch.equal(g3, noise.grad)

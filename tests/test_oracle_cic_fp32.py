@@ -60,3 +60,20 @@ def test_lattice_home_cells_are_cell_centred():
     cells, f = cic_fp32.home_cells(np.zeros((3, 4 ** 3), F32), 4, 12)
     assert np.all(f == F32(0.5))
     assert set(np.unique(cells[0])) == {0 + 2, 3 + 2, 6 + 2, 9 + 2}
+
+
+def test_chunked_node_replay_equals_full_replay():
+    # the chunked scan (used where all particles' temporaries do not fit in
+    # host memory) keeps exactly the feeding particles, in ascending id
+    rng = np.random.default_rng(12)
+    n, nm = 16, 32
+    disp = (rng.standard_normal((3, n ** 3)) * 2.0).astype(np.float32)
+    disp[:, :500] = (np.float32(7.3) - cic_fp32._axis_terms(n, nm)[0][0]).astype(np.float32)  # a crowded cell
+    nodes = np.r_[rng.integers(0, nm, (40, 3)), [[7, 7, 7], [8, 8, 8], [0, 0, 0], [31, 31, 31]]]
+    full = cic_fp32.density_at_nodes(disp, n, nm, nodes)
+    seen = []
+    for chunk in (777, 4096, n ** 3):
+        got = cic_fp32.density_at_nodes_chunked(disp, n, nm, nodes, chunk=chunk,
+                                                progress=lambda a, b: seen.append((a, b)))
+        assert got.tobytes() == full.tobytes()
+    assert seen[-1] == (n ** 3, n ** 3)
