@@ -4,14 +4,18 @@ Workload: 256^3 particles, 768^3 PM mesh (3x the particle grid), 600 Mpc/h
 box, flat LCDM Omega_m = 0.27, BBKS P(k) with sigma_8 = 0.8, Gaussian
 white-noise initial conditions (GPU Philox, seed 2) displaced by 2LPT,
 10 COLA steps uniform in a from 0.02 to 1.  A "step" is one cola_step: tile
-sort, deterministic CIC deposit, r2c FFT, Green's function x ik with three
-inverse FFTs, CIC readout fused with the kick/drift.
+sort, deterministic CIC deposit, r2c FFT, Green's function x ik and the
+inverse FFTs of the three force components, CIC readout fused with the
+kick/drift.
 
 Timed region: K consecutive steps of the 10-step schedule (K <= 10) after a
 fresh initial condition, inputs resident in HBM, bracketed by
-torch.cuda.synchronize().  A second pass with the library's per-stage HIP
-event timers gives the dominant kernel's achieved bandwidth against the
-8 TB/s HBM peak.  The FP64 CPU oracle is timed on one step of the same
+torch.cuda.synchronize().  Then, each in its own pass: the adjoint of the
+same K steps (fwd_adjoint), the 96-mock ensemble batched and one by one
+(batched), and the library's per-stage HIP event timers, which give the
+dominant kernel's achieved bandwidth against the 8 TB/s HBM peak (roofline;
+`traffic` comes from the committed counter summary while its kernel source
+is unchanged).  The FP64 CPU oracle is timed on one step of the same
 workload on the host cores (cpu_baseline).
 
 Prints one JSON line.
