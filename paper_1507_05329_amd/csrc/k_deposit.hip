@@ -470,11 +470,12 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   }
 }
 
-// 256 threads and 1024 particles in LDS (39 KB): four tiles share a compute
-// unit.  Measured against 512 threads / 2048 particles (62 KB, two tiles per
-// unit): equal on meshes 3x the particle grid (about 150 particles per tile),
-// 6-13% faster on meshes 2x the grid (about 500 per tile), where more regions
-// take the range-splitting path.  The result does not depend on the shape.
+// 256 threads; 512 particles in LDS (27 KB, five tiles per compute unit)
+// where a tile averages at most 256 particles (a mesh 3x the particle grid
+// has about 150), else 1024 (39 KB, four tiles).  Measured: 512 threads /
+// 2048 particles (62 KB, two tiles) was slower on every mesh; 512 against
+// 1024 saves 13% on the 768^3 mesh of 256^3 particles.  Fuller regions take
+// the range-splitting path.  The result does not depend on the shape.
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off, int np, int nm,
                     float dscale, float* out, long row_stride, int contrast, hipStream_t s,
                     int nmock, long mstride) {
@@ -483,8 +484,12 @@ void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off
   const long ntiles = (long)nt * nt * nt;
   const float cinv = (float)((double)nm * nm * nm / (double)np3);
   const dim3 grid((unsigned)ntiles, 1, (unsigned)nmock);
-  hipLaunchKernelGGL((k_deposit<1, 1024, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
-                     np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
+  if (np3 <= 256 * ntiles)
+    hipLaunchKernelGGL((k_deposit<1, 512, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
+                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
+  else
+    hipLaunchKernelGGL((k_deposit<1, 1024, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
+                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
 }
 
 void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,

@@ -28,7 +28,8 @@ __global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ dis
   counts = mock_ptr(counts, mstride);
   pkey = mock_ptr(pkey, mstride);
   prank = mock_ptr(prank, mstride);
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  // sub-cube order: a wave's particles share few buckets (fewer atomics)
+  const long i = subcube_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
   if (i >= np3) return;  // np3 is a multiple of 64 for every supported size: whole waves exit
   int c[3];
   float f[3];

@@ -121,9 +121,10 @@ def test_density_bit_exact_clustered_overflow_paths(sim):
 @pytest.mark.parametrize("nm", [96, 128])
 def test_density_bit_exact_sparse_tiles(nm):
     # 32^3 particles on a 96^3 / 128^3 mesh (about 150 / 64 particles per
-    # 16^3 tile).  One cell with 1500 particles (more than the 1024 held in
-    # LDS: ordered selection), a tile with 1500 more (cell ranges halved until
-    # they fit), a tile with 600 (fits), the rest random.
+    # 16^3 tile: the 512-particle LDS shape).  One cell with 1500 particles
+    # (ordered selection), a tile with 1500 more and one with 600 (cell
+    # ranges halved until they fit), the rest random.  The 64^3 mesh of the
+    # other tests (512 per tile) takes the 1024-particle shape.
     from paper_1507_05329_amd.sim import ColaSim
     say(f"[gpu] density sparse tiles nm={nm}")
     s = ColaSim(NP, nm, L)
