@@ -280,138 +280,6 @@ __device__ __forceinline__ void store_cols(float2* __restrict__ dst, long es, co
 constexpr int pcols(int n) { return ((n / 2 + 1) + 15) / 16 * 16; }
 
 // ---------------------------------------------------------------------------
-// z pass: rows of N reals (row stride `cols` complex).  NL rows per workgroup.
-template <int N>
-__global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_r2c_z(
-    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
-    long mstride) {
-  constexpr int H = N / 2, LD = lds_ld(H), NL = rows_nl(H), T = threads_for(NL * H);
-  constexpr int LE = (NL * H + T - 1) / T;
-  mesh = mock_ptr(mesh, mstride);
-  __shared__ float2 lds[NL * LD];
-  __shared__ float2 twl[N / 2];
-  float2* base = mesh + blockIdx.y * mesh_stride;
-  const long r0 = (long)blockIdx.x * NL;
-  load_twiddles<N / 2, T>(twl, tw);
-  {
-    float2 t[LE];
-#pragma unroll
-    for (int b = 0; b < LE; ++b) {
-      const int i = threadIdx.x + b * T;
-      const int l = i / H, j = i - l * H;
-      if (((NL * H) % T == 0 || i < NL * H) && r0 + l < nrows) t[b] = base[(r0 + l) * cols + j];
-    }
-#pragma unroll
-    for (int b = 0; b < LE; ++b) {
-      const int i = threadIdx.x + b * T;
-      const int l = i / H, j = i - l * H;
-      if (((NL * H) % T == 0 || i < NL * H) && r0 + l < nrows) lds[l * LD + pe(j)] = t[b];
-    }
-  }
-  __syncthreads();
-  lds_fft<H, NL, LD, T, 2, 1>(lds, twl);
-  // split step: X_k = E_k + W_n^k O_k, E = (Z_k + conj Z_{h-k})/2, O = -i (Z_k - conj Z_{h-k})/2
-  constexpr int COLS = pcols(N), NO = NL * COLS, KO = (NO + T - 1) / T;
-  float2 xs[KO];
-#pragma unroll
-  for (int q = 0; q < KO; ++q) {
-    const int i = threadIdx.x + q * T;
-    const int l = i / COLS, k = i - l * COLS;
-    xs[q] = make_float2(0.f, 0.f);
-    if ((NO % T == 0 || i < NO) && k <= H) {
-      const float2 a = lds[l * LD + pe(k == H ? 0 : k)];
-      float2 b = lds[l * LD + pe(k == 0 ? 0 : H - k)];
-      b.y = -b.y;
-      const float2 e = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y + b.y));
-      const float2 o = make_float2(0.5f * (a.y - b.y), -0.5f * (a.x - b.x));
-      xs[q] = cadd(e, cmul(tw_get<N>(twl, k), o));
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < KO; ++q) {
-    const int i = threadIdx.x + q * T;
-    const int l = i / COLS, k = i - l * COLS;
-    if ((NO % T == 0 || i < NO) && r0 + l < nrows) base[(r0 + l) * COLS + k] = xs[q];
-  }
-}
-
-// Inverse z pass: half spectrum (H+1 values) -> N reals, unnormalised.
-template <int N>
-__global__ __launch_bounds__(threads_for(rows_nl(N / 2) * (N / 2))) void k_c2r_z(
-    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
-    long mstride) {
-  constexpr int H = N / 2, LD = lds_ld(H), NL = rows_nl(H), T = threads_for(NL * H);
-  mesh = mock_ptr(mesh, mstride);
-  __shared__ float2 lds[NL * LD];
-  __shared__ float2 twl[N / 2];
-  float2* base = mesh + blockIdx.y * mesh_stride;
-  const long r0 = (long)blockIdx.x * NL;
-  // Each thread loads whole pairs (k, h-k) of a row and forms
-  //   Z'_k = (X_k + conj X_{h-k}) + i (X_k - conj X_{h-k}) exp(+2 pi i k / n)
-  // (and Z'_{h-k} likewise) in registers, k = 0 .. h/2.
-  constexpr int HP = H / 2 + 1, NPR = NL * HP, KP = (NPR + T - 1) / T;
-  float2 xa[KP], xb[KP];
-#pragma unroll
-  for (int b = 0; b < KP; ++b) {
-    const int i = threadIdx.x + b * T;
-    const int l = i / HP, k = i - l * HP;
-    xa[b] = make_float2(0.f, 0.f);
-    xb[b] = make_float2(0.f, 0.f);
-    if ((NPR % T == 0 || i < NPR) && r0 + l < nrows) {
-      xa[b] = base[(r0 + l) * cols + k];
-      xb[b] = base[(r0 + l) * cols + (H - k)];
-    }
-  }
-  load_twiddles<N / 2, T>(twl, tw);
-  __syncthreads();
-#pragma unroll
-  for (int b = 0; b < KP; ++b) {
-    const int i = threadIdx.x + b * T;
-    if (NPR % T == 0 || i < NPR) {
-      const int l = i / HP, k = i - l * HP;
-      const int k2 = H - k;
-      float2 za, zb;
-      {
-        const float2 cb = make_float2(xb[b].x, -xb[b].y);
-        const float2 e = cadd(xa[b], cb);
-        float2 w = tw_get<N>(twl, k);
-        w.y = -w.y;
-        const float2 o = cmul(csub(xa[b], cb), w);
-        za = cadd(e, make_float2(-o.y, o.x));
-      }
-      {
-        const float2 ca = make_float2(xa[b].x, -xa[b].y);
-        const float2 e = cadd(xb[b], ca);
-        float2 w = tw_get<N>(twl, k2);
-        w.y = -w.y;
-        const float2 o = cmul(csub(xb[b], ca), w);
-        zb = cadd(e, make_float2(-o.y, o.x));
-      }
-      lds[l * LD + pe(k)] = za;
-      if (k2 != k && k2 != H) lds[l * LD + pe(k2)] = zb;
-    }
-  }
-  __syncthreads();
-  lds_fft<H, NL, LD, T, 2, 0>(lds, twl);
-  {
-    constexpr int KO = (NL * H + T - 1) / T;
-    float2 t[KO];
-#pragma unroll
-    for (int q = 0; q < KO; ++q) {
-      const int i = threadIdx.x + q * T;
-      const int l = i / H, j = i - l * H;
-      if ((NL * H) % T == 0 || i < NL * H) t[q] = lds[l * LD + pe(j)];
-    }
-#pragma unroll
-    for (int q = 0; q < KO; ++q) {
-      const int i = threadIdx.x + q * T;
-      const int l = i / H, j = i - l * H;
-      if (((NL * H) % T == 0 || i < NL * H) && r0 + l < nrows) base[(r0 + l) * cols + j] = t[q];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Strided column passes.  Element e of column c in plane p sits at
 // data[p * plane_stride + e * elem_stride + c].
 struct ColGeom {
@@ -453,8 +321,233 @@ __device__ __forceinline__ float2 multiplier(int kind, int green, int ca, int cb
   return make_float2(1.f, 0.f);
 }
 
+// ---------------------------------------------------------------------------
+// Register-staged transforms.  The first stage of a transform takes its
+// inputs from registers (filled straight from HBM), the last one leaves its
+// outputs in registers (written straight to HBM), and only the stage
+// boundaries in between go through LDS.
+//
+// Orders: ORD 0 takes the radices as radix_at lists them, ORD 1 in reverse.
+// After a transform in one order the last stage of radix R leaves each thread
+// with elements j + r n/R; the first stage of the other order has the same
+// radix and reads exactly these, so a spectral multiplier between a forward
+// and an inverse transform is applied in registers.
+constexpr int rad_o(int n, int ord, int s) { return ord ? radix_at(n, nstage(n) - 1 - s) : radix_at(n, s); }
+constexpr int ns_o(int n, int ord, int s) {
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= rad_o(n, ord, i);
+  return p;
+}
+// LDS layout between stages s and s+1: the line is cut into the R_{s+1}
+// segments of n / R_{s+1} elements that one butterfly of stage s+1 reads
+// together, each followed by PAD unused slots.  Reads of stage s+1 and
+// writes of stage s (whose R outputs lie in one segment) are then a
+// per-thread base plus compile-time offsets.  PAD = (NS_s - segment) mod 16
+// puts the output blocks of neighbouring stage-s butterflies on different
+// LDS banks (segments shorter than 16 are left unpadded).
+constexpr int seg_o(int n, int ord, int s) { return n / rad_o(n, ord, s + 1); }
+constexpr int pad_o(int n, int ord, int s) {
+  return seg_o(n, ord, s) < 16 ? 0 : ((ns_o(n, ord, s) - seg_o(n, ord, s)) % 16 + 16) % 16;
+}
+// Line pitch: holds every layout of both orders; 2 mod 16 float2, so the 8
+// lines x 2 rows that 16 lanes of a column pass touch fall on distinct bank
+// pairs.
+constexpr int fld(int n) {
+  int m = n;
+  for (int o = 0; o < 2; ++o)
+    for (int s = 0; s + 1 < nstage(n); ++s) {
+      const int sp = rad_o(n, o, s + 1) * (seg_o(n, o, s) + pad_o(n, o, s));
+      if (sp > m) m = sp;
+    }
+  return (m + 13) / 16 * 16 + 2;
+}
+// Column passes: W lines of length n.  Twiddle entries kept in LDS: the
+// whole period where it fits, else the first half.
+constexpr int fcols_w(int n) {
+  int w = 16;
+  while (w > 1 && w * fld(n) * 8 + n * 4 > kLdsLimit) w /= 2;
+  return w;
+}
+constexpr int ftw_len(int n) { return fcols_w(n) * fld(n) * 8 + n * 8 <= kLdsLimit ? n : n / 2; }
+constexpr int fcols_threads(int n) { return threads_for(fcols_w(n) * n); }
+// z passes: NL rows of n reals, i.e. of h = n/2 complex values; the twiddle
+// table has period n (the transform of length h takes every second entry).
+constexpr int frows_nl(int n) {
+  int nl = 16;
+  while (nl > 1 && nl * fld(n / 2) * 8 + n * 4 > kLdsLimit) nl /= 2;
+  return nl;
+}
+constexpr int frows_tw_len(int n) { return frows_nl(n) * fld(n / 2) * 8 + n * 8 <= kLdsLimit ? n : n / 2; }
+constexpr int frows_threads(int n) { return threads_for(frows_nl(n) * (n / 2)); }
+
+// exp(-2 pi i m / NT) from an LDS table of TL = NT or NT / 2 entries.
+template <int NT, int TL>
+__device__ __forceinline__ float2 tw_at(const float2* __restrict__ twl, int m) {
+  if constexpr (TL == NT) return twl[m];
+  else return tw_get<NT>(twl, m);
+}
+// a * conj(w)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 w) {
+  return make_float2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+}
+
+// Stage S of order ORD on W lines of length N with T threads.  Column passes
+// (ROWS = false): butterfly t = tid + b T is line c = t mod W, index
+// j = t / W, so the lanes of a wave cover W adjacent columns and their HBM
+// accesses are W-wide runs.  z passes (ROWS = true): line l = t / NBL,
+// j = t mod NBL, lanes run along a row; the twiddle table has period 2N.
+template <int N, int ORD, int S, int W, int T, bool ROWS>
+struct Stg {
+  static constexpr int LEN = N, NST = nstage(N), TWS = ROWS ? 2 : 1;
+  static constexpr int R = rad_o(N, ORD, S), NS = ns_o(N, ORD, S), NBL = N / R;
+  static constexpr int NB = W * NBL, KB = (NB + T - 1) / T;
+  static constexpr int STEP = N / (NS * R) * TWS;
+  // element j + r NBL of the layout before this stage sits at j + r RSTR
+  static constexpr int RSTR = S > 0 ? NBL + pad_o(N, ORD, S - 1) : NBL;
+  // outputs go to the layout after this stage: blocks of QB butterfly
+  // groups per segment, WPAD slots after each segment
+  static constexpr int WPAD = S + 1 < NST ? pad_o(N, ORD, S) : 0;
+  static constexpr int QB = S + 1 < NST ? seg_o(N, ORD, S) / (NS * R) : 1;
+  __device__ static bool ok(int t) { return NB % T == 0 || t < NB; }
+  __device__ static void map(int t, int& line, int& j) {
+    if constexpr (ROWS) {
+      line = t / NBL;
+      j = t - line * NBL;
+    } else {
+      line = t % W;
+      j = t / W;
+    }
+  }
+};
+
+// Twiddles of the stage (none at NS = 1), then the length-R DFT.
+template <class St, int FWD, int TL>
+__device__ __forceinline__ void st_bfly(float2* v, const float2* __restrict__ twl, int j) {
+  if constexpr (St::NS > 1) {
+    const int m1 = (j % St::NS) * St::STEP;
+#pragma unroll
+    for (int r = 1; r < St::R; ++r) {
+      const float2 w = tw_at<St::LEN * St::TWS, TL>(twl, r * m1);
+      v[r] = FWD ? cmul(v[r], w) : cmulc(v[r], w);
+    }
+  }
+  Dft<St::R>::run(v, FWD ? -1.f : 1.f);
+}
+
+template <class St, int T, int LD, int FWD, int TL>
+__device__ __forceinline__ void lds_gather_bfly(float2 (&v)[St::KB][St::R], const float2* __restrict__ lds,
+                                                const float2* __restrict__ twl, int tid) {
+#pragma unroll
+  for (int b = 0; b < St::KB; ++b) {
+    const int t = tid + b * T;
+    if (St::ok(t)) {
+      int c, j;
+      St::map(t, c, j);
+      const float2* p = lds + c * LD + j;
+#pragma unroll
+      for (int r = 0; r < St::R; ++r) v[b][r] = p[r * St::RSTR];
+      st_bfly<St, FWD, TL>(v[b], twl, j);
+    }
+  }
+}
+
+template <class St, int T, int LD>
+__device__ __forceinline__ void lds_scatter(const float2 (&v)[St::KB][St::R], float2* lds, int tid) {
+#pragma unroll
+  for (int b = 0; b < St::KB; ++b) {
+    const int t = tid + b * T;
+    if (St::ok(t)) {
+      int c, j;
+      St::map(t, c, j);
+      const int q = j / St::NS, k = j - q * St::NS;
+      float2* p = lds + c * LD + q * (St::NS * St::R) + k + St::WPAD * (q / St::QB);
+#pragma unroll
+      for (int r = 0; r < St::R; ++r) p[r * St::NS] = v[b][r];
+    }
+  }
+}
+
+// Stages S .. NST-2, LDS to LDS.
+template <int N, int ORD, int S, int W, int T, bool ROWS, int LD, int FWD, int TL>
+__device__ __forceinline__ void mid_stages(float2* lds, const float2* __restrict__ twl, int tid) {
+  if constexpr (S + 1 < nstage(N)) {
+    using St = Stg<N, ORD, S, W, T, ROWS>;
+    float2 v[St::KB][St::R];
+    lds_gather_bfly<St, T, LD, FWD, TL>(v, lds, twl, tid);
+    __syncthreads();
+    lds_scatter<St, T, LD>(v, lds, tid);
+    __syncthreads();
+    mid_stages<N, ORD, S + 1, W, T, ROWS, LD, FWD, TL>(lds, twl, tid);
+  }
+}
+
+// One transform of order ORD from the first stage's inputs in registers (v0,
+// overwritten) to the last stage's outputs in registers (vl): value r of
+// slot b is element j + r N/R of line c (Stg::map).  The caller has the
+// twiddle table in LDS and no thread still reading LDS.
+template <int N, int ORD, int W, int T, bool ROWS, int LD, int FWD, int TL, class A0, class AL>
+__device__ __forceinline__ void reg_fft(A0& v0, AL& vl, float2* lds, const float2* __restrict__ twl, int tid) {
+  using S0 = Stg<N, ORD, 0, W, T, ROWS>;
+  using SL = Stg<N, ORD, nstage(N) - 1, W, T, ROWS>;
+  static_assert(sizeof(A0) == sizeof(float2) * S0::KB * S0::R, "first-stage registers");
+  static_assert(sizeof(AL) == sizeof(float2) * SL::KB * SL::R, "last-stage registers");
+#pragma unroll
+  for (int b = 0; b < S0::KB; ++b) Dft<S0::R>::run(v0[b], FWD ? -1.f : 1.f);
+  if constexpr (nstage(N) == 1) {
+#pragma unroll
+    for (int b = 0; b < S0::KB; ++b)
+#pragma unroll
+      for (int r = 0; r < S0::R; ++r) vl[b][r] = v0[b][r];
+  } else {
+    lds_scatter<S0, T, LD>(v0, lds, tid);
+    __syncthreads();
+    mid_stages<N, ORD, 1, W, T, ROWS, LD, FWD, TL>(lds, twl, tid);
+    lds_gather_bfly<SL, T, LD, FWD, TL>(vl, lds, twl, tid);
+  }
+}
+
+// Element index (returned) and line of value r of slot b in stage St.
+template <class St, int T>
+__device__ __forceinline__ int st_elem(int tid, int b, int r, int& c) {
+  int j;
+  St::map(tid + b * T, c, j);
+  return j + r * St::NBL;
+}
+
+template <class St, int W, int T>
+__device__ __forceinline__ void col_load_global(float2 (&v)[St::KB][St::R], const float2* __restrict__ src,
+                                                long es, int tid) {
+#pragma unroll
+  for (int b = 0; b < St::KB; ++b) {
+    const int t = tid + b * T;
+    int c, j;
+    St::map(t, c, j);
+    const float2* p = src + (long)j * es + c;
+#pragma unroll
+    for (int r = 0; r < St::R; ++r)
+      v[b][r] = St::ok(t) ? p[(long)r * St::NBL * es] : make_float2(0.f, 0.f);
+  }
+}
+
+// Last stage: element j + r NS (NS = N / R).
+template <class St, int W, int T>
+__device__ __forceinline__ void col_store_global(const float2 (&v)[St::KB][St::R], float2* dst, long es,
+                                                 int tid) {
+#pragma unroll
+  for (int b = 0; b < St::KB; ++b) {
+    const int t = tid + b * T;
+    if (St::ok(t)) {
+      int c, j;
+      St::map(t, c, j);
+      float2* p = dst + (long)j * es + c;
+#pragma unroll
+      for (int r = 0; r < St::R; ++r) p[(long)r * St::NS * es] = v[b][r];
+    }
+  }
+}
+
 template <int N, int MODE>
-__global__ __launch_bounds__(cols_threads(N, MODE), holds_regs(MODE) ? 4 : 1) void k_cols(
+__global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
     const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
     ColGeom g, const float2* __restrict__ tw, int mult, int ca, int cb, float scale,
     const float* __restrict__ amp, int y_is_plane_freq, const StepCoef* __restrict__ coef,
@@ -465,135 +558,239 @@ __global__ __launch_bounds__(cols_threads(N, MODE), holds_regs(MODE) ? 4 : 1) vo
   if constexpr (MODE == X_FWD_GREEN) {
     if (coef) scale = mock_ptr(coef, mstride)->gscale;
   }
-  constexpr int W = cols_w(N), LD = lds_ld(N), T = cols_threads(N, MODE);
-  constexpr int E = (W * N + T - 1) / T;
+  constexpr int W = fcols_w(N), LD = fld(N), T = fcols_threads(N), TL = ftw_len(N);
+  constexpr int NST = nstage(N);
   __shared__ float2 lds[W * LD];
-  __shared__ float2 twl[N / 2];
+  __shared__ float2 twl[TL];
   const uint32_t nblk = (uint32_t)g.nchunk * g.nplanes;
   const uint32_t bid = xcd_remap(blockIdx.x, nblk);
   const int p = bid / g.nchunk;
   const int c0 = (bid - p * g.nchunk) * W;
-  const long mofs = (long)blockIdx.y * mesh_stride;
-  const float2* src = in + mofs + p * g.plane_stride + c0;
-  // load: consecutive threads take consecutive columns
-  load_twiddles<N / 2, T>(twl, tw);
-  load_cols<N, W, LD, T>(lds, src, g.elem_stride);
-  __syncthreads();
+  const long es = g.elem_stride;
+  const long ofs = (long)blockIdx.y * mesh_stride + (long)p * g.plane_stride + c0;
+  const int tid = threadIdx.x;
   const int pfreq = y_is_plane_freq ? signed_freq(p, N) : 0;
+  using S0 = Stg<N, 0, 0, W, T, false>;
+  using SL = Stg<N, 0, NST - 1, W, T, false>;
+  float2 v[S0::KB][S0::R];
+  col_load_global<S0, W, T>(v, in + ofs, es, tid);
+  load_twiddles<TL, T>(twl, tw);
 
-  if constexpr (MODE == X_FWD || MODE == X_INV) {
-    lds_fft<N, W, LD, T, 1, MODE == X_FWD ? 1 : 0>(lds, twl);
-  } else if constexpr (MODE == X_FWD_AMP) {
-    lds_fft<N, W, LD, T, 1, 1>(lds, twl);
-    for (int i = threadIdx.x; i < N * W; i += T) {
-      const int c = i / N, e = i - c * N;
-      const float2 m = multiplier(0, 0, 0, 0, 0.f, signed_freq(e, N), pfreq, c0 + c, N, amp, 1);
-      lds[c * LD + pe(e)] = cmul(lds[c * LD + pe(e)], m);
+  if constexpr (MODE == X_FWD || MODE == X_INV || MODE == X_FWD_AMP || MODE == X_MULT_INV) {
+    if constexpr (MODE == X_MULT_INV) {
+#pragma unroll
+      for (int b = 0; b < S0::KB; ++b)
+#pragma unroll
+        for (int r = 0; r < S0::R; ++r) {
+          int c;
+          const int e = st_elem<S0, T>(tid, b, r, c);
+          v[b][r] = cmul(v[b][r], multiplier(mult, 0, ca, cb, scale, signed_freq(e, N), pfreq, c0 + c, N,
+                                             amp, 0));
+        }
     }
-    __syncthreads();
-  } else if constexpr (MODE == X_MULT_INV) {
-    for (int i = threadIdx.x; i < N * W; i += T) {
-      const int c = i / N, e = i - c * N;
-      const float2 m = multiplier(mult, 0, ca, cb, scale, signed_freq(e, N), pfreq, c0 + c, N, amp, 0);
-      lds[c * LD + pe(e)] = cmul(lds[c * LD + pe(e)], m);
+    float2 o[SL::KB][SL::R];
+    reg_fft<N, 0, W, T, false, LD, (MODE == X_FWD || MODE == X_FWD_AMP) ? 1 : 0, TL>(v, o, lds, twl, tid);
+    if constexpr (MODE == X_FWD_AMP) {
+#pragma unroll
+      for (int b = 0; b < SL::KB; ++b)
+#pragma unroll
+        for (int r = 0; r < SL::R; ++r) {
+          int c;
+          const int e = st_elem<SL, T>(tid, b, r, c);
+          o[b][r] = cmul(o[b][r], multiplier(0, 0, 0, 0, 0.f, signed_freq(e, N), pfreq, c0 + c, N, amp, 1));
+        }
     }
-    __syncthreads();
-    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
-  }
-
-  if constexpr (MODE == X_FWD_GREEN) {
+    col_store_global<SL, W, T>(o, out0 + ofs, es, tid);
+  } else if constexpr (MODE == X_FWD_GREEN) {
     // PM, x pass: forward along x gives S = DFT[delta]; with phi = scale S / |n|^2
     //   out0 = IDFT_x[i n_x phi]  (n_x on its Nyquist index -> 0)  -> g_x,
     //   out1 = IDFT_x[phi]                                         -> g_y, g_z
     // (n_y and n_z are constant along an x line; the y pass applies them).
-    lds_fft<N, W, LD, T, 1, 1>(lds, twl);
-    float2 phi[E];
+    using SI = Stg<N, 1, NST - 1, W, T, false>;
+    float2 f[SL::KB][SL::R];
+    reg_fft<N, 0, W, T, false, LD, 1, TL>(v, f, lds, twl, tid);
+    float2 u[SL::KB][SL::R];
 #pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int i = threadIdx.x + b * T;
-      if ((W * N) % T == 0 || i < N * W) {
-        const int c = i / N, e = i - c * N;
+    for (int b = 0; b < SL::KB; ++b)
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) {
+        int c;
+        const int e = st_elem<SL, T>(tid, b, r, c);
         const int nx = signed_freq(e, N), nz = c0 + c;
         const int n2 = nx * nx + pfreq * pfreq + nz * nz;
         const float inv = (n2 == 0 || nz > N / 2) ? 0.f : scale / (float)n2;
-        const float2 v = lds[c * LD + pe(e)];
-        phi[b] = make_float2(inv * v.x, inv * v.y);
+        f[b][r] = make_float2(inv * f[b][r].x, inv * f[b][r].y);
         const float kx = (nx == N / 2 || nx == -N / 2) ? 0.f : (float)nx;
-        lds[c * LD + pe(e)] = make_float2(-kx * phi[b].y, kx * phi[b].x);  // i n_x phi
+        u[b][r] = make_float2(-kx * f[b][r].y, kx * f[b][r].x);  // i n_x phi
       }
-    }
+    float2 o[SI::KB][SI::R];
     __syncthreads();
-    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
-    {
-      float2* dst = out0 + p * g.plane_stride + c0;
-      for (int i = threadIdx.x; i < N * W; i += T) {
-        const int e = i / W, c = i - e * W;
-        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
-      }
-    }
+    reg_fft<N, 1, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
+    col_store_global<SI, W, T>(o, out0 + ofs, es, tid);
     __syncthreads();
-#pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int i = threadIdx.x + b * T;
-      if ((W * N) % T == 0 || i < N * W) {
-        const int c = i / N, e = i - c * N;
-        lds[c * LD + pe(e)] = phi[b];
-      }
-    }
-    __syncthreads();
-    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
-    {
-      float2* dst = out1 + p * g.plane_stride + c0;
-      for (int i = threadIdx.x; i < N * W; i += T) {
-        const int e = i / W, c = i - e * W;
-        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
-      }
-    }
+    reg_fft<N, 1, W, T, false, LD, 0, TL>(f, o, lds, twl, tid);
+    col_store_global<SI, W, T>(o, out1 + ofs, es, tid);
   } else if constexpr (MODE == X_INV_GRAD_YZ) {
     // PM, inverse y pass of B = IDFT_x[phi]: out0 = IDFT_y[i n_y B], out1 =
     // IDFT_y[i n_z B] (each component zeroed on its own Nyquist index).
-    float2 bv[E];
+    float2 u[S0::KB][S0::R];
 #pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int i = threadIdx.x + b * T;
-      if ((W * N) % T == 0 || i < N * W) {
-        const int c = i / N, e = i - c * N;
-        const int ny = signed_freq(e, N);
+    for (int b = 0; b < S0::KB; ++b)
+#pragma unroll
+      for (int r = 0; r < S0::R; ++r) {
+        int c;
+        const int ny = signed_freq(st_elem<S0, T>(tid, b, r, c), N);
         const float ky = (ny == N / 2 || ny == -N / 2) ? 0.f : (float)ny;
-        bv[b] = lds[c * LD + pe(e)];
-        lds[c * LD + pe(e)] = make_float2(-ky * bv[b].y, ky * bv[b].x);  // i n_y B
+        u[b][r] = make_float2(-ky * v[b][r].y, ky * v[b][r].x);  // i n_y B
       }
-    }
-    __syncthreads();
-    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
-    {
-      float2* dst = out0 + p * g.plane_stride + c0;
-      for (int i = threadIdx.x; i < N * W; i += T) {
-        const int e = i / W, c = i - e * W;
-        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
-      }
-    }
-    __syncthreads();
+    float2 o[SL::KB][SL::R];
+    reg_fft<N, 0, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
+    col_store_global<SL, W, T>(o, out0 + ofs, es, tid);
 #pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int i = threadIdx.x + b * T;
-      if ((W * N) % T == 0 || i < N * W) {
-        const int c = i / N, e = i - c * N;
+    for (int b = 0; b < S0::KB; ++b)
+#pragma unroll
+      for (int r = 0; r < S0::R; ++r) {
+        int c;
+        st_elem<S0, T>(tid, b, r, c);
         const float kz = (c0 + c >= N / 2) ? 0.f : (float)(c0 + c);
-        lds[c * LD + pe(e)] = make_float2(-kz * bv[b].y, kz * bv[b].x);  // i n_z B
+        u[b][r] = make_float2(-kz * v[b][r].y, kz * v[b][r].x);  // i n_z B
       }
-    }
     __syncthreads();
-    lds_fft<N, W, LD, T, 1, 0>(lds, twl);
-    {
-      float2* dst = out1 + p * g.plane_stride + c0;
-      for (int i = threadIdx.x; i < N * W; i += T) {
-        const int e = i / W, c = i - e * W;
-        dst[e * g.elem_stride + c] = lds[c * LD + pe(e)];
-      }
+    reg_fft<N, 0, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
+    col_store_global<SL, W, T>(o, out1 + ofs, es, tid);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z passes: NL rows of N reals per workgroup (row stride `cols` complex),
+// through a length-H = N/2 complex transform of the pairs (x_2m, x_2m+1).
+
+// Forward: Z = DFT_H[x_2m + i x_2m+1], then the split step
+//   X_k = E_k + W_N^k O_k,  E = (Z_k + conj Z_{H-k})/2,  O = -i (Z_k - conj Z_{H-k})/2
+// for k = 0 .. H (columns beyond H are written as zeros).
+template <int N>
+__global__ __launch_bounds__(frows_threads(N), 4) void k_r2c_z(
+    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
+    long mstride) {
+  constexpr int H = N / 2, LD = fld(H), NL = frows_nl(N), T = frows_threads(N), TL = frows_tw_len(N);
+  using S0 = Stg<H, 0, 0, NL, T, true>;
+  using SL = Stg<H, 0, nstage(H) - 1, NL, T, true>;
+  mesh = mock_ptr(mesh, mstride);
+  __shared__ float2 lds[NL * LD];
+  __shared__ float2 twl[TL];
+  float2* base = mesh + blockIdx.y * mesh_stride;
+  const long r0 = (long)blockIdx.x * NL;
+  const int tid = threadIdx.x;
+  float2 v[S0::KB][S0::R];
+#pragma unroll
+  for (int b = 0; b < S0::KB; ++b) {
+    const int t = tid + b * T;
+    int l, j;
+    S0::map(t, l, j);
+    const bool in = S0::ok(t) && r0 + l < nrows;
+    const float2* p = base + (r0 + l) * cols + j;
+#pragma unroll
+    for (int r = 0; r < S0::R; ++r) v[b][r] = in ? p[r * S0::NBL] : make_float2(0.f, 0.f);
+  }
+  load_twiddles<TL, T>(twl, tw);
+  float2 z[SL::KB][SL::R];
+  reg_fft<H, 0, NL, T, true, LD, 1, TL>(v, z, lds, twl, tid);
+  __syncthreads();
+  // Z in natural order: element e of row l at lds[l * LD + e]
+#pragma unroll
+  for (int b = 0; b < SL::KB; ++b) {
+    const int t = tid + b * T;
+    if (SL::ok(t)) {
+      int l, j;
+      SL::map(t, l, j);
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) lds[l * LD + j + r * SL::NS] = z[b][r];
     }
-  } else {
-    store_cols<N, W, LD, T>(out0 + mofs + p * g.plane_stride + c0, g.elem_stride, lds);
+  }
+  __syncthreads();
+  constexpr int COLS = pcols(N), NO = NL * COLS, KO = (NO + T - 1) / T;
+  float2 xs[KO];
+#pragma unroll
+  for (int q = 0; q < KO; ++q) {
+    const int i = tid + q * T;
+    const int l = i / COLS, k = i - l * COLS;
+    xs[q] = make_float2(0.f, 0.f);
+    if ((NO % T == 0 || i < NO) && k <= H) {
+      const float2 a = lds[l * LD + (k == H ? 0 : k)];
+      float2 c = lds[l * LD + (k == 0 ? 0 : H - k)];
+      c.y = -c.y;
+      const float2 e = make_float2(0.5f * (a.x + c.x), 0.5f * (a.y + c.y));
+      const float2 o = make_float2(0.5f * (a.y - c.y), -0.5f * (a.x - c.x));
+      xs[q] = cadd(e, cmul(tw_at<N, TL>(twl, k), o));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KO; ++q) {
+    const int i = tid + q * T;
+    const int l = i / COLS, k = i - l * COLS;
+    if ((NO % T == 0 || i < NO) && r0 + l < nrows) base[(r0 + l) * COLS + k] = xs[q];
+  }
+}
+
+// Inverse: half spectrum (H+1 values) -> N reals, unnormalised.  The first
+// stage's inputs are formed in registers from X_k and X_{H-k}:
+//   Z'_k = (X_k + conj X_{H-k}) + i (X_k - conj X_{H-k}) exp(+2 pi i k / N),
+// and z = IDFT_H[Z'] holds the pairs (x_2m, x_2m+1).
+template <int N>
+__global__ __launch_bounds__(frows_threads(N), 4) void k_c2r_z(
+    float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
+    long mstride) {
+  constexpr int H = N / 2, LD = fld(H), NL = frows_nl(N), T = frows_threads(N), TL = frows_tw_len(N);
+  using S0 = Stg<H, 0, 0, NL, T, true>;
+  using SL = Stg<H, 0, nstage(H) - 1, NL, T, true>;
+  mesh = mock_ptr(mesh, mstride);
+  __shared__ float2 lds[NL * LD];
+  __shared__ float2 twl[TL];
+  float2* base = mesh + blockIdx.y * mesh_stride;
+  const long r0 = (long)blockIdx.x * NL;
+  const int tid = threadIdx.x;
+  float2 xa[S0::KB][S0::R], xb[S0::KB][S0::R];
+#pragma unroll
+  for (int b = 0; b < S0::KB; ++b) {
+    const int t = tid + b * T;
+    int l, j;
+    S0::map(t, l, j);
+    const bool in = S0::ok(t) && r0 + l < nrows;
+    const float2* p = base + (r0 + l) * cols;
+#pragma unroll
+    for (int r = 0; r < S0::R; ++r) {
+      const int k = j + r * S0::NBL;
+      xa[b][r] = in ? p[k] : make_float2(0.f, 0.f);
+      xb[b][r] = in ? p[H - k] : make_float2(0.f, 0.f);
+    }
+  }
+  load_twiddles<TL, T>(twl, tw);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < S0::KB; ++b) {
+    int l, j;
+    S0::map(tid + b * T, l, j);
+#pragma unroll
+    for (int r = 0; r < S0::R; ++r) {
+      const int k = j + r * S0::NBL;
+      const float2 cb = make_float2(xb[b][r].x, -xb[b][r].y);
+      const float2 e = cadd(xa[b][r], cb);
+      const float2 o = cmulc(csub(xa[b][r], cb), tw_at<N, TL>(twl, k));
+      xa[b][r] = cadd(e, make_float2(-o.y, o.x));
+    }
+  }
+  float2 z[SL::KB][SL::R];
+  reg_fft<H, 0, NL, T, true, LD, 0, TL>(xa, z, lds, twl, tid);
+#pragma unroll
+  for (int b = 0; b < SL::KB; ++b) {
+    const int t = tid + b * T;
+    int l, j;
+    SL::map(t, l, j);
+    if (SL::ok(t) && r0 + l < nrows) {
+      float2* p = base + (r0 + l) * cols + j;
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) p[r * SL::NS] = z[b][r];
+    }
   }
 }
 
@@ -714,7 +911,7 @@ ColGeom geom(int n, int w, int axis) {
 template <int N>
 void r2c_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s, int nmock,
            long mstride) {
-  constexpr int NL = rows_nl(N / 2), T = threads_for(NL * (N / 2));
+  constexpr int NL = frows_nl(N), T = frows_threads(N);
   const long nrows = (long)N * N;
   dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch, (unsigned)nmock);
   hipLaunchKernelGGL(k_r2c_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw,
@@ -724,7 +921,7 @@ void r2c_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStre
 template <int N>
 void c2r_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s, int nmock,
            long mstride) {
-  constexpr int NL = rows_nl(N / 2), T = threads_for(NL * (N / 2));
+  constexpr int NL = frows_nl(N), T = frows_threads(N);
   const long nrows = (long)N * N;
   dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch, (unsigned)nmock);
   hipLaunchKernelGGL(k_c2r_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw,
@@ -735,33 +932,33 @@ template <int N>
 void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbatch, long mesh_stride,
             const float2* tw, int mult, int ca, int cb, float scale, const float* amp, hipStream_t s,
             const StepCoef* coef = nullptr, int nmock = 1, long mstride = 0) {
-  constexpr int W = cols_w(N);
+  constexpr int W = fcols_w(N);
   const ColGeom g = geom(N, W, axis);
   dim3 grid((unsigned)(g.nchunk * g.nplanes), (unsigned)nbatch, (unsigned)nmock);
   const int yf = axis == 0 ? 1 : 0;
   switch (mode) {
     case X_FWD:
-      hipLaunchKernelGGL((k_cols<N, X_FWD>), grid, dim3(cols_threads(N, X_FWD)), 0, s, in, out[0], nullptr, nullptr,
+      hipLaunchKernelGGL((k_cols<N, X_FWD>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
                          mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
       break;
     case X_INV:
-      hipLaunchKernelGGL((k_cols<N, X_INV>), grid, dim3(cols_threads(N, X_INV)), 0, s, in, out[0], nullptr, nullptr,
+      hipLaunchKernelGGL((k_cols<N, X_INV>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
                          mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
       break;
     case X_FWD_AMP:
-      hipLaunchKernelGGL((k_cols<N, X_FWD_AMP>), grid, dim3(cols_threads(N, X_FWD_AMP)), 0, s, in, out[0], nullptr, nullptr,
+      hipLaunchKernelGGL((k_cols<N, X_FWD_AMP>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
                          mesh_stride, g, tw, 0, 0, 0, 1.f, amp, yf, nullptr, mstride);
       break;
     case X_MULT_INV:
-      hipLaunchKernelGGL((k_cols<N, X_MULT_INV>), grid, dim3(cols_threads(N, X_MULT_INV)), 0, s, in, out[0], nullptr, nullptr,
+      hipLaunchKernelGGL((k_cols<N, X_MULT_INV>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
                          mesh_stride, g, tw, mult, ca, cb, scale, nullptr, yf, nullptr, mstride);
       break;
     case X_FWD_GREEN:
-      hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN>), grid, dim3(cols_threads(N, X_FWD_GREEN)), 0, s, in, out[0], out[1], nullptr,
+      hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], out[1], nullptr,
                          mesh_stride, g, tw, M_GRAD, 0, 0, scale, nullptr, yf, coef, mstride);
       break;
     case X_INV_GRAD_YZ:
-      hipLaunchKernelGGL((k_cols<N, X_INV_GRAD_YZ>), grid, dim3(cols_threads(N, X_INV_GRAD_YZ)), 0, s, in, out[0], out[1], nullptr,
+      hipLaunchKernelGGL((k_cols<N, X_INV_GRAD_YZ>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], out[1], nullptr,
                          mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
       break;
   }
