@@ -546,6 +546,8 @@ __device__ __forceinline__ void col_store_global(const float2 (&v)[St::KB][St::R
   }
 }
 
+constexpr int kPlainOrd = 1;
+
 template <int N, int MODE>
 __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
     const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
@@ -570,8 +572,10 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
   const long ofs = (long)blockIdx.y * mesh_stride + (long)p * g.plane_stride + c0;
   const int tid = threadIdx.x;
   const int pfreq = y_is_plane_freq ? signed_freq(p, N) : 0;
-  using S0 = Stg<N, 0, 0, W, T, false>;
-  using SL = Stg<N, 0, NST - 1, W, T, false>;
+  // plain transforms: order kPlainOrd; the others start in order 0
+  constexpr int O0 = (MODE == X_FWD || MODE == X_INV) ? kPlainOrd : 0;
+  using S0 = Stg<N, O0, 0, W, T, false>;
+  using SL = Stg<N, O0, NST - 1, W, T, false>;
   float2 v[S0::KB][S0::R];
   col_load_global<S0, W, T>(v, in + ofs, es, tid);
   load_twiddles<TL, T>(twl, tw);
@@ -589,7 +593,7 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
         }
     }
     float2 o[SL::KB][SL::R];
-    reg_fft<N, 0, W, T, false, LD, (MODE == X_FWD || MODE == X_FWD_AMP) ? 1 : 0, TL>(v, o, lds, twl, tid);
+    reg_fft<N, O0, W, T, false, LD, (MODE == X_FWD || MODE == X_FWD_AMP) ? 1 : 0, TL>(v, o, lds, twl, tid);
     if constexpr (MODE == X_FWD_AMP) {
 #pragma unroll
       for (int b = 0; b < SL::KB; ++b)
@@ -618,7 +622,8 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
         const int e = st_elem<SL, T>(tid, b, r, c);
         const int nx = signed_freq(e, N), nz = c0 + c;
         const int n2 = nx * nx + pfreq * pfreq + nz * nz;
-        const float inv = (n2 == 0 || nz > N / 2) ? 0.f : scale / (float)n2;
+        // hardware reciprocal (within 1 ulp): one instruction instead of a division
+        const float inv = (n2 == 0 || nz > N / 2) ? 0.f : scale * __builtin_amdgcn_rcpf((float)n2);
         f[b][r] = make_float2(inv * f[b][r].x, inv * f[b][r].y);
         const float kx = (nx == N / 2 || nx == -N / 2) ? 0.f : (float)nx;
         u[b][r] = make_float2(-kx * f[b][r].y, kx * f[b][r].x);  // i n_x phi

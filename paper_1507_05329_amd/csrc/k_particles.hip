@@ -14,6 +14,10 @@
 
 namespace cola {
 
+// FORCE_ONLY: write the interpolated force (no kick or drift).  Otherwise
+// the particle's state is requested together with its displacement, so its
+// loads are in flight during the mesh gathers.
+template <bool FORCE_ONLY>
 __global__ __launch_bounds__(256) void k_readout_kick_drift(
     const float* __restrict__ g0, const float* __restrict__ g1, const float* __restrict__ g2,
     long row_stride, float* __restrict__ disp, float* __restrict__ vres,
@@ -26,10 +30,18 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
   g1 = mock_ptr(g1, mstride);
   g2 = mock_ptr(g2, mstride);
   disp = mock_ptr(disp, mstride);
-  vres = mock_ptr(vres, mstride);
-  psi1 = mock_ptr(psi1, mstride);
-  psi2 = mock_ptr(psi2, mstride);
-  if (force_out) force_out = mock_ptr(force_out, mstride);
+  float v0[3], p1[3], p2[3];
+  if constexpr (!FORCE_ONLY) {
+    vres = mock_ptr(vres, mstride);
+    psi1 = mock_ptr(psi1, mstride);
+    psi2 = mock_ptr(psi2, mstride);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      v0[d] = vres[d * np3 + i];
+      p1[d] = psi1[d * np3 + i];
+      p2[d] = psi2[d * np3 + i];
+    }
+  }
   int c[3];
   float f[3];
   const float dscale = 1.0f;
@@ -48,19 +60,19 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
 #pragma unroll
     for (int d = 0; d < 3; ++d) F[d] += w * g[d][idx];
   }
-  if (force_out) {
+  if constexpr (FORCE_ONLY) {
+    force_out = mock_ptr(force_out, mstride);
 #pragma unroll
     for (int d = 0; d < 3; ++d) force_out[d * np3 + i] = F[d];
-    return;
-  }
-  const KickDrift kd = mock_ptr(coef, mstride)->kd;
+  } else {
+    const KickDrift kd = mock_ptr(coef, mstride)->kd;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const long j = d * np3 + i;
-    const float p1 = psi1[j], p2 = psi2[j];
-    const float v = vres[j] + kd.K * F[d] - kd.c1 * p1 - kd.c2 * p2;
-    vres[j] = v;
-    disp[j] = disp[j] + kd.I * v + kd.e1 * p1 + kd.e2 * p2;
+    for (int d = 0; d < 3; ++d) {
+      const long j = d * np3 + i;
+      const float v = v0[d] + kd.K * F[d] - kd.c1 * p1[d] - kd.c2 * p2[d];
+      vres[j] = v;
+      disp[j] = disp[j] + kd.I * v + kd.e1 * p1[d] + kd.e2 * p2[d];
+    }
   }
 }
 
@@ -69,9 +81,13 @@ void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2
                                int np, int nm, const StepCoef* coef, float* force_out,
                                hipStream_t s, int nmock, long mstride) {
   const long np3 = (long)np * np * np;
-  hipLaunchKernelGGL(k_readout_kick_drift, dim3((unsigned)((np3 + 255) / 256), 1, (unsigned)nmock),
-                     dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2, np, nm, np3, coef,
-                     force_out, mstride);
+  const dim3 grid((unsigned)((np3 + 255) / 256), 1, (unsigned)nmock);
+  if (force_out)
+    hipLaunchKernelGGL(k_readout_kick_drift<true>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres,
+                       psi1, psi2, np, nm, np3, coef, force_out, mstride);
+  else
+    hipLaunchKernelGGL(k_readout_kick_drift<false>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp,
+                       vres, psi1, psi2, np, nm, np3, coef, force_out, mstride);
 }
 
 __global__ void k_set_coef(StepCoef* dst, StepCoef v, long mstride) { *mock_ptr(dst, mstride) = v; }
