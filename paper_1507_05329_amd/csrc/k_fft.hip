@@ -370,6 +370,11 @@ constexpr int fcols_w(int n) {
 }
 constexpr int ftw_len(int n) { return fcols_w(n) * fld(n) * 8 + n * 8 <= kLdsLimit ? n : n / 2; }
 constexpr int fcols_threads(int n) { return threads_for(fcols_w(n) * n); }
+// Waves per SIMD the register budget must allow: two 1024-thread workgroups per CU.
+constexpr int min_waves(int t) { return t >= 1024 ? 8 : 4; }
+// The order whose first stage has the smaller radix, i.e. the more
+// butterflies to spread a pass's HBM loads over.
+constexpr int lo_first(int n) { return rad_o(n, 0, 0) <= rad_o(n, 1, 0) ? 0 : 1; }
 // z passes: NL rows of n reals, i.e. of h = n/2 complex values; the twiddle
 // table has period n (the transform of length h takes every second entry).
 constexpr int frows_nl(int n) {
@@ -378,7 +383,12 @@ constexpr int frows_nl(int n) {
   return nl;
 }
 constexpr int frows_tw_len(int n) { return frows_nl(n) * fld(n / 2) * 8 + n * 8 <= kLdsLimit ? n : n / 2; }
-constexpr int frows_threads(int n) { return threads_for(frows_nl(n) * (n / 2)); }
+// 1024 threads where that leaves 6 values per thread (the register budget of
+// two such workgroups per CU; measured on the 768 mesh: r2c 0.72 against
+// 0.75 ms, c2r 2.25 against 2.28 ms on 512 threads).
+constexpr int frows_threads(int n) {
+  return frows_nl(n) * (n / 2) == 6144 ? 1024 : threads_for(frows_nl(n) * (n / 2));
+}
 
 // exp(-2 pi i m / NT) from an LDS table of TL = NT or NT / 2 entries.
 template <int NT, int TL>
@@ -572,8 +582,11 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
   const long ofs = (long)blockIdx.y * mesh_stride + (long)p * g.plane_stride + c0;
   const int tid = threadIdx.x;
   const int pfreq = y_is_plane_freq ? signed_freq(p, N) : 0;
-  // plain transforms: order kPlainOrd; the others start in order 0
-  constexpr int O0 = (MODE == X_FWD || MODE == X_INV) ? kPlainOrd : 0;
+  // plain transforms in order kPlainOrd; the others start in the order
+  // with the smaller first radix (the Green pass returns in the other one),
+  // except the gradient y pass at 2048 (that order spills registers there)
+  constexpr int O0 = (MODE == X_FWD || MODE == X_INV) ? kPlainOrd
+                     : (MODE == X_INV_GRAD_YZ && N >= 2048) ? 0 : lo_first(N);
   using S0 = Stg<N, O0, 0, W, T, false>;
   using SL = Stg<N, O0, NST - 1, W, T, false>;
   float2 v[S0::KB][S0::R];
@@ -610,9 +623,9 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
     //   out0 = IDFT_x[i n_x phi]  (n_x on its Nyquist index -> 0)  -> g_x,
     //   out1 = IDFT_x[phi]                                         -> g_y, g_z
     // (n_y and n_z are constant along an x line; the y pass applies them).
-    using SI = Stg<N, 1, NST - 1, W, T, false>;
+    using SI = Stg<N, 1 - O0, NST - 1, W, T, false>;
     float2 f[SL::KB][SL::R];
-    reg_fft<N, 0, W, T, false, LD, 1, TL>(v, f, lds, twl, tid);
+    reg_fft<N, O0, W, T, false, LD, 1, TL>(v, f, lds, twl, tid);
     float2 u[SL::KB][SL::R];
 #pragma unroll
     for (int b = 0; b < SL::KB; ++b)
@@ -630,10 +643,10 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
       }
     float2 o[SI::KB][SI::R];
     __syncthreads();
-    reg_fft<N, 1, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
+    reg_fft<N, 1 - O0, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
     col_store_global<SI, W, T>(o, out0 + ofs, es, tid);
     __syncthreads();
-    reg_fft<N, 1, W, T, false, LD, 0, TL>(f, o, lds, twl, tid);
+    reg_fft<N, 1 - O0, W, T, false, LD, 0, TL>(f, o, lds, twl, tid);
     col_store_global<SI, W, T>(o, out1 + ofs, es, tid);
   } else if constexpr (MODE == X_INV_GRAD_YZ) {
     // PM, inverse y pass of B = IDFT_x[phi]: out0 = IDFT_y[i n_y B], out1 =
@@ -649,7 +662,7 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
         u[b][r] = make_float2(-ky * v[b][r].y, ky * v[b][r].x);  // i n_y B
       }
     float2 o[SL::KB][SL::R];
-    reg_fft<N, 0, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
+    reg_fft<N, O0, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
     col_store_global<SL, W, T>(o, out0 + ofs, es, tid);
 #pragma unroll
     for (int b = 0; b < S0::KB; ++b)
@@ -661,7 +674,7 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
         u[b][r] = make_float2(-kz * v[b][r].y, kz * v[b][r].x);  // i n_z B
       }
     __syncthreads();
-    reg_fft<N, 0, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
+    reg_fft<N, O0, W, T, false, LD, 0, TL>(u, o, lds, twl, tid);
     col_store_global<SL, W, T>(o, out1 + ofs, es, tid);
   }
 }
@@ -674,12 +687,13 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
 //   X_k = E_k + W_N^k O_k,  E = (Z_k + conj Z_{H-k})/2,  O = -i (Z_k - conj Z_{H-k})/2
 // for k = 0 .. H (columns beyond H are written as zeros).
 template <int N>
-__global__ __launch_bounds__(frows_threads(N), 4) void k_r2c_z(
+__global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void k_r2c_z(
     float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
     long mstride) {
   constexpr int H = N / 2, LD = fld(H), NL = frows_nl(N), T = frows_threads(N), TL = frows_tw_len(N);
-  using S0 = Stg<H, 0, 0, NL, T, true>;
-  using SL = Stg<H, 0, nstage(H) - 1, NL, T, true>;
+  constexpr int OR = lo_first(H);
+  using S0 = Stg<H, OR, 0, NL, T, true>;
+  using SL = Stg<H, OR, nstage(H) - 1, NL, T, true>;
   mesh = mock_ptr(mesh, mstride);
   __shared__ float2 lds[NL * LD];
   __shared__ float2 twl[TL];
@@ -699,7 +713,7 @@ __global__ __launch_bounds__(frows_threads(N), 4) void k_r2c_z(
   }
   load_twiddles<TL, T>(twl, tw);
   float2 z[SL::KB][SL::R];
-  reg_fft<H, 0, NL, T, true, LD, 1, TL>(v, z, lds, twl, tid);
+  reg_fft<H, OR, NL, T, true, LD, 1, TL>(v, z, lds, twl, tid);
   __syncthreads();
   // Z in natural order: element e of row l at lds[l * LD + e]
 #pragma unroll
@@ -742,12 +756,13 @@ __global__ __launch_bounds__(frows_threads(N), 4) void k_r2c_z(
 //   Z'_k = (X_k + conj X_{H-k}) + i (X_k - conj X_{H-k}) exp(+2 pi i k / N),
 // and z = IDFT_H[Z'] holds the pairs (x_2m, x_2m+1).
 template <int N>
-__global__ __launch_bounds__(frows_threads(N), 4) void k_c2r_z(
+__global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void k_c2r_z(
     float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
     long mstride) {
   constexpr int H = N / 2, LD = fld(H), NL = frows_nl(N), T = frows_threads(N), TL = frows_tw_len(N);
-  using S0 = Stg<H, 0, 0, NL, T, true>;
-  using SL = Stg<H, 0, nstage(H) - 1, NL, T, true>;
+  constexpr int OR = lo_first(H);
+  using S0 = Stg<H, OR, 0, NL, T, true>;
+  using SL = Stg<H, OR, nstage(H) - 1, NL, T, true>;
   mesh = mock_ptr(mesh, mstride);
   __shared__ float2 lds[NL * LD];
   __shared__ float2 twl[TL];
@@ -785,7 +800,7 @@ __global__ __launch_bounds__(frows_threads(N), 4) void k_c2r_z(
     }
   }
   float2 z[SL::KB][SL::R];
-  reg_fft<H, 0, NL, T, true, LD, 0, TL>(xa, z, lds, twl, tid);
+  reg_fft<H, OR, NL, T, true, LD, 0, TL>(xa, z, lds, twl, tid);
 #pragma unroll
   for (int b = 0; b < SL::KB; ++b) {
     const int t = tid + b * T;
