@@ -47,6 +47,7 @@ struct DepShared {
   uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
   uint32_t seg_pre[kMaxSeg];              // particles in the segments before
   uint32_t seg_total;
+  uint32_t offs[8][9];                    // bucket offsets of the 8 source tiles
   int nseg;
   int nrun;
   uint32_t count;
@@ -389,19 +390,27 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
   const int t0[3] = {tx * kTile, ty * kTile, tz * kTile};
 
-  // Segments: thread nb < 8 handles the neighbour tile (tx-dx, ty-dy, tz-dz),
-  // taking the buckets whose face class covers the required offset bits.
-  if (threadIdx.x < 8) {
-    const int nb = threadIdx.x;
+  // Bucket offsets of the source tiles (tx-dx, ty-dy, tz-dz), one per thread.
+  if (threadIdx.x < 72) {
+    const int nb = threadIdx.x / 9, q = threadIdx.x - nb * 9;
     const int dx = (nb >> 2) & 1, dy = (nb >> 1) & 1, dz = nb & 1;
     int ux = tx - dx, uy = ty - dy, uz = tz - dz;
     if (ux < 0) ux += nt;
     if (uy < 0) uy += nt;
     if (uz < 0) uz += nt;
-    const uint32_t tn = ((uint32_t)ux * nt + uy) * nt + uz;
+    sh.offs[nb][q] = off[(((uint32_t)ux * nt + uy) * nt + uz) * 8u + q];
+  }
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sh.rho[q][i] = 0.0f;
+  __syncthreads();
+  // Segments: thread nb < 8 takes the buckets of source tile nb whose face
+  // class covers the required offset bits.
+  if (threadIdx.x < 8) {
+    const int nb = threadIdx.x;
     uint32_t o[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) o[q] = off[tn * 8u + q];
+    for (int q = 0; q < 9; ++q) o[q] = sh.offs[nb][q];
     int slot = nb * 4;
     int cls = 0;
     while (cls < 8) {
@@ -415,23 +424,30 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
     }
     for (; slot < nb * 4 + 4; ++slot) sh.seg_len[slot] = 0;
   }
-  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT)
-#pragma unroll
-    for (int q = 0; q < NC; ++q) sh.rho[q][i] = 0.0f;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int ns = 0;
-    uint32_t tot = 0;
-    for (int q = 0; q < kMaxSeg; ++q)
-      if (sh.seg_len[q] > 0) {
-        sh.seg_start[ns] = sh.seg_start[q];
-        sh.seg_len[ns] = sh.seg_len[q];
-        sh.seg_pre[ns] = tot;
-        tot += sh.seg_len[q];
-        ++ns;
-      }
-    sh.nseg = ns;
-    sh.seg_total = tot;
+  // Drop the empty segments, keeping their order (one wave: ballot for the
+  // positions, a lane scan for the particles before each segment).
+  if (threadIdx.x < 64) {
+    const int q = threadIdx.x;
+    const uint32_t len = q < kMaxSeg ? sh.seg_len[q] : 0u;
+    const uint32_t st = q < kMaxSeg ? sh.seg_start[q] : 0u;
+    const uint64_t mask = __ballot(len > 0);
+    uint32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t a = __shfl_up(incl, o, 64);
+      if (q >= o) incl += a;
+    }
+    if (len > 0) {
+      const int pos = __popcll(mask & ((1ull << q) - 1ull));
+      sh.seg_start[pos] = st;
+      sh.seg_len[pos] = len;
+      sh.seg_pre[pos] = incl - len;
+    }
+    if (q == 63) {
+      sh.nseg = __popcll(mask);
+      sh.seg_total = incl;
+    }
   }
   __syncthreads();
 
