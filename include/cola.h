@@ -148,10 +148,11 @@ int cola_set_state(cola_ctx* ctx, const float* dev_disp, const float* dev_vres,
                    const float* dev_psi1, const float* dev_psi2, double a_x, double a_v);
 
 /* In-place 3D real FFT on the context's FFT engine: dev_mesh holds an
- * n^3 real field in padded rows of 2 (n/2 + 1) floats (n one of np, nmesh);
- * forward (inverse = 0) leaves the unnormalised half spectrum
- * [x][y][0..n/2] as interleaved complex; inverse (1) maps it back without
- * the 1/n^3 factor. */
+ * n^3 real field in padded rows of 2 c floats, c = n/2 + 1 rounded up to a
+ * multiple of 16 (n one of np, nmesh); forward (inverse = 0) leaves the
+ * unnormalised half spectrum [x][y][0..n/2] as interleaved complex (the
+ * columns beyond n/2 of a row are zero); inverse (1) maps it back without
+ * the 1/n^3 factor; the real result depends only on columns 0 .. n/2. */
 int cola_fft3d(cola_ctx* ctx, int32_t n, float* dev_mesh, int32_t inverse);
 
 /* ---- Reverse mode (adjoint).  Cotangents are float32 device arrays in the

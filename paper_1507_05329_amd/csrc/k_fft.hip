@@ -953,7 +953,13 @@ void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbat
             const float2* tw, int mult, int ca, int cb, float scale, const float* amp, hipStream_t s,
             const StepCoef* coef = nullptr, int nmock = 1, long mstride = 0) {
   constexpr int W = fcols_w(N);
-  const ColGeom g = geom(N, W, axis);
+  ColGeom g = geom(N, W, axis);
+  // The Green pass takes only the column blocks that hold a frequency
+  // 0 .. N/2 (the rest of a padded row is never read; the passes after it
+  // transform whatever is there, column by column).  Measured on the 768
+  // mesh: 1.71 against 1.77 ms; the same trim slows the other column passes
+  // and the c2r pass that follows (rows no longer written in whole lines).
+  if (mode == X_FWD_GREEN) g.nchunk = (N / 2 + 1 + W - 1) / W;
   dim3 grid((unsigned)(g.nchunk * g.nplanes), (unsigned)nbatch, (unsigned)nmock);
   const int yf = axis == 0 ? 1 : 0;
   switch (mode) {
