@@ -1,13 +1,16 @@
 // 3D real-to-complex FFT for the PM solver (Koda et al. 2015, Sec. 2.3: FFTs
-// dominate the run time), written as a mixed-radix Stockham autosort FFT
-// staged through LDS.  A 3D transform is three passes over HBM:
+// dominate the run time), written as a mixed-radix Stockham autosort FFT.
+// A 3D transform is three passes over HBM:
 //   z (contiguous rows): real-to-complex by a half-length complex FFT plus
 //     the split step, in place in rows of padded_cols(n) complex values;
-//   y and x (strided): a workgroup loads W adjacent columns x n elements
-//     (W-wide contiguous runs), transforms them in LDS and writes back.
-// The x pass also hosts the k-space multipliers: the PM Green's function
-// times i k (three outputs from one forward transform), and the 2LPT
-// multipliers of the initial conditions.
+//   y and x (strided): a workgroup takes W adjacent columns x n elements
+//     (W-wide contiguous runs) and transforms them.
+// Inside a pass the first stage's inputs come straight from HBM into
+// registers and the last stage's outputs go straight back; only the stage
+// boundaries in between are exchanged through LDS.  The x pass also hosts
+// the k-space multipliers: the PM Green's function times i k (two outputs
+// from one forward transform), the 2LPT multipliers of the initial
+// conditions and the adjoint's combinations.
 //
 // Stockham stage with radix R on a line of length L after Ns = product of
 // earlier radices: butterfly j (0 <= j < L/R) reads x[j + r L/R], applies
@@ -33,27 +36,12 @@ constexpr int radix_at(int n, int s) {
   return (m == 1 && s < ns) ? r[s] : 0;
 }
 constexpr int nstage(int n) { int s = 0; while (radix_at(n, s)) ++s; return s; }
-constexpr int ns_before(int n, int s) { int p = 1; for (int i = 0; i < s; ++i) p *= radix_at(n, i); return p; }
 
-// LDS line layout: element e of a line sits at pe(e) = e + e/32 (one pad
-// slot after every 32), so the stride-R writes of a Stockham stage spread
-// over the banks; lines are lds_ld(n) apart (odd, for the column loads).
-constexpr int lds_ld(int n) { return n + n / 32 + 1; }
-__device__ __forceinline__ int pe(int e) { return e + (e >> 5); }
-
-// Launch shapes: at most 80 KB of LDS per workgroup, 256 threads below
-// 4096 staged complex values, 512 from 4096 (measured on the 768 mesh: the
-// row and column passes run 8-18% faster on 512 threads than on 256).
+// Launch shapes: at most 80 KB of LDS per workgroup; 256 threads below 4096
+// staged complex values, 512 from 4096 (measured on the 768 mesh: the row
+// and column passes run 8-18% faster on 512 threads than on 256).
 constexpr int kLdsLimit = 80 * 1024;
-constexpr int cols_w(int n) { int w = 16; while (w > 1 && w * lds_ld(n) * 8 + n * 4 > kLdsLimit) w /= 2; return w; }
-constexpr int rows_nl(int h) { int nl = 16; while (nl > 1 && nl * lds_ld(h) * 8 + h * 8 > kLdsLimit) nl /= 2; return nl; }
 constexpr int threads_for(int elems) { return elems >= 4096 ? 512 : 256; }
-// The two gradient passes keep a spectrum in registers across a transform:
-// spread it over 512 threads, and cap them at 128 VGPRs (4 waves per SIMD).
-constexpr bool holds_regs(int mode) { return mode == X_FWD_GREEN || mode == X_INV_GRAD_YZ; }
-constexpr int cols_threads(int n, int mode) {
-  return (holds_regs(mode) && cols_w(n) * n >= 4096) ? 512 : threads_for(cols_w(n) * n);
-}
 
 bool make_plan(int n, FftPlan* plan) {
   if (n < 2 || nstage(n) == 0) return false;
@@ -147,55 +135,6 @@ __device__ __forceinline__ float2 tw_get(const float2* __restrict__ twl, int m) 
   return make_float2(-w.x, -w.y);
 }
 
-// Stages S.. of a length-N transform of NL lines (line l at buf[l * LD]), T
-// threads, twiddle table stride TWS, FWD = 1 forward / 0 inverse.
-template <int N, int NL, int LD, int T, int TWS, int FWD, int S>
-__device__ __forceinline__ void fft_stages(float2* __restrict__ buf, const float2* __restrict__ tw,
-                                           int tid) {
-  if constexpr (S < nstage(N)) {
-    constexpr int R = radix_at(N, S), NS = ns_before(N, S);
-    constexpr int NBL = N / R, NBF = NBL * NL, KB = (NBF + T - 1) / T;
-    constexpr int STEP = (N / (NS * R)) * TWS;
-    constexpr float sgn = FWD ? -1.f : 1.f;
-    float2 v[KB][R];
-#pragma unroll
-    for (int b = 0; b < KB; ++b) {
-      const int t = tid + b * T;
-      if (NBF % T == 0 || t < NBF) {
-        const int l = t / NBL, j = t - l * NBL;
-        const float2* src = buf + l * LD;
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[b][r] = src[pe(j + r * NBL)];
-        if constexpr (NS > 1) {
-          const int k = j % NS;
-#pragma unroll
-          for (int r = 1; r < R; ++r) {
-            float2 w = tw_get<N * TWS>(tw, r * k * STEP);  // exp(-2 pi i m / n)
-            if (!FWD) w.y = -w.y;         // inverse: conjugate
-            v[b][r] = cmul(v[b][r], w);
-          }
-        }
-        Dft<R>::run(v[b], sgn);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < KB; ++b) {
-      const int t = tid + b * T;
-      if (NBF % T == 0 || t < NBF) {
-        const int l = t / NBL, j = t - l * NBL;
-        const int k = j % NS;
-        float2* dst = buf + l * LD;
-        const int o = (j - k) * R + k;
-#pragma unroll
-        for (int r = 0; r < R; ++r) dst[pe(o + r * NS)] = v[b][r];
-      }
-    }
-    __syncthreads();
-    fft_stages<N, NL, LD, T, TWS, FWD, S + 1>(buf, tw, tid);
-  }
-}
-
 // threadIdx.x through an empty asm: the compiler cannot prove two such
 // values equal, so address arithmetic derived from them is not shared.
 __device__ __forceinline__ int opaque_tid() {
@@ -204,17 +143,8 @@ __device__ __forceinline__ int opaque_tid() {
   return t;
 }
 
-// tid: the thread's index (threadIdx.x; a caller inside a loop passes a
-// value the compiler cannot treat as loop-invariant, so that the stages'
-// address arithmetic is not hoisted out of the loop and kept live).
-template <int N, int NL, int LD, int T, int TWS, int FWD>
-__device__ __forceinline__ void lds_fft(float2* __restrict__ buf, const float2* __restrict__ tw,
-                                        int tid = threadIdx.x) {
-  fft_stages<N, NL, LD, T, TWS, FWD, 0>(buf, tw, tid);
-}
-
-// Global -> LDS copies with every load of a thread issued before the first
-// LDS store, so each wave keeps all of its loads in flight.
+// Twiddle table into LDS, every load of a thread issued before its first
+// LDS store.
 template <int NT, int T>
 __device__ __forceinline__ void load_twiddles(float2* __restrict__ twl, const float2* __restrict__ tw) {
   constexpr int K = (NT + T - 1) / T;
@@ -228,51 +158,6 @@ __device__ __forceinline__ void load_twiddles(float2* __restrict__ twl, const fl
   for (int b = 0; b < K; ++b) {
     const int i = threadIdx.x + b * T;
     if (NT % T == 0 || i < NT) twl[i] = t[b];
-  }
-}
-
-// W adjacent columns of N elements (element stride es) into LDS lines.
-template <int N, int W, int LD, int T>
-__device__ __forceinline__ void load_cols(float2* __restrict__ lds, const float2* __restrict__ src, long es) {
-  constexpr int K = (N * W + T - 1) / T;
-  float2 t[K];
-#pragma unroll
-  for (int b = 0; b < K; ++b) {
-    const int i = threadIdx.x + b * T;
-    const int e = i / W, c = i - e * W;
-    if ((N * W) % T == 0 || i < N * W) t[b] = src[e * es + c];
-  }
-#pragma unroll
-  for (int b = 0; b < K; ++b) {
-    const int i = threadIdx.x + b * T;
-    const int e = i / W, c = i - e * W;
-    if ((N * W) % T == 0 || i < N * W) lds[c * LD + pe(e)] = t[b];
-  }
-}
-
-// LDS lines -> W adjacent columns, in chunks of kCh values per thread (the
-// LDS reads of a chunk before its stores; the empty asm keeps the compiler
-// from hoisting later chunks and raising the register count).
-constexpr int kCh = 6;
-template <int N, int W, int LD, int T>
-__device__ __forceinline__ void store_cols(float2* __restrict__ dst, long es, const float2* __restrict__ lds) {
-  constexpr int K = (N * W + T - 1) / T;
-#pragma unroll
-  for (int b0 = 0; b0 < K; b0 += kCh) {
-    float2 t[kCh];
-#pragma unroll
-    for (int q = 0; q < kCh; ++q) {
-      const int i = threadIdx.x + (b0 + q) * T;
-      const int e = i / W, c = i - e * W;
-      if (b0 + q < K && ((N * W) % T == 0 || i < N * W)) t[q] = lds[c * LD + pe(e)];
-    }
-#pragma unroll
-    for (int q = 0; q < kCh; ++q) {
-      const int i = threadIdx.x + (b0 + q) * T;
-      const int e = i / W, c = i - e * W;
-      if (b0 + q < K && ((N * W) % T == 0 || i < N * W)) dst[e * es + c] = t[q];
-    }
-    asm volatile("" ::: "memory");
   }
 }
 
@@ -819,92 +704,91 @@ __global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void
 // m_q is the gradient (i n_d scale / |n|^2) or Hessian (n_a n_b scale / |n|^2)
 // multiplier, optionally times the amplitude table; accumulate adds the result
 // to out instead of overwriting it.  Used by the adjoint (transposed Green's
-// function and transposed 2LPT maps).
+// function and transposed 2LPT maps).  Each input's forward transform ends
+// in registers, where the multiplied spectra are summed; the inverse
+// transform starts from that sum (mirrored radix orders).
 template <int N>
-__global__ __launch_bounds__(cols_threads(N, X_FWD_GREEN)) void k_combine(
+__global__ __launch_bounds__(fcols_threads(N), 4) void k_combine(
     const float2* __restrict__ in0, const float2* __restrict__ in1, const float2* __restrict__ in2,
     float2* out, ColGeom g, const float2* __restrict__ tw, CombineSpec cs,
     const float* __restrict__ amp) {
-  // the accumulator lives in registers across the inputs: spread it over
-  // as many threads as the Green's-function pass
-  constexpr int W = cols_w(N), LD = lds_ld(N), T = cols_threads(N, X_FWD_GREEN);
-  constexpr int E = (W * N + T - 1) / T;
+  constexpr int W = fcols_w(N), LD = fld(N), T = fcols_threads(N), TL = ftw_len(N);
+  constexpr int NST = nstage(N), OF = lo_first(N);
+  using S0 = Stg<N, OF, 0, W, T, false>;
+  using SL = Stg<N, OF, NST - 1, W, T, false>;
+  using SI = Stg<N, 1 - OF, NST - 1, W, T, false>;
   __shared__ float2 lds[W * LD];
-  __shared__ float2 twl[N / 2];
+  __shared__ float2 twl[TL];
   const uint32_t nblk = (uint32_t)g.nchunk * g.nplanes;
   const uint32_t bid = xcd_remap(blockIdx.x, nblk);
   const int p = bid / g.nchunk;
   const int c0 = (bid - p * g.nchunk) * W;
   const int pfreq = signed_freq(p, N);
-  load_twiddles<N / 2, T>(twl, tw);
-  // per-element scale / |n|^2 (times the amplitude), shared by the inputs
-  float2 acc[E];
-  float rw[E];
+  const long es = g.elem_stride, ofs = (long)p * g.plane_stride + c0;
+  const int tid = threadIdx.x;
   const int h = N / 2;
+  load_twiddles<TL, T>(twl, tw);
+  float2 acc[SL::KB][SL::R];
 #pragma unroll
-  for (int b = 0; b < E; ++b) {
-    acc[b] = make_float2(0.f, 0.f);
-    rw[b] = 0.f;
-    const int i = threadIdx.x + b * T;
-    if ((W * N) % T == 0 || i < N * W) {
-      const int c = i / N, e = i - c * N;
-      const int nx = signed_freq(e, N), nz = c0 + c;
-      const int n2 = nx * nx + pfreq * pfreq + nz * nz;
-      const bool nyq = nx == h || nx == -h || pfreq == h || pfreq == -h || nz == h;
-      if (n2 != 0 && nz <= h && !(cs.use_amp && nyq))
-        rw[b] = cs.scale / (float)n2 * (cs.use_amp ? amp[n2] : 1.f);
-    }
-  }
+  for (int b = 0; b < SL::KB; ++b)
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) acc[b][r] = make_float2(0.f, 0.f);
   const float2* ins[3] = {in0, in1, in2};
 #pragma unroll 1
   for (int q = 0; q < cs.nin; ++q) {
-    const float2* src = ins[q] + p * g.plane_stride + c0;
-    load_cols<N, W, LD, T>(lds, src, g.elem_stride);
-    __syncthreads();
-    lds_fft<N, W, LD, T, 1, 1>(lds, twl, opaque_tid());
+    // a thread index the compiler cannot treat as loop-invariant, so the
+    // transform's address arithmetic is not hoisted out and kept live
+    const int qt = opaque_tid();
+    float2 v[S0::KB][S0::R];
+    col_load_global<S0, W, T>(v, ins[q] + ofs, es, qt);
+    if (q > 0) __syncthreads();  // the previous transform's last LDS reads are done
+    float2 f[SL::KB][SL::R];
+    reg_fft<N, OF, W, T, false, LD, 1, TL>(v, f, lds, twl, qt);
     const int kind = cs.kind[q], ca = cs.ca[q], cb = cs.cb[q];
 #pragma unroll
-    for (int b = 0; b < E; ++b) {
-      const int i = threadIdx.x + b * T;
-      if ((W * N) % T == 0 || i < N * W) {
-        const int c = i / N, e = i - c * N;
+    for (int b = 0; b < SL::KB; ++b)
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) {
+        int c;
+        const int e = st_elem<SL, T>(qt, b, r, c);
         const int nx = signed_freq(e, N), nz = c0 + c;
         const int na = ca == 0 ? nx : (ca == 1 ? pfreq : nz);
         const bool nyq = nx == h || nx == -h || pfreq == h || pfreq == -h || nz == h;
-        const float2 x = lds[c * LD + pe(e)];
+        // scale / |n|^2 (times the amplitude), recomputed per input rather
+        // than held in registers across the inputs (hardware reciprocal)
+        const int n2 = nx * nx + pfreq * pfreq + nz * nz;
+        const float rw = (n2 != 0 && nz <= h && !(cs.use_amp && nyq))
+                             ? cs.scale * __builtin_amdgcn_rcpf((float)n2) * (cs.use_amp ? amp[n2] : 1.f)
+                             : 0.f;
+        const float2 x = f[b][r];
         if (kind == M_GRAD) {
           // i n_a rw; zero on the axis' own Nyquist plane (Green) or any Nyquist index
           const bool z = cs.green ? (na == h || na == -h) : nyq;
-          const float f = z ? 0.f : (float)na * rw[b];
-          acc[b] = cadd(acc[b], make_float2(-f * x.y, f * x.x));
+          const float m = z ? 0.f : (float)na * rw;
+          acc[b][r] = cadd(acc[b][r], make_float2(-m * x.y, m * x.x));
         } else {
           const int nb = cb == 0 ? nx : (cb == 1 ? pfreq : nz);
-          const float f = nyq ? 0.f : (float)na * (float)nb * rw[b];
-          acc[b] = cadd(acc[b], make_float2(f * x.x, f * x.y));
+          const float m = nyq ? 0.f : (float)na * (float)nb * rw;
+          acc[b][r] = cadd(acc[b][r], make_float2(m * x.x, m * x.y));
         }
       }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int b = 0; b < E; ++b) {
-    const int i = threadIdx.x + b * T;
-    if ((W * N) % T == 0 || i < N * W) {
-      const int c = i / N, e = i - c * N;
-      lds[c * LD + pe(e)] = acc[b];
-    }
   }
   __syncthreads();
-  lds_fft<N, W, LD, T, 1, 0>(lds, twl);
-  float2* dst = out + p * g.plane_stride + c0;
-  for (int i = threadIdx.x; i < N * W; i += T) {
-    const int e = i / W, c = i - e * W;
-    const float2 v = lds[c * LD + pe(e)];
-    if (cs.accumulate) {
-      const float2 o = dst[e * g.elem_stride + c];
-      dst[e * g.elem_stride + c] = cadd(o, v);
-    } else {
-      dst[e * g.elem_stride + c] = v;
+  float2 o[SI::KB][SI::R];
+  reg_fft<N, 1 - OF, W, T, false, LD, 0, TL>(acc, o, lds, twl, tid);
+  float2* dst = out + ofs;
+#pragma unroll
+  for (int b = 0; b < SI::KB; ++b) {
+    const int t = tid + b * T;
+    if (SI::ok(t)) {
+      int c, j;
+      SI::map(t, c, j);
+      float2* pd = dst + (long)j * es + c;
+#pragma unroll
+      for (int r = 0; r < SI::R; ++r) {
+        float2* e = pd + (long)r * SI::NS * es;
+        *e = cs.accumulate ? cadd(*e, o[b][r]) : o[b][r];
+      }
     }
   }
 }
@@ -1061,10 +945,10 @@ namespace {
 template <int N>
 void combine_n(const float2* const in[3], float2* out, const CombineSpec& cs, const float* amp,
                const float2* tw, hipStream_t s) {
-  constexpr int W = cols_w(N);
+  constexpr int W = fcols_w(N);
   const ColGeom g = geom(N, W, 0);
   dim3 grid((unsigned)(g.nchunk * g.nplanes), 1);
-  hipLaunchKernelGGL(k_combine<N>, grid, dim3(cols_threads(N, X_FWD_GREEN)), 0, s, in[0], in[1], in[2], out,
+  hipLaunchKernelGGL(k_combine<N>, grid, dim3(fcols_threads(N)), 0, s, in[0], in[1], in[2], out,
                      g, tw, cs, amp);
 }
 }  // namespace
