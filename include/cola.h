@@ -171,6 +171,30 @@ int cola_fft3d(cola_ctx* ctx, int32_t n, float* dev_mesh, int32_t inverse);
 int cola_step_adjoint(cola_ctx* ctx, double a0, double a1, double a_v0, const float* dev_disp0,
                       float* dev_dbar, float* dev_vbar, float* dev_psi1bar, float* dev_psi2bar);
 
+/* Storing instead of recomputing the forces of the adjoint (a memory-for-
+ * time trade of the reverse pass; the method's forces are those of the PM
+ * step, Sec. 2.2 and 2.3).  A force slot holds the three real force-mesh
+ * components of one step in the context's padded mesh layout;
+ * cola_force_slot_bytes gives its size (3 nmesh^2 c complex float32, c as
+ * for cola_fft3d: 5.5 GB at nmesh = 768).  The caller allocates and owns
+ * slots (device memory, 256-byte aligned); the library keeps no pointer to
+ * them between calls.
+ *
+ * cola_step_keep is cola_step (same result, bit for bit) with the step's
+ * force pipeline run in dev_slot instead of the context's mesh region, so
+ * the slot ends up holding the forces at the step's start positions; it
+ * overwrites the whole slot.  cola_step_adjoint_kept is cola_step_adjoint
+ * (same result, bit for bit) reading those forces from dev_slot instead of
+ * recomputing them; dev_disp0 and a0 must be the start positions and time
+ * of the step that filled the slot (not checked: other positions give the
+ * adjoint of a different force).  The slot is only read.  Errors: EINVAL
+ * for a null or misaligned slot, otherwise as cola_step / cola_step_adjoint. */
+int cola_force_slot_bytes(const cola_ctx* ctx, size_t* bytes);
+int cola_step_keep(cola_ctx* ctx, double a0, double a1, void* dev_slot);
+int cola_step_adjoint_kept(cola_ctx* ctx, double a0, double a1, double a_v0, const float* dev_disp0,
+                           const void* dev_slot, float* dev_dbar, float* dev_vbar,
+                           float* dev_psi1bar, float* dev_psi2bar);
+
 /* dev_dbar += d <delta_bar, delta(disp)> / d disp, where delta is the density
  * contrast cola_density computes at displacements dev_disp and dev_delta_bar
  * is an nmesh^3 float32 C-order mesh. */

@@ -58,6 +58,9 @@ _SIGS = {
     "cola_density_adjoint": (C.c_int, [_P, _P, _P, _P]),
     "cola_pk_adjoint": (C.c_int, [_P, _P, _I, _DP, _I, _DP, _P]),
     "cola_init_2lpt_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "cola_force_slot_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "cola_step_keep": (C.c_int, [_P, _D, _D, _P]),
+    "cola_step_adjoint_kept": (C.c_int, [_P, _D, _D, _D, _P, _P, _P, _P, _P, _P]),
     "cola_synchronize": (C.c_int, [_P]),
     "cola_batch_workspace_query": (C.c_int, [C.POINTER(cola_params), _I, C.POINTER(C.c_size_t)]),
     "cola_batch_create": (C.c_int, [C.POINTER(cola_params), _I, _P, C.c_size_t, _P, C.POINTER(_P)]),

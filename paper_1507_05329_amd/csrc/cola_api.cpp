@@ -592,8 +592,11 @@ int cola_fft3d(cola_ctx* c, int32_t n, float* mesh, int32_t inverse) {
 // ---------------------------------------------------------------------------
 // Adjoint.
 
-int cola_step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const float* disp0,
-                      float* dbar, float* vbar, float* p1bar, float* p2bar) {
+namespace {
+// Adjoint of one step.  kept: the step's force meshes left by
+// cola_step_keep (three meshes mesh_stride apart), or null to recompute them.
+int step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const float* disp0, const float2* kept,
+                 float* dbar, float* vbar, float* p1bar, float* p2bar) {
   if (!c || !disp0 || !dbar || !vbar || !p1bar || !p2bar) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no 2LPT fields (run an initial condition first)");
   if (!(a0 > 0) || !(a1 > a0) || !(a_v0 > 0) || !std::isfinite(a1))
@@ -604,16 +607,24 @@ int cola_step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const floa
   const double alpha = s[0];
   const int np = c->p.np, nm = c->p.nmesh;
   const long rs = 2 * padded_cols(nm);
-  // forward force meshes at the checkpointed positions (also sorts them)
   launch_set_coef(c->coef, coef, 1, 0, c->stream);
-  force_meshes(c, disp0);
-  float* g[3];
-  for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<float*>(c->mesh[d]);
+  const float* g[3];
+  if (kept) {
+    // the forward step's force meshes; sort the checkpointed positions for
+    // the transposed readout below
+    tile_sort(c, nm, disp0);
+    for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<const float*>(kept + (size_t)d * c->mesh_stride);
+  } else {
+    // forward force meshes at the checkpointed positions (also sorts them)
+    force_meshes(c, disp0);
+    for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<const float*>(c->mesh[d]);
+  }
+  float* gbar = reinterpret_cast<float*>(c->mesh[0]);
   // reverse kick/drift and the readout weight gradient; Fbar -> c->fbar
   launch_adj_readout_kick(disp0, g[0], g[1], g[2], rs, np, nm, kd, dbar, vbar, p1bar, p2bar, c->fbar,
                           c->stream);
   // gbar_d = R^T Fbar_d (deterministic weighted deposit over the same sort)
-  launch_deposit3_weighted(disp0, c->perm, c->offsets, np, nm, c->fbar, g[0], rs, 2 * c->mesh_stride,
+  launch_deposit3_weighted(disp0, c->perm, c->offsets, np, nm, c->fbar, gbar, rs, 2 * c->mesh_stride,
                            c->stream);
   // rhobar = (Nm^3/Np) deltabar,  deltabar = -sum_d G_d gbar_d
   fft_r2c_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream);
@@ -628,9 +639,38 @@ int cola_step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const floa
   fft_combine_x(ins, c->mesh[0], nm, cs, nullptr, c->tw, c->stream);
   fft_y(c->mesh[0], nm, 1, 0, 1, c->tw, c->stream);
   fft_c2r_z(c->mesh[0], nm, 1, 0, c->tw, c->stream);
-  launch_adj_deposit_grad(disp0, g[0], rs, np, nm, 1.0f, 1.0f, dbar, c->stream);
+  launch_adj_deposit_grad(disp0, gbar, rs, np, nm, 1.0f, 1.0f, dbar, c->stream);
   LAUNCH_CHECK(c, "cola_step_adjoint");
   return COLA_OK;
+}
+}  // namespace
+
+int cola_step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const float* disp0,
+                      float* dbar, float* vbar, float* p1bar, float* p2bar) {
+  return step_adjoint(c, a0, a1, a_v0, disp0, nullptr, dbar, vbar, p1bar, p2bar);
+}
+
+int cola_force_slot_bytes(const cola_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return COLA_EINVAL;
+  *bytes = 3 * (size_t)c->mesh_stride * sizeof(float2);
+  return COLA_OK;
+}
+
+int cola_step_keep(cola_ctx* c, double a0, double a1, void* slot) {
+  if (!c || !slot) return fail(c, COLA_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(slot) % 256 != 0) return fail(c, COLA_EINVAL, "slot must be 256-byte aligned");
+  // the step's force pipeline runs in the slot instead of the context's meshes
+  float2* own[3] = {c->mesh[0], c->mesh[1], c->mesh[2]};
+  for (int d = 0; d < 3; ++d) c->mesh[d] = static_cast<float2*>(slot) + (size_t)d * c->mesh_stride;
+  const int r = cola_step(c, a0, a1);
+  for (int d = 0; d < 3; ++d) c->mesh[d] = own[d];
+  return r;
+}
+
+int cola_step_adjoint_kept(cola_ctx* c, double a0, double a1, double a_v0, const float* disp0,
+                           const void* slot, float* dbar, float* vbar, float* p1bar, float* p2bar) {
+  if (!slot) return fail(c, COLA_EINVAL, "null argument");
+  return step_adjoint(c, a0, a1, a_v0, disp0, static_cast<const float2*>(slot), dbar, vbar, p1bar, p2bar);
 }
 
 int cola_density_adjoint(cola_ctx* c, const float* disp, const float* delta_bar, float* dbar) {

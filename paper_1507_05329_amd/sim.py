@@ -154,10 +154,27 @@ class ColaSim:
         self._chk(self.lib.cola_fft3d(self.ctx, n, _ptr(mesh), int(inverse)), "fft3d")
 
     # -- adjoint (reverse mode) -------------------------------------------
-    def step_adjoint(self, a0, a1, a_v0, disp0, dbar, vbar, psi1bar, psi2bar):
-        """Cotangents (dbar, vbar) at a1 -> at a0 in place; psi bars accumulate."""
-        self._chk(self.lib.cola_step_adjoint(self.ctx, a0, a1, a_v0, _ptr(disp0), _ptr(dbar), _ptr(vbar),
-                                             _ptr(psi1bar), _ptr(psi2bar)), "step_adjoint")
+    def step_adjoint(self, a0, a1, a_v0, disp0, dbar, vbar, psi1bar, psi2bar, slot=None):
+        """Cotangents (dbar, vbar) at a1 -> at a0 in place; psi bars accumulate.
+        slot: the force slot step_keep filled for this step (forces read, not
+        recomputed)."""
+        if slot is None:
+            self._chk(self.lib.cola_step_adjoint(self.ctx, a0, a1, a_v0, _ptr(disp0), _ptr(dbar), _ptr(vbar),
+                                                 _ptr(psi1bar), _ptr(psi2bar)), "step_adjoint")
+        else:
+            self._chk(self.lib.cola_step_adjoint_kept(self.ctx, a0, a1, a_v0, _ptr(disp0), _ptr(slot),
+                                                      _ptr(dbar), _ptr(vbar), _ptr(psi1bar), _ptr(psi2bar)),
+                      "step_adjoint_kept")
+
+    def force_slot(self) -> torch.Tensor:
+        """A device buffer for step_keep (the three force meshes of one step)."""
+        n = C.c_size_t()
+        self._chk(self.lib.cola_force_slot_bytes(self.ctx, C.byref(n)), "force_slot_bytes")
+        return torch.empty(n.value // 4, dtype=torch.float32, device=self.device)
+
+    def step_keep(self, a0: float, a1: float, slot: torch.Tensor):
+        """step(a0, a1), leaving the step's force meshes in slot."""
+        self._chk(self.lib.cola_step_keep(self.ctx, a0, a1, _ptr(slot)), "step_keep")
 
     def density_adjoint(self, disp, delta_bar, dbar):
         """dbar += d<delta_bar, density(disp)>/d disp."""

@@ -191,3 +191,44 @@ def test_lean_pk_gradient_equals_checkpointed_autograd(table):
     s.close()
     assert np.array_equal(p0, p.detach().numpy()) and np.array_equal(p3, p0)
     assert torch.equal(g0, noise.grad) and torch.equal(g3, noise.grad)
+
+
+def test_kept_forces_equal_recomputed(table):
+    """cola_step_keep equals cola_step and cola_step_adjoint_kept equals
+    cola_step_adjoint bit for bit (32^3 / 64^3, a step from the middle of a
+    run; the adjoint twice from one slot, which it only reads)."""
+    from paper_1507_05329_amd.sim import ColaSim
+    say("[gpu] kept force meshes")
+    s = ColaSim(32, 64, 100.0)
+    try:
+        s.init_2lpt(1, *table)
+        e = step_edges()
+        for i in range(4):
+            s.step(e[i], e[i + 1])
+        st0 = s.get_state()
+        slot = s.force_slot()
+        s.step_keep(e[4], e[5], slot)
+        kept = s.get_state()
+        s.set_state(st0["disp"], st0["vres"], None, None, st0["a_x"], st0["a_v"])
+        s.step(e[4], e[5])
+        plain = s.get_state()
+        assert torch.equal(kept["disp"], plain["disp"]) and torch.equal(kept["vres"], plain["vres"])
+        assert kept["a_x"] == plain["a_x"] and kept["a_v"] == plain["a_v"]
+        rng = np.random.default_rng(3)
+        d1 = dev(rng.standard_normal(st0["disp"].shape))
+        v1 = dev(rng.standard_normal(st0["disp"].shape))
+        outs = []
+        for use in (None, slot, slot):
+            d, v = d1.clone(), v1.clone()
+            p1, p2 = torch.zeros_like(d), torch.zeros_like(d)
+            s.step_adjoint(e[4], e[5], st0["a_v"], st0["disp"], d, v, p1, p2, slot=use)
+            outs.append((d, v, p1, p2))
+        torch.cuda.synchronize()
+        for other in outs[1:]:
+            for a, b in zip(outs[0], other):
+                assert torch.equal(a, b)
+        with pytest.raises(Exception):
+            s.step_keep(e[5], e[6], slot[1:])   # misaligned slot: EINVAL, state unchanged
+        assert s.get_state()["a_x"] == plain["a_x"]
+    finally:
+        s.close()
