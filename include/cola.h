@@ -176,7 +176,7 @@ int cola_step_adjoint(cola_ctx* ctx, double a0, double a1, double a_v0, const fl
  * step, Sec. 2.2 and 2.3).  A force slot holds the three real force-mesh
  * components of one step in the context's padded mesh layout;
  * cola_force_slot_bytes gives its size (3 nmesh^2 c complex float32, c as
- * for cola_fft3d: 5.5 GB at nmesh = 768).  The caller allocates and owns
+ * for cola_fft3d: 5.7 GB at nmesh = 768).  The caller allocates and owns
  * slots (device memory, 256-byte aligned); the library keeps no pointer to
  * them between calls.
  *
