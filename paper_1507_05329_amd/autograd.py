@@ -4,7 +4,11 @@ The backward pass is the hand-written adjoint of libcola (reverse kick/drift,
 transposed CIC readout and deposit, transposed Green's function, transposed
 2LPT maps).  Memory: the full particle state is kept every ``segment`` steps;
 inside a segment the step-start positions are recomputed forward, then the
-segment is reversed (each step is recomputed at most once).
+segment is reversed (each step is recomputed at most once).  With
+keep_forces the recomputed steps leave their force meshes in one slot per
+step of the segment (cola_step_keep) and the adjoint reads them instead of
+recomputing the forces a second time (same gradient, bit for bit; a slot is
+three PM meshes).
 """
 from __future__ import annotations
 
@@ -14,29 +18,35 @@ import torch
 from .sim import ColaSim
 
 
-def _run_segment(sim, edges, i0, i1):
-    """Forward steps i0..i1-1 from the current state; returns step-start (disp, a_v)."""
+def _run_segment(sim, edges, i0, i1, slots=None):
+    """Forward steps i0..i1-1 from the current state; returns step-start (disp, a_v).
+    slots: one force slot per step (cola_step_keep) or None."""
     out = []
     for i in range(i0, i1):
         st = sim.get_state()
         out.append((st["disp"], st["a_v"]))
-        sim.step(edges[i], edges[i + 1])
+        if slots is None:
+            sim.step(edges[i], edges[i + 1])
+        else:
+            sim.step_keep(edges[i], edges[i + 1], slots[i - i0])
     return out
 
 
-def _backward(sim, noise, edges, saved_states, segment, dbar, vbar):
+def _backward(sim, noise, edges, saved_states, segment, dbar, vbar, keep_forces=False):
     p1b = torch.zeros_like(dbar)
     p2b = torch.zeros_like(dbar)
     nstep = len(edges) - 1
     starts = list(range(0, nstep, segment))
+    slots = [sim.force_slot() for _ in range(min(segment, nstep))] if keep_forces else None
     for s0 in reversed(starts):
         s1 = min(s0 + segment, nstep)
         st = saved_states[s0]
         sim.set_state(st["disp"], st["vres"], st["psi1"], st["psi2"], st["a_x"], st["a_v"])
-        steps = _run_segment(sim, edges, s0, s1)
+        steps = _run_segment(sim, edges, s0, s1, slots)
         for i in reversed(range(s0, s1)):
             disp0, a_v0 = steps[i - s0]
-            sim.step_adjoint(edges[i], edges[i + 1], a_v0, disp0, dbar, vbar, p1b, p2b)
+            sim.step_adjoint(edges[i], edges[i + 1], a_v0, disp0, dbar, vbar, p1b, p2b,
+                             slot=None if slots is None else slots[i - s0])
     return sim.init_adjoint(noise, dbar, p1b, p2b)
 
 
@@ -55,9 +65,10 @@ class ColaDensity(torch.autograd.Function):
     """noise (np^3) -> final density contrast (nmesh^3) through a full COLA run."""
 
     @staticmethod
-    def forward(ctx, noise, sim: ColaSim, k, pk, edges, segment=1):
+    def forward(ctx, noise, sim: ColaSim, k, pk, edges, segment=1, keep_forces=False):
         saved = _forward(sim, noise.detach().contiguous(), k, pk, edges, segment)
         ctx.sim, ctx.edges, ctx.saved, ctx.segment = sim, list(edges), saved, segment
+        ctx.keep = keep_forces
         final = sim.get_state()
         ctx.final_disp = final["disp"]
         ctx.save_for_backward(noise)
@@ -70,17 +81,18 @@ class ColaDensity(torch.autograd.Function):
         dbar = torch.zeros_like(ctx.final_disp)
         sim.density_adjoint(ctx.final_disp, grad_delta.contiguous(), dbar)
         vbar = torch.zeros_like(dbar)
-        wbar = _backward(sim, noise.contiguous(), ctx.edges, ctx.saved, ctx.segment, dbar, vbar)
-        return wbar, None, None, None, None, None
+        wbar = _backward(sim, noise.contiguous(), ctx.edges, ctx.saved, ctx.segment, dbar, vbar, ctx.keep)
+        return wbar, None, None, None, None, None, None
 
 
 class ColaPowerSpectrum(torch.autograd.Function):
     """noise -> binned P(k) of the final particles (host bins returned as a CPU tensor)."""
 
     @staticmethod
-    def forward(ctx, noise, sim: ColaSim, k, pk, edges, kedges, ngrid=None, segment=1):
+    def forward(ctx, noise, sim: ColaSim, k, pk, edges, kedges, ngrid=None, segment=1, keep_forces=False):
         saved = _forward(sim, noise.detach().contiguous(), k, pk, edges, segment)
         ctx.sim, ctx.edges, ctx.saved, ctx.segment = sim, list(edges), saved, segment
+        ctx.keep = keep_forces
         ctx.kedges, ctx.ngrid = np.asarray(kedges, np.float64), ngrid
         final = sim.get_state()
         ctx.final_disp = final["disp"]
@@ -95,8 +107,8 @@ class ColaPowerSpectrum(torch.autograd.Function):
         dbar = torch.zeros_like(ctx.final_disp)
         sim.pk_adjoint(ctx.final_disp, ctx.kedges, grad_p.detach().cpu().double().numpy(), dbar, ctx.ngrid)
         vbar = torch.zeros_like(dbar)
-        wbar = _backward(sim, noise.contiguous(), ctx.edges, ctx.saved, ctx.segment, dbar, vbar)
-        return wbar, None, None, None, None, None, None, None
+        wbar = _backward(sim, noise.contiguous(), ctx.edges, ctx.saved, ctx.segment, dbar, vbar, ctx.keep)
+        return wbar, None, None, None, None, None, None, None, None
 
 
 def pk_noise_gradient(sim: ColaSim, noise, k, pk, edges, kedges, cbar, ngrid=None, every=None):

@@ -232,3 +232,21 @@ def test_kept_forces_equal_recomputed(table):
         assert s.get_state()["a_x"] == plain["a_x"]
     finally:
         s.close()
+
+
+@pytest.mark.parametrize("segment", [1, 4])
+def test_autograd_kept_forces_same_gradient(sim, table, segment):
+    """keep_forces (the backward's recomputed steps store their forces and the
+    adjoint reads them) gives the same noise gradient bit for bit."""
+    from paper_1507_05329_amd.autograd import ColaDensity
+    say(f"[gpu] autograd with kept forces, segment={segment}")
+    w = white_noise(4, NP)
+    target = dev(seeded_normal(5, (NM,) * 3))
+    e = step_edges()
+    grads = []
+    for keep in (False, True):
+        noise = dev(w).requires_grad_(True)
+        delta = ColaDensity.apply(noise, sim, *table, e, segment, keep)
+        ((delta - target) ** 2).sum().backward()
+        grads.append(noise.grad.detach().clone())
+    assert torch.equal(grads[0], grads[1])
