@@ -86,10 +86,11 @@ __device__ __forceinline__ long subcube_particle(uint32_t b, int t, int np) {
   return ((long)i * np + j) * np + k;
 }
 
-// The same for the force readout, in columns of 8 x 1 x 32 ids (16 x 1 x 16
-// when np is not a multiple of 32): deeper along i, one j.  Measured on the
-// 256^3 / 768^3 run: readout 1.89 against 2.00 ms per step (2 x 4 x 32),
-// 1.90 for 4 x 2 x 32, 1.95 for 4 x 4 x 16, 2.14 for 1 x 8 x 32.
+// The same for the force readout and its adjoint, in columns of 8 x 1 x 32
+// ids (16 x 1 x 16 when np is not a multiple of 32): deeper along i, one j.
+// Measured on the 256^3 / 768^3 run: readout 1.89 against 2.00 ms per step
+// (2 x 4 x 32), 1.90 for 4 x 2 x 32, 1.95 for 4 x 4 x 16, 2.14 for 1 x 8 x 32;
+// the bucket count (which aggregates atomics per wave) is slower with it.
 __device__ __forceinline__ long readout_particle(uint32_t b, int t, int np) {
   const int lk = (np & 31) == 0 ? 5 : 4;           // ids along k per block row: 32 or 16
   const uint32_t nbk = (uint32_t)np >> lk, nbj = (uint32_t)np;

@@ -1,8 +1,8 @@
 // CIC force readout fused with the COLA kick and drift (Koda et al. 2015,
 // Sec. 2.2, eqs. cola-kick and cola-drift; 2LPT growing mode of Sec. 2.1).
 //
-// Per particle (one thread each; blocks walk the lattice in sub-cubes, see
-// subcube_particle):
+// Per particle (one thread each; blocks walk the lattice in columns of
+// particles, see readout_particle):
 //   F_d   = sum_s w_s g_d[c + s]                      (same CIC weights as the deposit)
 //   v_d  += K F_d - c1 Psi1_d - c2 Psi2_d             (c1 = K alpha D1, c2 = K alpha (D2 - D1^2):
 //                                                      the residual force F - d^2/dt^2-term of 2LPT)
