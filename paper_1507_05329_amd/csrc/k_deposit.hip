@@ -41,7 +41,7 @@ struct DepShared {
   static constexpr int kNC = NC, kCap = CAP, kT = DT;
   uint64_t keys[kCap];                    // cell << 41 | id << 11 | slot
   float fx[kCap], fy[kCap], fz[kCap];
-  float rho[NC][kTile * kTile * kTile];
+  alignas(16) float rho[NC][kTile * kTile * kTile];
   uint16_t run[kCap + 1];                 // start of each run of equal cell
   uint32_t scan[DT / 64];
   uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
@@ -475,13 +475,23 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
     n = gather_keys(sh, disp, perm, np3, np, nm, dscale, t0, lo, hi);
   }
 
-  for (int nn = threadIdx.x; nn < kTile * kTile * kTile; nn += kDT) {
+  // four consecutive z nodes per thread and store (rows of the padded
+  // layout and tile origins are 16-byte aligned); measured 1.60 against
+  // 1.65 ms on the 768^3 mesh with one node per store
+  for (int qd = threadIdx.x; qd < kTile * kTile * kTile / 4; qd += kDT) {
+    const int nn = qd * 4;
     const int nx = nn / (kTile * kTile), ny = (nn / kTile) % kTile, nz = nn % kTile;
     const long o = ((long)(t0[0] + nx) * nm + (t0[1] + ny)) * row_stride + (t0[2] + nz);
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      const float rho = sh.rho[q][nn];
-      out[q * mesh_stride + o] = contrast ? __fsub_rn(__fmul_rn(rho, cinv), 1.0f) : rho;
+      float4 r = *reinterpret_cast<const float4*>(&sh.rho[q][nn]);
+      if (contrast) {
+        r.x = __fsub_rn(__fmul_rn(r.x, cinv), 1.0f);
+        r.y = __fsub_rn(__fmul_rn(r.y, cinv), 1.0f);
+        r.z = __fsub_rn(__fmul_rn(r.z, cinv), 1.0f);
+        r.w = __fsub_rn(__fmul_rn(r.w, cinv), 1.0f);
+      }
+      *reinterpret_cast<float4*>(out + q * mesh_stride + o) = r;
     }
   }
 }
