@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "cola_internal.h"
@@ -967,14 +968,20 @@ void enqueue_batch_step(cola_batch* b, hipStream_t s, bool parallel) {
     for (cola_batch::Group& G : b->groups) enqueue_group(b, G, s);
     return;
   }
+  // groups by decreasing work (particles x mocks), the heaviest branch
+  // enqueued first: it is the step's critical path
+  std::vector<size_t> ord(ng);
+  for (size_t g = 0; g < ng; ++g) ord[g] = g;
+  auto work = [&](size_t g) { return (double)b->groups[g].first->np3 * (double)b->groups[g].idx.size(); };
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
   hipEventRecord(b->ev[0], s);
-  for (size_t g = 1; g < ng; ++g) {
-    hipStreamWaitEvent(b->branch[g - 1], b->ev[0], 0);
-    enqueue_group(b, b->groups[g], b->branch[g - 1]);
-    hipEventRecord(b->ev[g], b->branch[g - 1]);
+  for (size_t k = 0; k + 1 < ng; ++k) {
+    hipStreamWaitEvent(b->branch[k], b->ev[0], 0);
+    enqueue_group(b, b->groups[ord[k]], b->branch[k]);
+    hipEventRecord(b->ev[k + 1], b->branch[k]);
   }
-  enqueue_group(b, b->groups[0], s);
-  for (size_t g = 1; g < ng; ++g) hipStreamWaitEvent(s, b->ev[g], 0);
+  enqueue_group(b, b->groups[ord[ng - 1]], s);
+  for (size_t k = 1; k < ng; ++k) hipStreamWaitEvent(s, b->ev[k], 0);
 }
 
 void drop_graph(cola_batch* b) {
