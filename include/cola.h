@@ -131,7 +131,8 @@ int cola_density(cola_ctx* ctx, float* dev_out);
  * / V over the half space {kz>0} U {kz=0,ky>0} U {kz=0,ky=0,kx>0} with
  * |k| <= pi ngrid / box, binned by k_edges[nbins+1] (h/Mpc, increasing; bin b
  * holds edges[b] <= |k| < edges[b+1]).  Host outputs: mean |k|, mean P and
- * mode count per bin.  Synchronises the stream.  nbins <= 4096. */
+ * mode count per bin; a bin without modes reports count 0 and NaN for its
+ * mean |k| and P.  Synchronises the stream.  nbins <= 4096. */
 int cola_pk(cola_ctx* ctx, int32_t ngrid, const double* k_edges, int32_t nbins,
             double* host_kmean, double* host_pk, int64_t* host_nmodes);
 

@@ -241,6 +241,38 @@ def test_full_run_power_spectrum_matches_oracle(sim, table):
     assert err.max() < 5e-3
 
 
+@pytest.mark.parametrize("ngrid", [32, 48])
+def test_pk_coarser_grid_and_empty_bins(sim, table, ngrid):
+    """cola_pk on a grid coarser than the PM mesh (the deposit rescales the
+    displacements; 48 is not a power of two), with bins that hold no mode
+    (narrower than the mode spacing, and beyond the grid's Nyquist wave
+    number): mode counts equal the FP64 estimator's on the same particles,
+    empty bins report NaN mean |k| and P (the documented contract), every
+    other bin finite values."""
+    say(f"[gpu] P(k) on a {ngrid}^3 grid with empty bins")
+    w = white_noise(7, NP)
+    sim.init_from_noise(to_dev(w), *table)
+    e = step_edges()
+    for i in range(3):
+        sim.step(e[i], e[i + 1])
+    kf = 2 * np.pi / L
+    kny = np.pi * ngrid / L
+    edges = np.concatenate([[0.2 * kf, 0.3 * kf], np.linspace(kf, kny, 9)[1:], [1.5 * kny, 2.0 * kny]])
+    edges.sort()
+    km, p_g, n_g = sim.pk(edges, ngrid)
+    st = sim.get_state()
+    pos = ic.lattice(NP, L) + st["disp"].cpu().numpy().astype(np.float64) * (L / NM)
+    k_e, p_e, n_e = pk.power_spectrum(pos, L, ngrid, edges)
+    assert np.array_equal(n_g, n_e)
+    empty = n_e == 0
+    assert empty.sum() >= 2                 # the sub-spacing bin and those beyond k_Nyq
+    assert np.all(np.isnan(p_g[empty])) and np.all(np.isnan(km[empty]))
+    ok = ~empty
+    assert np.all(np.isfinite(p_g[ok])) and np.all(np.isfinite(km[ok]))
+    assert np.abs(p_g[ok] / p_e[ok] - 1).max() < 1e-4
+    assert np.abs(km[ok] / k_e[ok] - 1).max() < 1e-12
+
+
 def test_noise_matches_oracle_philox(sim):
     z = sim.noise(2024).cpu().numpy()
     ref = philox.normal_field(2024, NP)
