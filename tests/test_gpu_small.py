@@ -149,6 +149,30 @@ def test_density_bit_exact_sparse_tiles(nm):
         s.close()
 
 
+def test_density_bit_exact_mesh_equal_to_particle_grid():
+    """The densest allowed configuration: a 32^3 mesh for 32^3 particles
+    (about 4000 particles per 16^3 tile region, far above the LDS capacity:
+    every tile takes the cell-range splitting), lattice-perturbed and with a
+    400-particle clump in one cell.  Bit-exact against the FP32 replay and
+    the run-to-run repeat."""
+    from paper_1507_05329_amd.sim import ColaSim
+    say("[gpu] density, mesh = particle grid")
+    s = ColaSim(NP, NP, L)
+    try:
+        rng = np.random.default_rng(11)
+        base = ic.lattice(NP, L) * (NP / L) - 0.5
+        target = base + rng.standard_normal((3, NP ** 3)) * 0.7
+        target[:, :400] = 9.0 + rng.uniform(0, 1, (3, 400))
+        disp = (target - base).astype(np.float32)
+        z = np.zeros((3, NP ** 3), np.float32)
+        s.set_state(to_dev(disp), to_dev(z), to_dev(z), to_dev(z), 0.5, 0.5)
+        got = s.density().cpu().numpy()
+        assert got.tobytes() == cic_fp32.density(disp, NP, NP).tobytes()
+        assert s.density().cpu().numpy().tobytes() == got.tobytes()
+    finally:
+        s.close()
+
+
 def test_density_matches_fp64_oracle(sim):
     disp = random_disp(2, 3.0)
     set_disp(sim, disp)
