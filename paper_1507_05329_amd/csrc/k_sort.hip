@@ -28,30 +28,37 @@ __global__ __launch_bounds__(256) void k_bin_count(const float* __restrict__ dis
   counts = mock_ptr(counts, mstride);
   pkey = mock_ptr(pkey, mstride);
   prank = mock_ptr(prank, mstride);
-  // sub-cube order: a wave's particles share few buckets (fewer atomics)
+  // Sub-cube order: a workgroup's particles share few buckets. Every supported
+  // np is a multiple of 16, so np^3 is a multiple of 256 and each thread of
+  // the grid has a particle.
   const long i = subcube_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
-  if (i >= np3) return;  // np3 is a multiple of 64 for every supported size: whole waves exit
   int c[3];
   float f[3];
   home_cell(disp, np3, (uint32_t)i, np, nm, dscale, c, f);
   const uint32_t b = bucket_of(c, nm >> 4);
   pkey[i] = b;
-  // Wavefront-aggregated count: lanes with equal bucket share one atomic
-  // (consecutive particles are Lagrangian neighbours and share buckets).
-  const int lane = threadIdx.x & 63;
-  uint64_t todo = __ballot(1);
-  uint32_t rank = 0;
-  while (todo) {
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const uint32_t lb = __shfl(b, leader, 64);
-    const uint64_t same = __ballot(b == lb) & todo;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&counts[lb], (uint32_t)__popcll(same));
-    base = __shfl(base, leader, 64);
-    if (b == lb) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
-    todo &= ~same;
+  // Workgroup-aggregated count: an LDS table (open addressing, 512 slots for
+  // at most 256 keys) counts the workgroup's particles per bucket, then one
+  // global atomic per distinct bucket reserves their places.
+  constexpr uint32_t kEmpty = 0xffffffffu, kSlots = 512;
+  __shared__ uint32_t hkey[kSlots], hcnt[kSlots], hbase[kSlots];
+  for (uint32_t j = threadIdx.x; j < kSlots; j += 256) {
+    hkey[j] = kEmpty;
+    hcnt[j] = 0u;
   }
-  prank[i] = rank;
+  __syncthreads();
+  uint32_t h = (b * 2654435761u) >> 23;
+  for (;;) {
+    const uint32_t prev = atomicCAS(&hkey[h], kEmpty, b);
+    if (prev == kEmpty || prev == b) break;
+    h = (h + 1) & (kSlots - 1);
+  }
+  const uint32_t local = atomicAdd(&hcnt[h], 1u);
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < kSlots; j += 256)
+    if (hkey[j] != kEmpty) hbase[j] = atomicAdd(&counts[hkey[j]], hcnt[j]);
+  __syncthreads();
+  prank[i] = hbase[h] + local;
 }
 
 void launch_bin_count(const float* disp, int np, int nm, float dscale, uint32_t* counts,
