@@ -13,6 +13,8 @@ Modules
   ic         Gaussian field -> 2LPT displacements (Sec. 2.1, 2LPT growing mode)
   pm         CIC deposit, Poisson/gradient, CIC readout (Sec. 2.2-2.3)
   cola       residual kick/drift integrator (eqs. cola-drift, cola-kick)
+  velocity   full particle velocities at the position time, redshift-space
+             displacements (Sec. 2.1-2.2, Sec. 4.4)
   pk         matter power-spectrum estimator (Sec. 3.3)
   cic_fp32   float32 same-order replay of the deterministic CIC deposit
   adjoint    reverse-mode derivative of the step and of the 2LPT map

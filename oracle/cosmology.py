@@ -56,6 +56,27 @@ def growth_D2(a: float, om: float) -> float:
     return -3.0 / 7.0 * d1 * d1 * omega_matter(a, om) ** (-1.0 / 143.0)
 
 
+def growth_D1_prime(a: float, om: float) -> float:
+    """dD1/da of the Heath form D1 = c E(a) int_0^a da' / (a' E)^3.
+
+    Product rule: dD1/da = D1 (dE/da)/E + c / (a E)^3 * E, with
+    dE/da = -3 Om / (2 a^4 E) and c = 2.5 Om / (unnormalised D1 at a = 1).
+    """
+    e = hubble_E(a, om)
+    de = -1.5 * om / (a ** 4 * e)
+    c = 2.5 * om / _heath_unnormalised(1.0, om)
+    return growth_D1(a, om) * de / e + c / (a * e) ** 3 * e
+
+
+def growth_D2_prime(a: float, om: float) -> float:
+    """dD2/da of D2 = -(3/7) D1^2 Omega(a)^(-1/143) (Sec. 2.1):
+    D2 [2 D1'/D1 - (1/143) dln Omega/da], dln Omega/da = -3 (1-Om) a^2 / (Om + (1-Om) a^3).
+    """
+    d1 = growth_D1(a, om)
+    dlnom = -3.0 * (1.0 - om) * a * a / (om + (1.0 - om) * a ** 3)
+    return growth_D2(a, om) * (2.0 * growth_D1_prime(a, om) / d1 - dlnom / 143.0)
+
+
 def poisson_alpha(a: float, om: float) -> float:
     """Source factor of the comoving Poisson equation, Sec. 2.2: (3/2) Omega_m / a."""
     return 1.5 * om / a

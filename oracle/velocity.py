@@ -1,0 +1,74 @@
+"""Particle velocities and redshift-space displacements, float64.
+
+Test infrastructure: the slow, plainly written reference that the GPU path is
+checked against; nothing in the library imports it.
+
+Paper passages followed (Koda et al. 2015):
+* Sec. 2.1: the COLA split of the velocity into a residual and the time
+  derivative of the 2LPT trajectory x_2LPT = q + D1 Psi1 + D2 Psi2; with the
+  canonical velocity v = a^2 dx/dt of Sec. 2.2 (equations of motion) the
+  2LPT part is a^2 adot (D1' Psi1 + D2' Psi2), ' = d/da.
+* Sec. 2.2, eq. cola-kick: the residual velocity between kicks follows the
+  kick ansatz, and the paper uses the same equations to interpolate
+  snapshots between steps.  The state holds v_res at a_v (the last half
+  step) and positions at a_x; the velocity at a_x is v_res(a_v) plus the
+  kick factor from a_v to a_x times F_res(x) (force at the position time).
+* Sec. 4.4 (mock catalogue): redshift-space position s = x + (v.xhat)/(aH)
+  xhat, v there the peculiar velocity a dx/dt, so the comoving shift is
+  (dx/dt . xhat)/H = v_canonical . xhat / (a adot).
+
+Readings:
+* The line of sight is a box axis (distant observer), the usual choice for
+  a periodic box; the shift applies to that displacement component only.
+* At a_v = a_x (the initial state) the kick factor is zero and no force is
+  needed.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import cosmology as cosmo
+from . import pm
+from .cola import State
+
+
+def snapshot_coefficients(state: State) -> dict:
+    """Scalars of the velocity at the position time a_x."""
+    a, a_v, om, n = state.a_x, state.a_v, state.om, state.n_lpt
+    adot = cosmo.adot(a, om)
+    return dict(
+        a=a,
+        adot=adot,
+        alpha=cosmo.poisson_alpha(a, om),
+        D1=cosmo.growth_D1(a, om),
+        D2=cosmo.growth_D2(a, om),
+        K=cosmo.kick_factor(a_v, a, a, om, n),
+        u1=a * a * adot * cosmo.growth_D1_prime(a, om),
+        u2=a * a * adot * cosmo.growth_D2_prime(a, om),
+    )
+
+
+def residual_velocity_at_position_time(state: State, force=None) -> np.ndarray:
+    """v_res carried from a_v to a_x by the kick ansatz with F_res(x)."""
+    c = snapshot_coefficients(state)
+    if state.a_v == state.a_x:
+        return state.v.copy()
+    F = pm.pm_force(state.positions(), state.nmesh, state.box, c["alpha"]) \
+        if force is None else force(state, c)
+    F_res = F - c["alpha"] * (c["D1"] * state.psi1 + (c["D2"] - c["D1"] ** 2) * state.psi2)
+    return state.v + c["K"] * F_res
+
+
+def full_velocity(state: State, force=None) -> np.ndarray:
+    """Canonical velocity v = a^2 dx/dt of every particle at a_x, shape (3, Np)."""
+    c = snapshot_coefficients(state)
+    v_res = residual_velocity_at_position_time(state, force)
+    return v_res + c["u1"] * state.psi1 + c["u2"] * state.psi2
+
+
+def rsd_displacement(state: State, v: np.ndarray, axis: int) -> np.ndarray:
+    """Displacement of the redshift-space position along ``axis``."""
+    c = snapshot_coefficients(state)
+    d = state.d.copy()
+    d[axis] = d[axis] + v[axis] / (c["a"] * c["adot"])
+    return d

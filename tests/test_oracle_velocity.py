@@ -1,0 +1,127 @@
+"""Pins for the oracle's velocities and redshift-space displacements
+(Sec. 2.1 COLA split, Sec. 2.2 equations of motion and kick ansatz,
+Sec. 4.4 redshift-space mapping)."""
+import copy
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import cola, cosmology as cosmo, ic, velocity
+from paper_1507_05329_amd.inputs import bbks_table, step_edges, white_noise
+
+OM = 0.27
+
+
+def plane_wave_fields(n, L, amp, axis=0):
+    x = np.arange(n) * L / n
+    shape = [1, 1, 1]
+    shape[axis] = n
+    dl = np.broadcast_to((amp * np.cos(2 * np.pi * x / L)).reshape(shape), (n, n, n)).copy()
+    p1, p2 = ic.lpt_from_delta(dl, L)
+    return p1.reshape(3, -1), p2.reshape(3, -1)
+
+
+@pytest.mark.parametrize("om", [0.27, 0.5])
+@pytest.mark.parametrize("a", [0.02, 0.1, 0.5, 1.0])
+def test_growth_derivatives_match_finite_differences(om, a):
+    h = 1e-5 * a
+    for f, fp in [(cosmo.growth_D1, cosmo.growth_D1_prime), (cosmo.growth_D2, cosmo.growth_D2_prime)]:
+        fd = (f(a + h, om) - f(a - h, om)) / (2 * h)
+        assert fp(a, om) == pytest.approx(fd, rel=1e-8)
+
+
+@pytest.mark.parametrize("a", [0.02, 0.3, 1.0])
+def test_growth_derivatives_einstein_de_sitter(a):
+    # Omega_m = 1: D1 = a, D2 = -(3/7) a^2 (Omega(a) = 1), so D1' = 1, D2' = -(6/7) a.
+    assert cosmo.growth_D1(a, 1.0) == pytest.approx(a, rel=1e-12)
+    assert cosmo.growth_D1_prime(a, 1.0) == pytest.approx(1.0, rel=1e-12)
+    assert cosmo.growth_D2_prime(a, 1.0) == pytest.approx(-6.0 / 7.0 * a, rel=1e-12)
+
+
+@pytest.mark.parametrize("om", [0.27, 0.5])
+def test_growth_rate_matches_growth_ode(om):
+    # Linear growth ODE D'' + (3/a + E'/E) D' = (3/2) Om D / (a^5 E^2), growing mode
+    # D = a deep in matter domination; f = a D'/D at late times from the ODE solution.
+    E = lambda a: np.sqrt(om / a ** 3 + 1 - om)
+    dE = lambda a: -1.5 * om / (a ** 4 * E(a))
+    rhs = lambda a, y: [y[1], -(3 / a + dE(a) / E(a)) * y[1] + 1.5 * om / (a ** 5 * E(a) ** 2) * y[0]]
+    sol = solve_ivp(rhs, [1e-4, 1.0], [1e-4, 1.0], rtol=1e-12, atol=1e-16, dense_output=True)
+    for a in [0.1, 0.5, 1.0]:
+        D, Dp = sol.sol(a)
+        f = a * cosmo.growth_D1_prime(a, om) / cosmo.growth_D1(a, om)
+        assert f == pytest.approx(a * Dp / D, rel=1e-7)
+        # and the second-order rate of D2 = -(3/7) D1^2 Omega^(-1/143): 2 f - (1/143) dln Omega/dln a
+        f2 = a * cosmo.growth_D2_prime(a, om) / cosmo.growth_D2(a, om)
+        dlnom = -3 * (1 - om) * a ** 3 / (om + (1 - om) * a ** 3)
+        assert f2 == pytest.approx(2 * a * Dp / D - dlnom / 143, rel=1e-7)
+
+
+def small_state(n=8, nm=16, box=64.0):
+    k, p = bbks_table()
+    return cola.init_state(white_noise(5, n), box, nm, k, p)
+
+
+def test_initial_velocity_is_the_2lpt_trajectory_derivative():
+    # At a_v = a_x the residual is zero: v = a^2 dx_2LPT/dt, with dx/dt = adot dx/da.
+    # dx/da by central differences of the oracle's own 2LPT displacement.
+    st = small_state()
+    a = st.a_x
+    h = 1e-5 * a
+    dxda = (ic.initial_displacement(st.psi1, st.psi2, a + h, OM)
+            - ic.initial_displacement(st.psi1, st.psi2, a - h, OM)) / (2 * h)
+    v = velocity.full_velocity(st)
+    np.testing.assert_allclose(v, a * a * cosmo.adot(a, OM) * dxda, rtol=1e-7, atol=1e-9 * np.abs(v).max())
+    # Redshift-space shift (dx/dt)/H = a dx/da along the chosen axis only.
+    for axis in range(3):
+        ds = velocity.rsd_displacement(st, v, axis)
+        np.testing.assert_allclose(ds[axis] - st.d[axis], a * dxda[axis], rtol=1e-7,
+                                   atol=1e-9 * np.abs(dxda).max())
+        others = [d for d in range(3) if d != axis]
+        assert np.array_equal(ds[others], st.d[others])
+
+
+def test_kaiser_factor_for_a_plane_wave_in_eds():
+    # Omega_m = 1, one plane wave along the line of sight: Psi2 = 0 and f = 1, so the
+    # redshift-space displacement is (1 + f) D1 Psi1 = 2 d; across the line of sight it is d.
+    p1, p2 = plane_wave_fields(8, 100.0, 0.3, axis=2)
+    assert np.abs(p2).max() < 1e-12 * np.abs(p1).max()
+    st = cola.state_from_fields(p1, p2, 100.0, 8, om=1.0)
+    v = velocity.full_velocity(st)
+    ds = velocity.rsd_displacement(st, v, 2)
+    np.testing.assert_allclose(ds[2], 2.0 * st.d[2], rtol=1e-12, atol=1e-15)
+    ds0 = velocity.rsd_displacement(st, v, 0)
+    np.testing.assert_allclose(ds0, st.d, rtol=0, atol=1e-15)
+
+
+def test_velocity_exact_for_1d_dynamics_after_steps():
+    # Before shell crossing the exact 1D force is alpha * (x - q); the trajectory is
+    # x = q + D1(a) Psi1, so v = a^2 adot D1'(a) Psi1 at every step (a_v != a_x there).
+    p1, p2 = plane_wave_fields(4, 100.0, 0.3)
+    st = cola.state_from_fields(p1, p2, 100.0, 4)
+    force = lambda s, c: c["alpha"] * s.d
+    e = step_edges()
+    for i in range(1, 5):
+        cola.step(st, e[i], force)
+        a = st.a_x
+        assert st.a_v != a
+        v = velocity.full_velocity(st, force)
+        want = a * a * cosmo.adot(a, OM) * cosmo.growth_D1_prime(a, OM) * p1
+        np.testing.assert_allclose(v, want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
+
+
+def test_position_time_velocity_continues_the_kick():
+    # The kick ansatz is linear in a^n at a fixed force time: carrying v_res from a_v to
+    # a_x and then stepping from (a_v = a_x) must give the same state as stepping directly.
+    st = small_state()
+    e = step_edges()
+    cola.step(st, e[1])
+    cola.step(st, e[2])
+    alt = copy.deepcopy(st)
+    alt.v = velocity.residual_velocity_at_position_time(st)
+    alt.a_v = alt.a_x
+    assert np.abs(alt.v - st.v).max() > 1e-3 * np.abs(st.v).max()   # the half kick is not negligible
+    cola.step(st, e[3])
+    cola.step(alt, e[3])
+    np.testing.assert_allclose(alt.v, st.v, rtol=1e-10, atol=1e-12 * np.abs(st.v).max())
+    np.testing.assert_allclose(alt.d, st.d, rtol=1e-10, atol=1e-12 * np.abs(st.d).max())
