@@ -17,7 +17,9 @@ where the slots fit in HBM), the 96-mock ensemble batched and one by one
 (batched), and the library's per-stage HIP event timers, which give the
 dominant kernel's achieved bandwidth against the 8 TB/s HBM peak (roofline;
 `traffic` comes from the committed counter summary while its kernel source
-is unchanged).  The FP64 CPU oracle is timed on one step of the same
+is unchanged), followed by the particle velocities at the final position
+time with their redshift-space displacement (velocity: whole call with its
+force pipeline, and the velocity kernel against its algorithmic bytes).  The FP64 CPU oracle is timed on one step of the same
 workload on the host cores (cpu_baseline).
 
 Prints one JSON line.
@@ -65,6 +67,31 @@ STAGE_SOURCES = {
     "fft_y": ["k_fft.hip"], "fft_x_green": ["k_fft.hip"], "ifft_y": ["k_fft.hip"],
     "ifft_z": ["k_fft.hip"], "ifft_y_grad": ["k_fft.hip"], "kick_drift": ["k_particles.hip"],
 }
+
+
+def velocity_leg(sim, cfg, reps=3):
+    """cola_velocity at the final state (a_v != a_x, so the call runs the force
+    pipeline, then the velocity kernel with a redshift-space output): whole-call
+    time and the kernel's own time from the stage timers (HIP events on the
+    library's stream) against its algorithmic bytes."""
+    import torch
+    vel, sdisp = sim.particles(), sim.particles()
+    sim.velocity(vel, rsd_axis=2, sdisp=sdisp)
+    torch.cuda.synchronize()
+    sim.stage_times()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.velocity(vel, rsd_axis=2, sdisp=sdisp)
+    torch.cuda.synchronize()
+    ms_call = (time.perf_counter() - t0) / reps * 1e3
+    ms, cnt = sim.stage_times()["velocity"]
+    ms_k = ms / max(cnt, 1)
+    n_p, M = cfg.np_side ** 3, cfg.nmesh ** 3
+    nbytes = 72 * n_p + 12 * min(M, 8 * n_p)   # state reads 48, outputs 24, CIC gathers
+    return {"ms_call": round(ms_call, 3), "ms_kernel": round(ms_k, 4), "bytes_alg": nbytes,
+            "GB/s": round(nbytes / (ms_k * 1e-3) / 1e9, 1),
+            "note": "velocity at the position time plus the redshift-space displacement (axis 2); "
+                    "the call includes the force pipeline at the current positions"}
 
 
 def measured_traffic(stage, workload):
@@ -231,6 +258,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
+    ap.add_argument("--no-velocity", action="store_true", help="skip the velocity / redshift-space leg")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (for HBM counter "
                          "calibration under rocprofv3) and exit")
@@ -299,6 +327,7 @@ def main():
     for i in range(1, args.steps if args.steps > 1 else 2):
         simt.step(e[i], e[i + 1])
     st = simt.stage_times()
+    snapshot = None if args.no_velocity else velocity_leg(simt, cfg)
     simt.close()
     sb = stage_bytes(cfg.np_side, cfg.nmesh)
     stages = {}
@@ -348,6 +377,7 @@ def main():
             "ms_forward_step": kept[0], "ms_adjoint_step": kept[1], "slots_GB": kept[2],
             "note": "forward steps keep their force meshes (one slot per step); the adjoint reads them"},
         "batched": batched,
+        "velocity": snapshot,
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,

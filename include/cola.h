@@ -58,7 +58,8 @@ extern "C" {
 #define COLA_STAGE_IFFT_Z    6  /* inverse complex-to-real pass along z, 3 meshes    */
 #define COLA_STAGE_KICKDRIFT 7  /* CIC readout fused with kick and drift             */
 #define COLA_STAGE_IFFT_Y_GRAD 8  /* inverse y pass giving the y and z components    */
-#define COLA_NSTAGE          9
+#define COLA_STAGE_VELOCITY  9  /* cola_velocity's particle kernel (not in a step)    */
+#define COLA_NSTAGE          10
 
 typedef struct cola_ctx cola_ctx;
 
@@ -139,6 +140,23 @@ int cola_pk(cola_ctx* ctx, int32_t ngrid, const double* k_edges, int32_t nbins,
 /* PM force F (mesh units) at the current positions, 3 * np^3 float32 into
  * dev_force; no state change (the force of Sec. 2.2 as used by cola_step). */
 int cola_force(cola_ctx* ctx, float* dev_force);
+
+/* Canonical particle velocity v = a^2 dx/dt at the position time a_x (Koda
+ * et al. 2015, Sec. 2.1: residual velocity plus the time derivative of the
+ * 2LPT trajectory, a^2 adot (D1' Psi1 + D2' Psi2); Sec. 2.2: the residual
+ * velocity, held at the last half step a_v, is carried to a_x by the kick
+ * ansatz with the force at the current positions) into dev_vel (3 * np^3
+ * float32, the layout and mesh units of cola_get_state; time unit 1/H0).
+ * If dev_sdisp is not NULL it also receives the redshift-space displacement
+ * (Sec. 4.4, distant observer along box axis rsd_axis in {0, 1, 2}): the
+ * displacement with v[rsd_axis] / (a adot) added to that component, the
+ * other two copied; positions wrap periodically as everywhere.  When
+ * a_v != a_x the force pipeline runs first (the force meshes are overwritten;
+ * the particle state is not changed); at the initial state (a_v = a_x) no
+ * force is needed.  dev_vel and dev_sdisp must not overlap each other or the
+ * workspace.  Errors: COLA_EINVAL for a NULL dev_vel, equal output pointers
+ * or a bad axis with dev_sdisp given; COLA_ESTATE without a particle state. */
+int cola_velocity(cola_ctx* ctx, float* dev_vel, float* dev_sdisp, int32_t rsd_axis);
 
 /* Copies the particle state out / in (device, 3 * np^3 float32 each, mesh
  * units).  Any pointer may be NULL to skip that array.  set_state also sets

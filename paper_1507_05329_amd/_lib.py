@@ -23,7 +23,7 @@ COLA_ENONFINITE = -6
 COLA_F_CHECK_FINITE = 1
 COLA_F_STAGE_TIMERS = 2
 STAGES = ["sort", "deposit", "fft_z", "fft_y", "fft_x_green", "ifft_y", "ifft_z", "kick_drift",
-          "ifft_y_grad"]
+          "ifft_y_grad", "velocity"]
 
 
 class cola_params(C.Structure):
@@ -49,6 +49,7 @@ _SIGS = {
     "cola_density": (C.c_int, [_P, _P]),
     "cola_pk": (C.c_int, [_P, _I, _DP, _I, _DP, _DP, C.POINTER(C.c_int64)]),
     "cola_force": (C.c_int, [_P, _P]),
+    "cola_velocity": (C.c_int, [_P, _P, _P, C.c_int32]),
     "cola_get_state": (C.c_int, [_P, _P, _P, _P, _P, _DP, _DP]),
     "cola_set_state": (C.c_int, [_P, _P, _P, _P, _P, _D, _D]),
     "cola_fft3d": (C.c_int, [_P, _I, _P, _I]),

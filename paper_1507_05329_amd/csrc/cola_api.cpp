@@ -512,6 +512,38 @@ int cola_force(cola_ctx* c, float* out) {
   return COLA_OK;
 }
 
+int cola_velocity(cola_ctx* c, float* vel, float* sdisp, int32_t axis) {
+  if (!c || !vel) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  if (sdisp && (axis < 0 || axis > 2)) return fail(c, COLA_EINVAL, "rsd_axis must be 0, 1 or 2");
+  if (sdisp == vel) return fail(c, COLA_EINVAL, "dev_vel and dev_sdisp must differ");
+  const double om = c->p.omega_m, n = c->p.n_lpt, a = c->a_x;
+  const double adot = a * hubble_E(a, om), alpha = 1.5 * om / a;
+  const double D1 = growth_D1(a, om), D2 = growth_D2(a, om);
+  // the kick from a_v to a_x (zero at the initial state, where a_v = a_x)
+  const double K = c->a_v == a ? 0.0 : kick_factor(c->a_v, a, a, om, n);
+  VelCoef k{};
+  k.K = (float)K;
+  k.u1 = (float)(a * a * adot * growth_D1_prime(a, om) - K * alpha * D1);
+  k.u2 = (float)(a * a * adot * growth_D2_prime(a, om) - K * alpha * (D2 - D1 * D1));
+  k.rsd = (float)(1.0 / (a * adot));
+  const float* g[3] = {nullptr, nullptr, nullptr};
+  if (K != 0.0) {
+    StepCoef v{};
+    v.gscale = (float)green_scale(c->p.nmesh, alpha);
+    launch_set_coef(c->coef, v, 1, 0, c->stream);
+    force_meshes(c, c->disp);
+    for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<const float*>(c->mesh[d]);
+  }
+  {
+    StageTimer t(c, COLA_STAGE_VELOCITY);
+    launch_velocity(g[0], g[1], g[2], 2 * padded_cols(c->p.nmesh), c->disp, c->vres, c->psi1, c->psi2, c->p.np,
+                    c->p.nmesh, k, vel, sdisp, axis, c->stream);
+  }
+  LAUNCH_CHECK(c, "cola_velocity");
+  return COLA_OK;
+}
+
 int cola_density(cola_ctx* c, float* out) {
   if (!c || !out) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");

@@ -43,6 +43,9 @@ double growth_D1(double a, double om);
 double growth_D2(double a, double om);
 double kick_factor(double a_v, double a_x, double a_h, double om, double n);
 double drift_factor(double a0, double a1, double a_h, double om, double n);
+// dD1/da and dD2/da (velocity of the 2LPT trajectory).
+double growth_D1_prime(double a, double om);
+double growth_D2_prime(double a, double om);
 // ln-ln interpolation of a P(k) table, end segments extended.
 double interp_pk(double k, const double* kt, const double* pt, int nk);
 
@@ -119,6 +122,17 @@ void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s);
 // Inverse y pass of the PM gradients: b -> IDFT_y[i n_y b] in place, IDFT_y[i n_z b] -> gz.
 void fft_y_grad_yz(float2* b, float2* gz, int n, const TwiddleSet& tw, hipStream_t s, int nmock = 1,
                    long mstride = 0);
+// Velocity at the position time (k_velocity.hip): v = v_res + K F + u1 Psi1 + u2 Psi2,
+// redshift-space shift rsd * v along one axis.
+struct VelCoef {
+  float K;       // kick factor from a_v to a_x (0: no force read)
+  float u1, u2;  // Psi1, Psi2 coefficients (2LPT velocity minus the kick's 2LPT force terms)
+  float rsd;     // 1 / (a adot)
+};
+// g0 == nullptr: no force gather (K must be 0); sdisp == nullptr: no redshift-space output.
+void launch_velocity(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+                     const float* vres, const float* psi1, const float* psi2, int np, int nm,
+                     const VelCoef& k, float* vel, float* sdisp, int axis, hipStream_t s);
 // Force readout + kick/drift (k_particles.hip).
 void launch_set_coef(StepCoef* dst, const StepCoef& v, int nmock, long mstride, hipStream_t s);
 void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2,

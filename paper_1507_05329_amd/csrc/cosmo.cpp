@@ -80,6 +80,22 @@ double drift_factor(double a0, double a1, double a_h, double om, double n) {
   return integrate(f, a0, a1, 1e-14);
 }
 
+// Derivative of the Heath form D1 = c E(a) int_0^a da'/(a'E)^3 by the product
+// rule: D1 (dE/da)/E + c E/(a E)^3, dE/da = -3 Om/(2 a^4 E), c = 2.5 Om/heath(1).
+double growth_D1_prime(double a, double om) {
+  const double e = hubble_E(a, om);
+  const double de = -1.5 * om / (a * a * a * a * e);
+  const double ae = a * e;
+  return growth_D1(a, om) * de / e + 2.5 * om / heath(1.0, om) * e / (ae * ae * ae);
+}
+
+// D2 = -(3/7) D1^2 Omega(a)^(-1/143): D2 (2 D1'/D1 - (1/143) dln Omega/da),
+// dln Omega/da = -3 (1 - Om) a^2 / (Om + (1 - Om) a^3).
+double growth_D2_prime(double a, double om) {
+  const double dlnom = -3.0 * (1.0 - om) * a * a / (om + (1.0 - om) * a * a * a);
+  return growth_D2(a, om) * (2.0 * growth_D1_prime(a, om) / growth_D1(a, om) - dlnom / 143.0);
+}
+
 double interp_pk(double k, const double* kt, const double* pt, int nk) {
   if (!(k > 0)) return 0.0;
   const double x = std::log(k);

@@ -1,0 +1,84 @@
+// Particle velocities at the position time and redshift-space displacements
+// (Koda et al. 2015: Sec. 2.1, velocity = residual + time derivative of the
+// 2LPT trajectory; Sec. 2.2, canonical velocity a^2 dx/dt and the kick
+// ansatz that carries the residual velocity between kicks; Sec. 4.4,
+// redshift-space position shifted along the line of sight by
+// (dx/dt . xhat) / H).
+//
+// Per particle (one thread each, the readout's column order):
+//   F_d  = sum_s w_s g_d[c + s]                 (only when the kick is not zero)
+//   v_d  = v_res_d + K F_d + u1 Psi1_d + u2 Psi2_d
+//          K  = kick factor from a_v to a_x with the force at a_x,
+//          u1 = a^2 adot D1' - K alpha D1,  u2 = a^2 adot D2' - K alpha (D2 - D1^2)
+//   s_d  = d_d + (d == axis ? v_d / (a adot) : 0)
+// Nothing of the state is written.
+#include "cola_device.h"
+#include "cola_internal.h"
+
+namespace cola {
+
+template <bool KICK, bool RSD>
+__global__ __launch_bounds__(256) void k_velocity(const float* __restrict__ g0, const float* __restrict__ g1,
+                                                  const float* __restrict__ g2, long row_stride,
+                                                  const float* __restrict__ disp, const float* __restrict__ vres,
+                                                  const float* __restrict__ psi1, const float* __restrict__ psi2,
+                                                  int np, int nm, long np3, VelCoef k, float* __restrict__ vel,
+                                                  float* __restrict__ sdisp, int axis) {
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  if (i >= np3) return;
+  float v[3], p1[3], p2[3], d[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    v[e] = vres[e * np3 + i];
+    p1[e] = psi1[e * np3 + i];
+    p2[e] = psi2[e * np3 + i];
+    if constexpr (RSD) d[e] = disp[e * np3 + i];
+  }
+  float F[3] = {0.f, 0.f, 0.f};
+  if constexpr (KICK) {
+    int c[3];
+    float f[3];
+    home_cell(disp, np3, (uint32_t)i, np, nm, 1.0f, c, f);
+    const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
+    const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
+    const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
+    const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
+                          ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
+    const float* g[3] = {g0, g1, g2};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const float w = cic_weight(f, s);
+      const long idx = rows[s >> 1] + ((s & 1) ? cz1 : c[2]);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) F[e] += w * g[e][idx];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const float ve = v[e] + k.K * F[e] + k.u1 * p1[e] + k.u2 * p2[e];
+    vel[e * np3 + i] = ve;
+    if constexpr (RSD) sdisp[e * np3 + i] = e == axis ? d[e] + k.rsd * ve : d[e];
+  }
+}
+
+void launch_velocity(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+                     const float* vres, const float* psi1, const float* psi2, int np, int nm,
+                     const VelCoef& k, float* vel, float* sdisp, int axis, hipStream_t s) {
+  const long np3 = (long)np * np * np;
+  const dim3 grid((unsigned)((np3 + 255) / 256));
+  const bool kick = g0 != nullptr, rsd = sdisp != nullptr;
+  if (kick && rsd)
+    hipLaunchKernelGGL((k_velocity<true, true>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+                       psi2, np, nm, np3, k, vel, sdisp, axis);
+  else if (kick)
+    hipLaunchKernelGGL((k_velocity<true, false>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+                       psi2, np, nm, np3, k, vel, sdisp, axis);
+  else if (rsd)
+    hipLaunchKernelGGL((k_velocity<false, true>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+                       psi2, np, nm, np3, k, vel, sdisp, axis);
+  else
+    hipLaunchKernelGGL((k_velocity<false, false>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres,
+                       psi1, psi2, np, nm, np3, k, vel, sdisp, axis);
+}
+
+}  // namespace cola

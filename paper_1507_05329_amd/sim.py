@@ -121,6 +121,18 @@ class ColaSim:
         self._chk(self.lib.cola_force(self.ctx, _ptr(out)), "force")
         return out
 
+    def velocity(self, out=None, rsd_axis=None, sdisp=None):
+        """Canonical particle velocity at the position time a_x (3 x np^3, mesh
+        units); with rsd_axis also the redshift-space displacement along that
+        axis.  Returns out, or (out, sdisp) when rsd_axis is given."""
+        if out is None:
+            out = self.particles()
+        if rsd_axis is not None and sdisp is None:
+            sdisp = self.particles()
+        self._chk(self.lib.cola_velocity(self.ctx, _ptr(out), _ptr(sdisp) if rsd_axis is not None else None,
+                                         -1 if rsd_axis is None else int(rsd_axis)), "velocity")
+        return out if rsd_axis is None else (out, sdisp)
+
     def pk(self, edges, ngrid=None):
         edges = np.ascontiguousarray(edges, np.float64)
         nb = len(edges) - 1
