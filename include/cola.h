@@ -137,6 +137,17 @@ int cola_density(cola_ctx* ctx, float* dev_out);
 int cola_pk(cola_ctx* ctx, int32_t ngrid, const double* k_edges, int32_t nbins,
             double* host_kmean, double* host_pk, int64_t* host_nmodes);
 
+/* cola_density and cola_pk of another displacement field on the same
+ * particle lattice: dev_disp holds 3 * np^3 float32 displacements in mesh
+ * units, the layout of cola_get_state (for example the redshift-space
+ * displacement of cola_velocity, Sec. 4.4).  Positions wrap periodically;
+ * the particle state is not read or changed (the force meshes are
+ * overwritten).  Same outputs, bounds and errors as cola_density / cola_pk,
+ * COLA_EINVAL for a NULL dev_disp. */
+int cola_density_of(cola_ctx* ctx, const float* dev_disp, float* dev_out);
+int cola_pk_of(cola_ctx* ctx, const float* dev_disp, int32_t ngrid, const double* k_edges, int32_t nbins,
+               double* host_kmean, double* host_pk, int64_t* host_nmodes);
+
 /* PM force F (mesh units) at the current positions, 3 * np^3 float32 into
  * dev_force; no state change (the force of Sec. 2.2 as used by cola_step). */
 int cola_force(cola_ctx* ctx, float* dev_force);

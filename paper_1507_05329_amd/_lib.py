@@ -50,6 +50,8 @@ _SIGS = {
     "cola_pk": (C.c_int, [_P, _I, _DP, _I, _DP, _DP, C.POINTER(C.c_int64)]),
     "cola_force": (C.c_int, [_P, _P]),
     "cola_velocity": (C.c_int, [_P, _P, _P, C.c_int32]),
+    "cola_density_of": (C.c_int, [_P, _P, _P]),
+    "cola_pk_of": (C.c_int, [_P, _P, C.c_int32, _DP, C.c_int32, _DP, _DP, C.POINTER(C.c_int64)]),
     "cola_get_state": (C.c_int, [_P, _P, _P, _P, _P, _DP, _DP]),
     "cola_set_state": (C.c_int, [_P, _P, _P, _P, _P, _D, _D]),
     "cola_fft3d": (C.c_int, [_P, _I, _P, _I]),

@@ -552,10 +552,17 @@ int cola_density(cola_ctx* c, float* out) {
   return COLA_OK;
 }
 
-int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double* kmean, double* pk,
-            int64_t* nmodes) {
-  if (!c || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
-  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+int cola_density_of(cola_ctx* c, const float* disp, float* out) {
+  if (!c || !disp || !out) return fail(c, COLA_EINVAL, "null argument");
+  deposit(c, c->p.nmesh, out, c->p.nmesh, 1, disp);
+  LAUNCH_CHECK(c, "cola_density_of");
+  return COLA_OK;
+}
+
+namespace {
+
+int pk_of(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32_t nbins, double* kmean,
+          double* pk, int64_t* nmodes) {
   if (nbins < 1 || nbins > kMaxBins) return fail(c, COLA_EINVAL, "nbins out of range");
   if (ng < 32 || ng > c->p.nmesh || !fft_size_supported(ng))
     return fail(c, COLA_EUNSUPPORTED, "ngrid must be a supported size in [32, nmesh]");
@@ -566,7 +573,7 @@ int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double*
   HIP_TRY(c, hipMemcpyAsync(c->pk_edges, edges, (nbins + 1) * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   float2* m = c->mesh[0];
-  deposit(c, ng, reinterpret_cast<float*>(m), 2 * padded_cols(ng), 1, c->disp);
+  deposit(c, ng, reinterpret_cast<float*>(m), 2 * padded_cols(ng), 1, disp);
   fft3d_forward(m, ng, c->tw, c->stream);
   launch_pk_bin(m, ng, c->p.box, c->pk_edges, nbins, c->pk_partial, kPkChunks, c->stream);
   launch_pk_reduce(c->pk_partial, nbins, kPkChunks, c->pk_out, c->stream);
@@ -582,6 +589,21 @@ int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double*
     pk[b] = n > 0 ? h[3 * b + 1] / n : NAN;
   }
   return COLA_OK;
+}
+
+}  // namespace
+
+int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double* kmean, double* pk,
+            int64_t* nmodes) {
+  if (!c || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  return pk_of(c, c->disp, ng, edges, nbins, kmean, pk, nmodes);
+}
+
+int cola_pk_of(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32_t nbins, double* kmean,
+               double* pk, int64_t* nmodes) {
+  if (!c || !disp || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
+  return pk_of(c, disp, ng, edges, nbins, kmean, pk, nmodes);
 }
 
 int cola_get_state(cola_ctx* c, float* d, float* v, float* p1, float* p2, double* ax, double* av) {

@@ -109,10 +109,15 @@ class ColaSim:
         for a0, a1 in zip(edges[:-1], edges[1:]):
             self.step(a0, a1)
 
-    def density(self, out=None) -> torch.Tensor:
+    def density(self, out=None, disp=None) -> torch.Tensor:
+        """Density contrast of the current positions, or of the displacement
+        field ``disp`` (3 x np^3, mesh units) on the same particle lattice."""
         if out is None:
             out = torch.empty((self.nmesh,) * 3, dtype=torch.float32, device=self.device)
-        self._chk(self.lib.cola_density(self.ctx, _ptr(out)), "density")
+        if disp is None:
+            self._chk(self.lib.cola_density(self.ctx, _ptr(out)), "density")
+        else:
+            self._chk(self.lib.cola_density_of(self.ctx, _ptr(disp), _ptr(out)), "density_of")
         return out
 
     def force(self, out=None) -> torch.Tensor:
@@ -133,13 +138,20 @@ class ColaSim:
                                          -1 if rsd_axis is None else int(rsd_axis)), "velocity")
         return out if rsd_axis is None else (out, sdisp)
 
-    def pk(self, edges, ngrid=None):
+    def pk(self, edges, ngrid=None, disp=None):
+        """Binned P(k) of the current positions, or of the displacement field
+        ``disp`` (3 x np^3, mesh units) on the same particle lattice."""
         edges = np.ascontiguousarray(edges, np.float64)
         nb = len(edges) - 1
         km, p = np.zeros(nb), np.zeros(nb)
         nm = np.zeros(nb, np.int64)
-        self._chk(self.lib.cola_pk(self.ctx, ngrid or self.nmesh, dptr(edges), nb, dptr(km), dptr(p),
-                                   nm.ctypes.data_as(C.POINTER(C.c_int64))), "pk")
+        cnt = nm.ctypes.data_as(C.POINTER(C.c_int64))
+        if disp is None:
+            self._chk(self.lib.cola_pk(self.ctx, ngrid or self.nmesh, dptr(edges), nb, dptr(km), dptr(p), cnt),
+                      "pk")
+        else:
+            self._chk(self.lib.cola_pk_of(self.ctx, _ptr(disp), ngrid or self.nmesh, dptr(edges), nb, dptr(km),
+                                          dptr(p), cnt), "pk_of")
         return km, p, nm
 
     def get_state(self, which=("disp", "vres", "psi1", "psi2"), out=None):

@@ -148,3 +148,64 @@ def test_velocity_production_size_against_fp64_combination():
         assert rel_l2(sd[1].astype(np.float64) - d[1], ref[1] / (a * adot)) < 1e-5
     finally:
         sim.close()
+
+
+def test_redshift_space_density_and_pk(small):
+    # Redshift-space displacement after 3 steps: cola_density_of is bit-exact against
+    # the FP32 replay of the deposit, cola_pk_of agrees with the oracle estimator on the
+    # same positions, and neither reads or changes the particle state.
+    from oracle import cic_fp32, pk
+    say("[gpu] redshift-space density and P(k)")
+    L, nm = 100.0, 64
+    small.init_from_noise(torch.from_numpy(white_noise(13, 32)).cuda(), *bbks_table())
+    e = step_edges()
+    for i in range(3):
+        small.step(e[i], e[i + 1])
+    before = state_bytes(small)
+    real = small.density().cpu().numpy()
+    _, sd = small.velocity(rsd_axis=2)
+    sd32 = sd.cpu().numpy()
+    dens = small.density(disp=sd).cpu().numpy()
+    assert dens.tobytes() == cic_fp32.density(sd32, 32, nm).tobytes()
+    assert dens.tobytes() != real.tobytes()
+    edges = pk.linear_edges(L, nm, dk=2 * np.pi / L)
+    km, p_g, n_g = small.pk(edges, disp=sd)
+    pos = ic.lattice(32, L) + sd32.astype(np.float64) * (L / nm)
+    k_e, p_e, n_e = pk.power_spectrum(pos, L, nm, edges)
+    assert np.array_equal(n_g, n_e)
+    ok = n_e > 0
+    assert np.abs(p_g[ok] / p_e[ok] - 1).max() < 1e-4
+    assert state_bytes(small) == before
+    assert small.density().cpu().numpy().tobytes() == real.tobytes()
+
+
+def test_kaiser_boost_in_the_linear_regime(small):
+    # At a = 0.02 the displacements are linear and the redshift-space density is the
+    # real-space one with every mode multiplied by (1 + f mu^2) (mu along the line of
+    # sight, f = dln D1/dln a).  Expected P(k): the oracle estimator applied to the GPU's
+    # real-space density boosted that way; the rest is O((k Psi)^2), below 1% here.
+    from oracle import pk
+    say("[gpu] Kaiser boost at a = 0.02")
+    L, nm = 100.0, 64
+    small.init_from_noise(torch.from_numpy(white_noise(14, 32)).cuda(), *bbks_table())
+    _, sd = small.velocity(rsd_axis=0)
+    edges = pk.linear_edges(L, nm, dk=2 * np.pi / L)
+    _, p_s, n = small.pk(edges, disp=sd)
+    a = 0.02
+    f = a * cosmo.growth_D1_prime(a, OM) / cosmo.growth_D1(a, OM)
+    dr = np.fft.rfftn(small.density().cpu().numpy().astype(np.float64))
+    kx = np.fft.fftfreq(nm)[:, None, None]
+    ky = np.fft.fftfreq(nm)[None, :, None]
+    kz = np.fft.rfftfreq(nm)[None, None, :]
+    k2 = kx * kx + ky * ky + kz * kz
+    mu2 = np.divide(kx * kx, k2, out=np.zeros_like(k2), where=k2 > 0)
+    boosted = np.fft.irfftn(dr * (1 + f * mu2), s=(nm,) * 3, axes=(0, 1, 2))
+    _, p_k, n_k = pk.power_from_delta(boosted, L, edges)
+    assert np.array_equal(n, n_k)
+    sel = (n > 0) & (edges[1:] <= 0.5)              # below half the particle Nyquist frequency
+    assert sel.sum() >= 6
+    err = np.abs(p_s[sel] / p_k[sel] - 1)
+    say("[gpu] max |P_s / P_Kaiser - 1| =", err.max())
+    assert err.max() < 0.01
+    _, p_r, _ = small.pk(edges)
+    assert (p_s[sel] / p_r[sel]).mean() > 1.5       # the boost itself (1 + 2f/3 + f^2/5 = 1.87)
