@@ -13,6 +13,11 @@ Paper passages followed (Koda et al. 2015):
   snapshots between steps.  The state holds v_res at a_v (the last half
   step) and positions at a_x; the velocity at a_x is v_res(a_v) plus the
   kick factor from a_v to a_x times F_res(x) (force at the position time).
+* Sec. 2.2, eqs. ansatz-drift and cola-drift: snapshots between steps.
+  Within the drift of the coming step the residual velocity decays as
+  (a/a_h)^n from its value after the step's kick, and the position follows
+  the drift integral of that velocity; the 2LPT part is evaluated at the
+  snapshot time.
 * Sec. 4.4 (mock catalogue): redshift-space position s = x + (v.xhat)/(aH)
   xhat, v there the peculiar velocity a dx/dt, so the comoving shift is
   (dx/dt . xhat)/H = v_canonical . xhat / (a adot).
@@ -72,3 +77,30 @@ def rsd_displacement(state: State, v: np.ndarray, axis: int) -> np.ndarray:
     d = state.d.copy()
     d[axis] = d[axis] + v[axis] / (c["a"] * c["adot"])
     return d
+
+
+def snapshot(state: State, a1: float, a_s: float, force=None):
+    """Displacement and canonical velocity at a_s in [a_x, a1] within the coming
+    step a_x -> a1 (the state is not changed).
+
+    Sec. 2.2: the step's kick (eq. cola-kick) takes v_res to the half step
+    a_h = (a_x + a1)/2 with F_res(x); during the drift the residual velocity
+    follows the drift ansatz v_res(a) = v_res(a_h) (a/a_h)^n, whose position
+    integral is eq. cola-drift from a_x to a_s; the 2LPT part is evaluated at a_s.
+    At a_s = a1 the displacement is the step's.
+    """
+    c = cosmo.step_coefficients(state.a_x, state.a_v, a1, state.om, state.n_lpt)
+    F = pm.pm_force(state.positions(), state.nmesh, state.box, c["alpha"]) \
+        if force is None else force(state, c)
+    F_res = F - c["alpha"] * (c["D1"] * state.psi1 + (c["D2"] - c["D1"] ** 2) * state.psi2)
+    v_half = state.v + c["K"] * F_res
+    om, n, a_h = state.om, state.n_lpt, c["a_h"]
+    I = cosmo.drift_factor(state.a_x, a_s, a_h, om, n)
+    d = (state.d + I * v_half
+         + (cosmo.growth_D1(a_s, om) - c["D1"]) * state.psi1
+         + (cosmo.growth_D2(a_s, om) - c["D2"]) * state.psi2)
+    u = a_s * a_s * cosmo.adot(a_s, om)
+    v = ((a_s / a_h) ** n * v_half
+         + u * cosmo.growth_D1_prime(a_s, om) * state.psi1
+         + u * cosmo.growth_D2_prime(a_s, om) * state.psi2)
+    return d, v

@@ -125,3 +125,54 @@ def test_position_time_velocity_continues_the_kick():
     cola.step(alt, e[3])
     np.testing.assert_allclose(alt.v, st.v, rtol=1e-10, atol=1e-12 * np.abs(st.v).max())
     np.testing.assert_allclose(alt.d, st.d, rtol=1e-10, atol=1e-12 * np.abs(st.d).max())
+
+
+def test_snapshot_ends_on_the_step_and_starts_on_the_state():
+    st = small_state()
+    e = step_edges()
+    cola.step(st, e[1])
+    d0 = st.d.copy()
+    d_a, _ = velocity.snapshot(st, e[2], st.a_x)
+    np.testing.assert_allclose(d_a, d0, rtol=0, atol=1e-15 * np.abs(d0).max())
+    d_b, _ = velocity.snapshot(st, e[2], e[2])
+    cola.step(st, e[2])
+    np.testing.assert_allclose(d_b, st.d, rtol=1e-13, atol=1e-13 * np.abs(st.d).max())
+
+
+def test_snapshot_velocity_is_the_derivative_of_its_position():
+    # dx/dt = v / a^2, so dx/da = v / (a^2 adot): central differences of the
+    # snapshot position in a_s against its velocity, inside the drift step.
+    st = small_state()
+    e = step_edges()
+    cola.step(st, e[1])
+    cola.step(st, e[2])
+    a1 = e[3]
+    F = {}
+    def frozen(s, c):                       # one force evaluation for all snapshots
+        if "F" not in F:
+            from oracle import pm
+            F["F"] = pm.pm_force(s.positions(), s.nmesh, s.box, c["alpha"])
+        return F["F"]
+    for a_s in [st.a_x + 0.25 * (a1 - st.a_x), st.a_x + 0.7 * (a1 - st.a_x)]:
+        h = 1e-5 * a_s
+        dp, _ = velocity.snapshot(st, a1, a_s + h, frozen)
+        dm, _ = velocity.snapshot(st, a1, a_s - h, frozen)
+        _, v = velocity.snapshot(st, a1, a_s, frozen)
+        want = v / (a_s * a_s * cosmo.adot(a_s, OM))
+        np.testing.assert_allclose((dp - dm) / (2 * h), want, rtol=1e-6, atol=1e-8 * np.abs(want).max())
+
+
+def test_snapshot_exact_for_1d_dynamics():
+    # Exact 1D force: x = q + D1(a) Psi1 and v = a^2 adot D1'(a) Psi1 at any a.
+    p1, p2 = plane_wave_fields(4, 100.0, 0.3)
+    st = cola.state_from_fields(p1, p2, 100.0, 4)
+    force = lambda s, c: c["alpha"] * s.d
+    e = step_edges()
+    cola.step(st, e[1], force)
+    cola.step(st, e[2], force)
+    for a_s in [e[2], 0.5 * (e[2] + e[3]), e[3] - 0.01]:
+        d, v = velocity.snapshot(st, e[3], a_s, force)
+        np.testing.assert_allclose(d, cosmo.growth_D1(a_s, OM) * p1, rtol=1e-10,
+                                   atol=1e-12 * np.abs(p1).max())
+        want = a_s * a_s * cosmo.adot(a_s, OM) * cosmo.growth_D1_prime(a_s, OM) * p1
+        np.testing.assert_allclose(v, want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
