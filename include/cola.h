@@ -58,7 +58,7 @@ extern "C" {
 #define COLA_STAGE_IFFT_Z    6  /* inverse complex-to-real pass along z, 3 meshes    */
 #define COLA_STAGE_KICKDRIFT 7  /* CIC readout fused with kick and drift             */
 #define COLA_STAGE_IFFT_Y_GRAD 8  /* inverse y pass giving the y and z components    */
-#define COLA_STAGE_VELOCITY  9  /* cola_velocity's particle kernel (not in a step)    */
+#define COLA_STAGE_VELOCITY  9  /* cola_velocity / cola_snapshot particle kernel      */
 #define COLA_NSTAGE          10
 
 typedef struct cola_ctx cola_ctx;
@@ -136,6 +136,26 @@ int cola_density(cola_ctx* ctx, float* dev_out);
  * mean |k| and P.  Synchronises the stream.  nbins <= 4096. */
 int cola_pk(cola_ctx* ctx, int32_t ngrid, const double* k_edges, int32_t nbins,
             double* host_kmean, double* host_pk, int64_t* host_nmodes);
+
+/* Snapshot at a_s inside the coming step a_x -> a1 (a_x <= a_s <= a1),
+ * without changing the state (Sec. 2.2, eqs. ansatz-drift and cola-drift;
+ * the paper interpolates its snapshots this way): the step's kick takes
+ * v_res to a_h = (a_x + a1)/2 with the force at the current positions, the
+ * residual velocity then decays as (a/a_h)^n_LPT and the position follows
+ * its drift integral to a_s; the 2LPT part is taken at a_s.  Writes the
+ * displacement to dev_disp and the canonical velocity to dev_vel (3 * np^3
+ * float32 each, the layout and units of cola_get_state) and, if dev_sdisp
+ * is not NULL, the redshift-space displacement along rsd_axis as
+ * cola_velocity does.  At a_s = a1 the displacement is the one cola_step
+ * would produce (to rounding); at a_s = a_x it is the current one.  The
+ * velocity at a_x differs from cola_velocity's (the drift ansatz against
+ * the kick ansatz, two interpolants of the paper).  Runs the force
+ * pipeline (the force meshes are overwritten).  Outputs must differ and not
+ * overlap the workspace.  Errors: COLA_EINVAL for NULL outputs, equal
+ * outputs, a1 <= a_x, a_s outside [a_x, a1] or a bad axis; COLA_ESTATE
+ * without a particle state. */
+int cola_snapshot(cola_ctx* ctx, double a1, double a_s, float* dev_disp, float* dev_vel, float* dev_sdisp,
+                  int32_t rsd_axis);
 
 /* cola_density and cola_pk of another displacement field on the same
  * particle lattice: dev_disp holds 3 * np^3 float32 displacements in mesh

@@ -552,6 +552,45 @@ int cola_density(cola_ctx* c, float* out) {
   return COLA_OK;
 }
 
+int cola_snapshot(cola_ctx* c, double a1, double a_s, float* dout, float* vout, float* sdisp, int32_t axis) {
+  if (!c || !dout || !vout) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  const double a0 = c->a_x;
+  if (!(a1 > a0) || !std::isfinite(a1)) return fail(c, COLA_EINVAL, "a1 must exceed the position time");
+  if (!(a_s >= a0 && a_s <= a1)) return fail(c, COLA_EINVAL, "a_s must lie in [a_x, a1]");
+  if (sdisp && (axis < 0 || axis > 2)) return fail(c, COLA_EINVAL, "rsd_axis must be 0, 1 or 2");
+  if (dout == vout || (sdisp && (sdisp == dout || sdisp == vout)))
+    return fail(c, COLA_EINVAL, "output arrays must differ");
+  const double om = c->p.omega_m, n = c->p.n_lpt;
+  double s[10];
+  step_scalars(&c->p, a0, c->a_v, a1, s);
+  const double alpha = s[0], D1 = s[1], D2 = s[2], K = s[5], a_h = s[7];
+  const double adot_s = a_s * hubble_E(a_s, om), u = a_s * a_s * adot_s;
+  SnapCoef k{};
+  k.K = (float)K;
+  k.c1 = (float)(K * alpha * D1);
+  k.c2 = (float)(K * alpha * (D2 - D1 * D1));
+  k.I = (float)drift_factor(a0, a_s, a_h, om, n);
+  k.e1 = (float)(growth_D1(a_s, om) - D1);
+  k.e2 = (float)(growth_D2(a_s, om) - D2);
+  k.sv = (float)std::pow(a_s / a_h, n);
+  k.w1 = (float)(u * growth_D1_prime(a_s, om));
+  k.w2 = (float)(u * growth_D2_prime(a_s, om));
+  k.rsd = (float)(1.0 / (a_s * adot_s));
+  StepCoef v{};
+  v.gscale = (float)green_scale(c->p.nmesh, alpha);
+  launch_set_coef(c->coef, v, 1, 0, c->stream);
+  force_meshes(c, c->disp);
+  {
+    StageTimer t(c, COLA_STAGE_VELOCITY);
+    launch_snapshot(reinterpret_cast<const float*>(c->mesh[0]), reinterpret_cast<const float*>(c->mesh[1]),
+                    reinterpret_cast<const float*>(c->mesh[2]), 2 * padded_cols(c->p.nmesh), c->disp, c->vres,
+                    c->psi1, c->psi2, c->p.np, c->p.nmesh, k, dout, vout, sdisp, axis, c->stream);
+  }
+  LAUNCH_CHECK(c, "cola_snapshot");
+  return COLA_OK;
+}
+
 int cola_density_of(cola_ctx* c, const float* disp, float* out) {
   if (!c || !disp || !out) return fail(c, COLA_EINVAL, "null argument");
   deposit(c, c->p.nmesh, out, c->p.nmesh, 1, disp);

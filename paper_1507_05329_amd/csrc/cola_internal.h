@@ -133,6 +133,17 @@ struct VelCoef {
 void launch_velocity(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
                      const float* vres, const float* psi1, const float* psi2, int np, int nm,
                      const VelCoef& k, float* vel, float* sdisp, int axis, hipStream_t s);
+// Snapshot inside the coming step (k_velocity.hip): the step's kick to a_h,
+// then the drift ansatz to a_s.
+struct SnapCoef {
+  float K, c1, c2;  // kick to a_h: v_h = v_res + K F - c1 Psi1 - c2 Psi2
+  float I, e1, e2;  // d_s = d + I v_h + e1 Psi1 + e2 Psi2
+  float sv, w1, w2; // v_s = sv v_h + w1 Psi1 + w2 Psi2
+  float rsd;        // 1 / (a_s adot(a_s))
+};
+void launch_snapshot(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+                     const float* vres, const float* psi1, const float* psi2, int np, int nm,
+                     const SnapCoef& k, float* dout, float* vout, float* sdisp, int axis, hipStream_t s);
 // Force readout + kick/drift (k_particles.hip).
 void launch_set_coef(StepCoef* dst, const StepCoef& v, int nmock, long mstride, hipStream_t s);
 void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2,

@@ -11,6 +11,14 @@
 //          K  = kick factor from a_v to a_x with the force at a_x,
 //          u1 = a^2 adot D1' - K alpha D1,  u2 = a^2 adot D2' - K alpha (D2 - D1^2)
 //   s_d  = d_d + (d == axis ? v_d / (a adot) : 0)
+// Snapshot at a_s inside the coming step a_x -> a1 (Sec. 2.2, eqs.
+// ansatz-drift and cola-drift): the step's kick to the half step a_h, then
+// the residual velocity decays as (a/a_h)^n and the position follows its
+// drift integral to a_s; the 2LPT part is taken at a_s:
+//   v_h  = v_res + K F - c1 Psi1 - c2 Psi2          (the step's kick)
+//   d_s  = d + I_s v_h + e1 Psi1 + e2 Psi2          (I_s: drift integral a_x -> a_s,
+//                                                    e = D(a_s) - D(a_x))
+//   v_s  = sv v_h + w1 Psi1 + w2 Psi2               (sv = (a_s/a_h)^n, w = a_s^2 adot D'(a_s))
 // Nothing of the state is written.
 #include "cola_device.h"
 #include "cola_internal.h"
@@ -59,6 +67,64 @@ __global__ __launch_bounds__(256) void k_velocity(const float* __restrict__ g0, 
     vel[e * np3 + i] = ve;
     if constexpr (RSD) sdisp[e * np3 + i] = e == axis ? d[e] + k.rsd * ve : d[e];
   }
+}
+
+template <bool RSD>
+__global__ __launch_bounds__(256) void k_snapshot(const float* __restrict__ g0, const float* __restrict__ g1,
+                                                  const float* __restrict__ g2, long row_stride,
+                                                  const float* __restrict__ disp, const float* __restrict__ vres,
+                                                  const float* __restrict__ psi1, const float* __restrict__ psi2,
+                                                  int np, int nm, long np3, SnapCoef k, float* __restrict__ dout,
+                                                  float* __restrict__ vout, float* __restrict__ sdisp, int axis) {
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  if (i >= np3) return;
+  float v[3], p1[3], p2[3], d[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    v[e] = vres[e * np3 + i];
+    p1[e] = psi1[e * np3 + i];
+    p2[e] = psi2[e * np3 + i];
+    d[e] = disp[e * np3 + i];
+  }
+  int c[3];
+  float f[3];
+  home_cell(disp, np3, (uint32_t)i, np, nm, 1.0f, c, f);
+  const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
+  const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
+  const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
+  const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
+                        ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
+  const float* g[3] = {g0, g1, g2};
+  float F[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const float w = cic_weight(f, s);
+    const long idx = rows[s >> 1] + ((s & 1) ? cz1 : c[2]);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) F[e] += w * g[e][idx];
+  }
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const float vh = v[e] + k.K * F[e] - k.c1 * p1[e] - k.c2 * p2[e];
+    const float ds = d[e] + k.I * vh + k.e1 * p1[e] + k.e2 * p2[e];
+    const float vs = k.sv * vh + k.w1 * p1[e] + k.w2 * p2[e];
+    dout[e * np3 + i] = ds;
+    vout[e * np3 + i] = vs;
+    if constexpr (RSD) sdisp[e * np3 + i] = e == axis ? ds + k.rsd * vs : ds;
+  }
+}
+
+void launch_snapshot(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+                     const float* vres, const float* psi1, const float* psi2, int np, int nm,
+                     const SnapCoef& k, float* dout, float* vout, float* sdisp, int axis, hipStream_t s) {
+  const long np3 = (long)np * np * np;
+  const dim3 grid((unsigned)((np3 + 255) / 256));
+  if (sdisp)
+    hipLaunchKernelGGL(k_snapshot<true>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2,
+                       np, nm, np3, k, dout, vout, sdisp, axis);
+  else
+    hipLaunchKernelGGL(k_snapshot<false>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2,
+                       np, nm, np3, k, dout, vout, sdisp, axis);
 }
 
 void launch_velocity(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,

@@ -138,6 +138,16 @@ class ColaSim:
                                          -1 if rsd_axis is None else int(rsd_axis)), "velocity")
         return out if rsd_axis is None else (out, sdisp)
 
+    def snapshot(self, a1: float, a_s: float, rsd_axis=None):
+        """Displacement and canonical velocity at a_s inside the coming step
+        a_x -> a1 (state unchanged); with rsd_axis also the redshift-space
+        displacement.  Returns (disp, vel) or (disp, vel, sdisp)."""
+        d, v = self.particles(), self.particles()
+        sd = self.particles() if rsd_axis is not None else None
+        self._chk(self.lib.cola_snapshot(self.ctx, a1, a_s, _ptr(d), _ptr(v), _ptr(sd) if sd is not None else None,
+                                         -1 if rsd_axis is None else int(rsd_axis)), "snapshot")
+        return (d, v) if sd is None else (d, v, sd)
+
     def pk(self, edges, ngrid=None, disp=None):
         """Binned P(k) of the current positions, or of the displacement field
         ``disp`` (3 x np^3, mesh units) on the same particle lattice."""

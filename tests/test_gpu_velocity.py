@@ -146,6 +146,19 @@ def test_velocity_production_size_against_fp64_combination():
         d = st["disp"].cpu().numpy()
         assert sd[0].tobytes() == d[0].tobytes() and sd[2].tobytes() == d[2].tobytes()
         assert rel_l2(sd[1].astype(np.float64) - d[1], ref[1] / (a * adot)) < 1e-5
+        # snapshot halfway through the coming step, same construction
+        a1 = e[4]
+        a_h = 0.5 * (a + a1)
+        a_s = a + 0.3 * (a1 - a)
+        ds, vs = sim.snapshot(a1, a_s)
+        vh = g("vres") + cosmo.kick_factor(a_v, a, a_h, OM, NLPT) * (F - alpha * (D1 * p1 + (D2 - D1 * D1) * p2))
+        d_ref = (d.astype(np.float64) + cosmo.drift_factor(a, a_s, a_h, OM, NLPT) * vh
+                 + (cosmo.growth_D1(a_s, OM) - D1) * p1 + (cosmo.growth_D2(a_s, OM) - D2) * p2)
+        u = a_s * a_s * cosmo.adot(a_s, OM)
+        v_ref = ((a_s / a_h) ** NLPT * vh
+                 + u * (cosmo.growth_D1_prime(a_s, OM) * p1 + cosmo.growth_D2_prime(a_s, OM) * p2))
+        assert rel_l2(ds.cpu().numpy().astype(np.float64) - d, d_ref - d) < 1e-5
+        assert rel_l2(vs.cpu().numpy(), v_ref) < 1e-6
     finally:
         sim.close()
 
@@ -209,3 +222,41 @@ def test_kaiser_boost_in_the_linear_regime(small):
     assert err.max() < 0.01
     _, p_r, _ = small.pk(edges)
     assert (p_s[sel] / p_r[sel]).mean() > 1.5       # the boost itself (1 + 2f/3 + f^2/5 = 1.87)
+
+
+def test_snapshot_matches_oracle_and_ends_on_the_step(small):
+    # After 2 steps: the snapshot halfway through the coming step against the oracle
+    # on the GPU's state; at a_s = a_x the displacement is the state's, at a_s = a1 it
+    # is what cola_step then produces; the state is not changed by the call.
+    say("[gpu] snapshot inside a step")
+    small.init_from_noise(torch.from_numpy(white_noise(15, 32)).cuda(), *bbks_table())
+    e = step_edges()
+    small.step(e[0], e[1])
+    small.step(e[1], e[2])
+    st = small.get_state()
+    before = state_bytes(small)
+    o = oracle_state(st, 32, 64, 100.0)
+    s = 64 / 100.0
+    a_s = e[2] + 0.4 * (e[3] - e[2])
+    d, v, sd = small.snapshot(e[3], a_s, rsd_axis=1)
+    assert state_bytes(small) == before
+    d_ref, v_ref = velocity.snapshot(o, e[3], a_s)
+    d = d.cpu().numpy().astype(np.float64) / s
+    v = v.cpu().numpy().astype(np.float64) / s
+    assert rel_l2(d - o.d, d_ref - o.d) < 1e-5
+    assert rel_l2(v, v_ref) < 1e-5
+    sd32 = sd.cpu().numpy()
+    adot_s = cosmo.adot(a_s, OM)
+    assert rel_l2(sd32[1].astype(np.float64) / s - d[1], v_ref[1] / (a_s * adot_s)) < 1e-5
+    d0, _ = small.snapshot(e[3], e[2])
+    assert np.array_equal(d0.cpu().numpy(), st["disp"].cpu().numpy())
+    d1, _ = small.snapshot(e[3], e[3])
+    small.step(e[2], e[3])
+    got = small.get_state()["disp"].cpu().numpy()
+    d1 = d1.cpu().numpy()
+    inc = got.astype(np.float64) - st["disp"].cpu().numpy()
+    assert rel_l2(d1.astype(np.float64) - st["disp"].cpu().numpy(), inc) < 1e-6
+    say("[gpu]   snapshot at a1 bitwise equal to the step:", d1.tobytes() == got.tobytes())
+    for bad in [(e[3], e[2] - 0.01), (e[3], e[3] + 0.01), (e[2], e[2])]:
+        with pytest.raises(ColaError):
+            small.snapshot(*bad)
