@@ -47,6 +47,10 @@ extern "C" {
 
 #define COLA_F_CHECK_FINITE 1  /* after each step, check the state for NaN/Inf */
 #define COLA_F_STAGE_TIMERS 2  /* record HIP events around every stage of cola_step */
+#define COLA_F_D2_ODE       4  /* second-order growth D2 from its growth equation,
+                                  d/dt(a^2 dD2/dt) = alpha (D2 - D1^2), instead of the
+                                  fit -(3/7) D1^2 Omega(a)^(-1/143) of Sec. 2.1 (they
+                                  differ by 2e-4 at a = 1 for Omega_m = 0.27)      */
 
 /* Stages timed under COLA_F_STAGE_TIMERS (index into cola_stage_times). */
 #define COLA_STAGE_SORT      0  /* tile sort: bucket counts, scan, scatter          */

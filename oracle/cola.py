@@ -47,18 +47,19 @@ class State:
     psi2: np.ndarray   # (3, Np)
     a_x: float
     a_v: float
+    d2_ode: bool = False   # D2 from its growth equation instead of the Sec. 2.1 fit
 
     def positions(self) -> np.ndarray:
         return self.q + self.d
 
 
-def init_state(noise, box, nmesh, ktab, ptab, a_init=0.02, om=0.27, n_lpt=-2.5):
+def init_state(noise, box, nmesh, ktab, ptab, a_init=0.02, om=0.27, n_lpt=-2.5, d2_ode=False):
     """2LPT initial state from white noise (x_res = v_res = 0 at a_init)."""
     np_side = noise.shape[0]
     psi1, psi2 = ic.initial_fields(noise, box, ktab, ptab)
-    d = ic.initial_displacement(psi1, psi2, a_init, om)
+    d = ic.initial_displacement(psi1, psi2, a_init, om, d2_ode)
     return State(np_side, nmesh, box, om, n_lpt, ic.lattice(np_side, box), d,
-                 np.zeros_like(d), psi1, psi2, a_init, a_init)
+                 np.zeros_like(d), psi1, psi2, a_init, a_init, d2_ode)
 
 
 def state_from_fields(psi1, psi2, box, nmesh, a_init=0.02, om=0.27, n_lpt=-2.5):
@@ -78,7 +79,7 @@ def step(state: State, a1: float, force=None) -> dict:
     ``force``: None for the PM force, else a callable (state, coeffs) -> F
     (used by tests that substitute an exactly known force law).
     """
-    c = cosmo.step_coefficients(state.a_x, state.a_v, a1, state.om, state.n_lpt)
+    c = cosmo.step_coefficients(state.a_x, state.a_v, a1, state.om, state.n_lpt, state.d2_ode)
     F = pm.pm_force(state.positions(), state.nmesh, state.box, c["alpha"]) \
         if force is None else force(state, c)
     state.v += c["K"] * residual_force(state, F, c)

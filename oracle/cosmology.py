@@ -77,6 +77,38 @@ def growth_D2_prime(a: float, om: float) -> float:
     return growth_D2(a, om) * (2.0 * growth_D1_prime(a, om) / d1 - dlnom / 143.0)
 
 
+def _growth_system(a_end: float, om: float):
+    """Unnormalised (D1, D1', D2, D2') at a_end from the growth equations
+    d/dt(a^2 dD1/dt) = alpha D1 and d/dt(a^2 dD2/dt) = alpha (D2 - D1^2), written in a
+    (' = d/da): D'' + (3/a + E'/E) D' = 1.5 Om/(a^5 E^2) * (D1 or D2 - D1^2), started
+    on the matter-dominated growing modes D1 = a, D2 = -(3/7) a^2 at a = 1e-5."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(a, y):
+        e = hubble_E(a, om)
+        damp = 3.0 / a - 1.5 * om / (a ** 4 * e * e)
+        src = 1.5 * om / (a ** 5 * e * e)
+        return [y[1], -damp * y[1] + src * y[0], y[3], -damp * y[3] + src * (y[2] - y[0] * y[0])]
+
+    a0 = 1e-5
+    y0 = [a0, 1.0, -3.0 / 7.0 * a0 * a0, -6.0 / 7.0 * a0]
+    sol = solve_ivp(rhs, [a0, a_end], y0, method="DOP853", rtol=1e-12, atol=1e-30)
+    return sol.y[:, -1]
+
+
+def growth_D2_ode(a: float, om: float) -> float:
+    """Second-order growth from its differential equation (the alternative to the
+    Sec. 2.1 fit), normalised with D1(1) = 1 (D2 scales as D1^2)."""
+    n1 = _growth_system(1.0, om)[0]
+    return _growth_system(a, om)[2] / (n1 * n1)
+
+
+def growth_D2_ode_prime(a: float, om: float) -> float:
+    """dD2/da of growth_D2_ode."""
+    n1 = _growth_system(1.0, om)[0]
+    return _growth_system(a, om)[3] / (n1 * n1)
+
+
 def poisson_alpha(a: float, om: float) -> float:
     """Source factor of the comoving Poisson equation, Sec. 2.2: (3/2) Omega_m / a."""
     return 1.5 * om / a
@@ -101,7 +133,16 @@ def drift_factor(a0: float, a1: float, a_h: float, om: float, n: float) -> float
     return val
 
 
-def step_coefficients(a_x: float, a_v: float, a1: float, om: float, n: float) -> dict:
+def D2_of(a: float, om: float, d2_ode: bool = False) -> float:
+    """The D2 a run uses: the Sec. 2.1 fit, or the growth-equation solution."""
+    return growth_D2_ode(a, om) if d2_ode else growth_D2(a, om)
+
+
+def D2_prime_of(a: float, om: float, d2_ode: bool = False) -> float:
+    return growth_D2_ode_prime(a, om) if d2_ode else growth_D2_prime(a, om)
+
+
+def step_coefficients(a_x: float, a_v: float, a1: float, om: float, n: float, d2_ode: bool = False) -> dict:
     """All scalars one COLA step a_x -> a1 needs (velocity currently at a_v).
 
     a_h = (a_x + a1)/2 is the half step (midpoint in a).
@@ -109,7 +150,7 @@ def step_coefficients(a_x: float, a_v: float, a1: float, om: float, n: float) ->
     a0 = a_x
     a_h = 0.5 * (a0 + a1)
     d1_0, d1_1 = growth_D1(a0, om), growth_D1(a1, om)
-    d2_0, d2_1 = growth_D2(a0, om), growth_D2(a1, om)
+    d2_0, d2_1 = D2_of(a0, om, d2_ode), D2_of(a1, om, d2_ode)
     return dict(
         a0=a0, a1=a1, a_v=a_v, a_h=a_h,
         alpha=poisson_alpha(a0, om),

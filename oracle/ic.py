@@ -132,6 +132,6 @@ def initial_fields(noise: np.ndarray, box: float, ktab, ptab):
     return psi1.reshape(3, n ** 3), psi2.reshape(3, n ** 3)
 
 
-def initial_displacement(psi1, psi2, a_init: float, om: float):
+def initial_displacement(psi1, psi2, a_init: float, om: float, d2_ode: bool = False):
     """d = D1(a) Psi1 + D2(a) Psi2 (positions x = q + d), Sec. 2.1."""
-    return cosmo.growth_D1(a_init, om) * psi1 + cosmo.growth_D2(a_init, om) * psi2
+    return cosmo.growth_D1(a_init, om) * psi1 + cosmo.D2_of(a_init, om, d2_ode) * psi2

@@ -46,10 +46,10 @@ def snapshot_coefficients(state: State) -> dict:
         adot=adot,
         alpha=cosmo.poisson_alpha(a, om),
         D1=cosmo.growth_D1(a, om),
-        D2=cosmo.growth_D2(a, om),
+        D2=cosmo.D2_of(a, om, state.d2_ode),
         K=cosmo.kick_factor(a_v, a, a, om, n),
         u1=a * a * adot * cosmo.growth_D1_prime(a, om),
-        u2=a * a * adot * cosmo.growth_D2_prime(a, om),
+        u2=a * a * adot * cosmo.D2_prime_of(a, om, state.d2_ode),
     )
 
 
@@ -89,7 +89,7 @@ def snapshot(state: State, a1: float, a_s: float, force=None):
     integral is eq. cola-drift from a_x to a_s; the 2LPT part is evaluated at a_s.
     At a_s = a1 the displacement is the step's.
     """
-    c = cosmo.step_coefficients(state.a_x, state.a_v, a1, state.om, state.n_lpt)
+    c = cosmo.step_coefficients(state.a_x, state.a_v, a1, state.om, state.n_lpt, state.d2_ode)
     F = pm.pm_force(state.positions(), state.nmesh, state.box, c["alpha"]) \
         if force is None else force(state, c)
     F_res = F - c["alpha"] * (c["D1"] * state.psi1 + (c["D2"] - c["D1"] ** 2) * state.psi2)
@@ -98,9 +98,9 @@ def snapshot(state: State, a1: float, a_s: float, force=None):
     I = cosmo.drift_factor(state.a_x, a_s, a_h, om, n)
     d = (state.d + I * v_half
          + (cosmo.growth_D1(a_s, om) - c["D1"]) * state.psi1
-         + (cosmo.growth_D2(a_s, om) - c["D2"]) * state.psi2)
+         + (cosmo.D2_of(a_s, om, state.d2_ode) - c["D2"]) * state.psi2)
     u = a_s * a_s * cosmo.adot(a_s, om)
     v = ((a_s / a_h) ** n * v_half
          + u * cosmo.growth_D1_prime(a_s, om) * state.psi1
-         + u * cosmo.growth_D2_prime(a_s, om) * state.psi2)
+         + u * cosmo.D2_prime_of(a_s, om, state.d2_ode) * state.psi2)
     return d, v

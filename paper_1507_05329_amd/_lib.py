@@ -22,6 +22,7 @@ COLA_EHIP = -5
 COLA_ENONFINITE = -6
 COLA_F_CHECK_FINITE = 1
 COLA_F_STAGE_TIMERS = 2
+COLA_F_D2_ODE = 4
 STAGES = ["sort", "deposit", "fft_z", "fft_y", "fft_x_green", "ifft_y", "ifft_z", "kick_drift",
           "ifft_y_grad", "velocity"]
 

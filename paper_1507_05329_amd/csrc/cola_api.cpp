@@ -247,7 +247,7 @@ void step_scalars(const cola_params* p, double a_x, double a_v, double a1, doubl
   const double om = p->omega_m, n = p->n_lpt;
   const double ah = 0.5 * (a_x + a1);
   const double d1a = growth_D1(a_x, om), d1b = growth_D1(a1, om);
-  const double d2a = growth_D2(a_x, om), d2b = growth_D2(a1, om);
+  const double d2a = D2_of(p, a_x), d2b = D2_of(p, a1);
   o[0] = 1.5 * om / a_x;
   o[1] = d1a;
   o[2] = d2a;
@@ -353,7 +353,7 @@ int ic_from_mesh_noise(cola_ctx* c, const double* k, const double* pk, int nk) {
   }
   const double a0 = c->p.a_init;
   launch_init_particles(c->disp, c->vres, c->psi1, c->psi2, c->np3,
-                        (float)growth_D1(a0, c->p.omega_m), (float)growth_D2(a0, c->p.omega_m),
+                        (float)growth_D1(a0, c->p.omega_m), (float)D2_of(&c->p, a0),
                         c->stream);
   LAUNCH_CHECK(c, "init_2lpt");
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // the amplitude table's host copy is released here
@@ -519,13 +519,13 @@ int cola_velocity(cola_ctx* c, float* vel, float* sdisp, int32_t axis) {
   if (sdisp == vel) return fail(c, COLA_EINVAL, "dev_vel and dev_sdisp must differ");
   const double om = c->p.omega_m, n = c->p.n_lpt, a = c->a_x;
   const double adot = a * hubble_E(a, om), alpha = 1.5 * om / a;
-  const double D1 = growth_D1(a, om), D2 = growth_D2(a, om);
+  const double D1 = growth_D1(a, om), D2 = D2_of(&c->p, a);
   // the kick from a_v to a_x (zero at the initial state, where a_v = a_x)
   const double K = c->a_v == a ? 0.0 : kick_factor(c->a_v, a, a, om, n);
   VelCoef k{};
   k.K = (float)K;
   k.u1 = (float)(a * a * adot * growth_D1_prime(a, om) - K * alpha * D1);
-  k.u2 = (float)(a * a * adot * growth_D2_prime(a, om) - K * alpha * (D2 - D1 * D1));
+  k.u2 = (float)(a * a * adot * D2_prime_of(&c->p, a) - K * alpha * (D2 - D1 * D1));
   k.rsd = (float)(1.0 / (a * adot));
   const float* g[3] = {nullptr, nullptr, nullptr};
   if (K != 0.0) {
@@ -572,10 +572,10 @@ int cola_snapshot(cola_ctx* c, double a1, double a_s, float* dout, float* vout, 
   k.c2 = (float)(K * alpha * (D2 - D1 * D1));
   k.I = (float)drift_factor(a0, a_s, a_h, om, n);
   k.e1 = (float)(growth_D1(a_s, om) - D1);
-  k.e2 = (float)(growth_D2(a_s, om) - D2);
+  k.e2 = (float)(D2_of(&c->p, a_s) - D2);
   k.sv = (float)std::pow(a_s / a_h, n);
   k.w1 = (float)(u * growth_D1_prime(a_s, om));
-  k.w2 = (float)(u * growth_D2_prime(a_s, om));
+  k.w2 = (float)(u * D2_prime_of(&c->p, a_s));
   k.rsd = (float)(1.0 / (a_s * adot_s));
   StepCoef v{};
   v.gscale = (float)green_scale(c->p.nmesh, alpha);
@@ -820,7 +820,7 @@ int cola_init_2lpt_adjoint(cola_ctx* c, const float* noise, const float* dbar0, 
   const long rs = 2 * padded_cols(np);
   const long ms = mesh_complex_count(np);
   const double om = c->p.omega_m, a0 = c->p.a_init;
-  const float D1 = (float)growth_D1(a0, om), D2 = (float)growth_D2(a0, om);
+  const float D1 = (float)growth_D1(a0, om), D2 = (float)D2_of(&c->p, a0);
   const double inv3 = 1.0 / ((double)np * np * np);
   const float sgrad = (float)(nm / (2.0 * kPi) * inv3);
   float2* C0 = ic_buf(c, 0);
@@ -990,7 +990,7 @@ namespace {
 
 bool same_group(const cola_params& a, const cola_params& b) {
   return a.np == b.np && a.nmesh == b.nmesh && a.omega_m == b.omega_m && a.n_lpt == b.n_lpt &&
-         a.a_init == b.a_init;
+         a.a_init == b.a_init && (a.flags & COLA_F_D2_ODE) == (b.flags & COLA_F_D2_ODE);
 }
 
 // Groups in first-appearance order; returns the workspace layout.

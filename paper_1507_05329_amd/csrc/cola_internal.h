@@ -46,6 +46,12 @@ double drift_factor(double a0, double a1, double a_h, double om, double n);
 // dD1/da and dD2/da (velocity of the 2LPT trajectory).
 double growth_D1_prime(double a, double om);
 double growth_D2_prime(double a, double om);
+// D2 from its growth equation instead of the fit, and dD2/da.
+double growth_D2_ode(double a, double om);
+double growth_D2_ode_prime(double a, double om);
+// The D2 (and dD2/da) the run uses: the fit, or the ODE under COLA_F_D2_ODE.
+double D2_of(const cola_params* p, double a);
+double D2_prime_of(const cola_params* p, double a);
 // ln-ln interpolation of a P(k) table, end segments extended.
 double interp_pk(double k, const double* kt, const double* pt, int nk);
 

@@ -96,6 +96,69 @@ double growth_D2_prime(double a, double om) {
   return growth_D2(a, om) * (2.0 * growth_D1_prime(a, om) / growth_D1(a, om) - dlnom / 143.0);
 }
 
+namespace {
+
+// The growth equations d/dt(a^2 dD1/dt) = alpha D1 and
+// d/dt(a^2 dD2/dt) = alpha (D2 - D1^2) in x = ln a:
+//   D_xx = -(2 - 1.5 Om(a)) D_x + 1.5 Om(a) S,  S = D1 or D2 - D1^2,
+// with Om(a) the matter fraction; started at a = 1e-5 on the matter-era
+// growing modes D1 = a, D2 = -(3/7) a^2; classical RK4 in x.
+void growth_ode_raw(double a_end, double om, double y[4]) {
+  const double x0 = std::log(1e-5), x1 = std::log(a_end);
+  const int n = 6000;
+  const double h = (x1 - x0) / n;
+  const double a0 = 1e-5;
+  y[0] = a0;                       // D1
+  y[1] = a0;                       // dD1/dx
+  y[2] = -3.0 / 7.0 * a0 * a0;     // D2
+  y[3] = -6.0 / 7.0 * a0 * a0;     // dD2/dx
+  auto f = [om](double x, const double* v, double* o) {
+    const double a = std::exp(x);
+    const double w = 1.5 * om / (om + (1.0 - om) * a * a * a);
+    o[0] = v[1];
+    o[1] = -(2.0 - w) * v[1] + w * v[0];
+    o[2] = v[3];
+    o[3] = -(2.0 - w) * v[3] + w * (v[2] - v[0] * v[0]);
+  };
+  double k1[4], k2[4], k3[4], k4[4], t[4];
+  for (int i = 0; i < n; ++i) {
+    const double x = x0 + i * h;
+    f(x, y, k1);
+    for (int j = 0; j < 4; ++j) t[j] = y[j] + 0.5 * h * k1[j];
+    f(x + 0.5 * h, t, k2);
+    for (int j = 0; j < 4; ++j) t[j] = y[j] + 0.5 * h * k2[j];
+    f(x + 0.5 * h, t, k3);
+    for (int j = 0; j < 4; ++j) t[j] = y[j] + h * k3[j];
+    f(x + h, t, k4);
+    for (int j = 0; j < 4; ++j) y[j] += h / 6.0 * (k1[j] + 2.0 * k2[j] + 2.0 * k3[j] + k4[j]);
+  }
+}
+
+}  // namespace
+
+// D2 from its growth equation, normalised with D1(1) = 1 (D2 scales as D1^2).
+double growth_D2_ode(double a, double om) {
+  double y[4], y1[4];
+  growth_ode_raw(a, om, y);
+  growth_ode_raw(1.0, om, y1);
+  return y[2] / (y1[0] * y1[0]);
+}
+
+double growth_D2_ode_prime(double a, double om) {
+  double y[4], y1[4];
+  growth_ode_raw(a, om, y);
+  growth_ode_raw(1.0, om, y1);
+  return y[3] / a / (y1[0] * y1[0]);
+}
+
+double D2_of(const cola_params* p, double a) {
+  return (p->flags & COLA_F_D2_ODE) ? growth_D2_ode(a, p->omega_m) : growth_D2(a, p->omega_m);
+}
+
+double D2_prime_of(const cola_params* p, double a) {
+  return (p->flags & COLA_F_D2_ODE) ? growth_D2_ode_prime(a, p->omega_m) : growth_D2_prime(a, p->omega_m);
+}
+
 double interp_pk(double k, const double* kt, const double* pt, int nk) {
   if (!(k > 0)) return 0.0;
   const double x = std::log(k);

@@ -49,6 +49,24 @@ def test_host_step_scalars_match_oracle():
         a_v = c["a_h"]
 
 
+def test_host_step_scalars_with_d2_from_its_growth_equation():
+    # COLA_F_D2_ODE: the library integrates the growth equation (RK4 in ln a); the
+    # oracle solves the same equation with an adaptive integrator.
+    lib, p = params()
+    p.flags = _lib.COLA_F_D2_ODE
+    edges = step_edges()
+    a_v = edges[0]
+    for a0, a1 in zip(edges[:-1], edges[1:]):
+        out = np.zeros(10)
+        assert lib.cola_step_scalars(C.byref(p), a0, a_v, a1, _lib.dptr(out)) == 0
+        c = cosmo.step_coefficients(a0, a_v, a1, 0.27, -2.5, d2_ode=True)
+        np.testing.assert_allclose([out[2], out[4], out[9]],
+                                   [c["D2"], c["dD2"], cosmo.growth_D2_ode(a1, 0.27)], rtol=1e-9, atol=1e-15)
+        np.testing.assert_allclose(out[[0, 1, 3, 5, 6, 7]],
+                                   [c["alpha"], c["D1"], c["dD1"], c["K"], c["I"], c["a_h"]], rtol=1e-12)
+        a_v = c["a_h"]
+
+
 @pytest.mark.parametrize("np_side,nmesh,code", [
     (32, 60, _lib.COLA_EUNSUPPORTED),    # not a multiple of 8
     (32, 40, _lib.COLA_EUNSUPPORTED),    # 40 = 8 * 5: prime factor 5

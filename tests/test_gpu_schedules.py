@@ -79,3 +79,33 @@ def test_step_count_convergence():
     say("[gpu]   rms |P_n/P_100 - 1| for n = 10, 20, 50:", d)
     assert d[1] > 2.5 * d[2]
     assert d[2] < 0.02
+
+
+def test_d2_from_growth_equation_matches_oracle():
+    # COLA_F_D2_ODE: initial displacement and the 10-step P(k) against the oracle run
+    # with the same D2; the run differs from the fit's (slightly: 2e-4 in D2 at a = 1).
+    from oracle import ic
+    from paper_1507_05329_amd import _lib
+    from paper_1507_05329_amd.inputs import step_edges
+    from paper_1507_05329_amd.sim import ColaSim
+    say("[gpu] D2 from its growth equation")
+    w = white_noise(23, NP)
+    sim = ColaSim(NP, NM, L, flags=_lib.COLA_F_D2_ODE)
+    try:
+        sim.init_from_noise(torch.from_numpy(w).cuda(), *bbks_table())
+        ref = cola.init_state(w, L, NM, *bbks_table(), d2_ode=True)
+        d0 = sim.get_state()["disp"].cpu().numpy().astype(np.float64) * (L / NM)
+        assert np.linalg.norm(d0 - ref.d) / np.linalg.norm(ref.d) < 1e-5
+        sim.run(step_edges())
+        km, p_g, n_g = sim.pk(pk_edges())
+    finally:
+        sim.close()
+    cola.run(ref, step_edges())
+    k_o, p_o, n_o = pk.power_spectrum(ref.positions(), L, NM, pk_edges())
+    assert np.array_equal(n_g, n_o)
+    sel = (n_o > 0) & (k_o < np.pi * NM / L / 2)
+    err = np.abs(p_g[sel] / p_o[sel] - 1)
+    say("[gpu]   max |P_gpu/P_oracle - 1| =", err.max())
+    assert err.max() < 5e-3
+    _, p_f, _ = run_gpu(w, step_edges())
+    assert np.abs(p_f[sel] / p_g[sel] - 1).max() > 1e-7   # the flag took effect

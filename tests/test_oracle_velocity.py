@@ -176,3 +176,35 @@ def test_snapshot_exact_for_1d_dynamics():
                                    atol=1e-12 * np.abs(p1).max())
         want = a_s * a_s * cosmo.adot(a_s, OM) * cosmo.growth_D1_prime(a_s, OM) * p1
         np.testing.assert_allclose(v, want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("a", [0.02, 0.3, 1.0])
+def test_d2_ode_einstein_de_sitter(a):
+    # Omega_m = 1: the growing second-order solution is exactly -(3/7) a^2.
+    assert cosmo.growth_D2_ode(a, 1.0) == pytest.approx(-3.0 / 7.0 * a * a, rel=1e-9)
+    assert cosmo.growth_D2_ode_prime(a, 1.0) == pytest.approx(-6.0 / 7.0 * a, rel=1e-9)
+
+
+@pytest.mark.parametrize("a", [0.1, 0.5, 1.0])
+def test_d2_ode_satisfies_its_growth_equation(a):
+    # a E d/da(a^3 E dD2/da) = (3/2) Om / a (D2 - D1^2), checked by central differences
+    # of a^3 E D2' (the oracle's own D2 and D2'), and D2' against differences of D2.
+    om = OM
+    E = lambda x: cosmo.hubble_E(x, om)
+    g = lambda x: x ** 3 * E(x) * cosmo.growth_D2_ode_prime(x, om)
+    h = 1e-4 * a
+    lhs = a * E(a) * (g(a + h) - g(a - h)) / (2 * h)
+    rhs = 1.5 * om / a * (cosmo.growth_D2_ode(a, om) - cosmo.growth_D1(a, om) ** 2)
+    assert lhs == pytest.approx(rhs, rel=1e-6)
+    d = (cosmo.growth_D2_ode(a + h, om) - cosmo.growth_D2_ode(a - h, om)) / (2 * h)
+    assert cosmo.growth_D2_ode_prime(a, om) == pytest.approx(d, rel=1e-7)
+
+
+def test_paper_d2_fit_close_to_the_growth_equation():
+    # With Omega(a) read as the matter fraction, the fit of Sec. 2.1 is within 0.05%
+    # of the growth-equation solution up to a = 1; without the Omega^(-1/143) factor
+    # it would be off by about 0.9% at a = 1.
+    for a in [0.02, 0.1, 0.5, 1.0]:
+        assert cosmo.growth_D2(a, OM) == pytest.approx(cosmo.growth_D2_ode(a, OM), rel=5e-4)
+    plain = -3.0 / 7.0 * cosmo.growth_D1(1.0, OM) ** 2
+    assert abs(plain / cosmo.growth_D2_ode(1.0, OM) - 1) > 5e-3
