@@ -76,7 +76,8 @@ typedef struct cola_params {
   int32_t nmesh;           /* PM mesh per side                                     */
   double  box;             /* periodic box side [Mpc/h]                            */
   double  omega_m;         /* matter density parameter                             */
-  double  n_lpt;           /* kick/drift ansatz exponent, Sec. 2.1 (paper: -2.5)   */
+  double  n_lpt;           /* kick/drift ansatz exponent, Sec. 2.1 (paper: -2.5);
+                              0: constant v_res in the drift, A + B ln a in the kick */
   double  a_init;          /* scale factor of the initial conditions               */
   int32_t flags;           /* COLA_F_* bits                                        */
   int32_t reserved;

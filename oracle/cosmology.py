@@ -117,8 +117,11 @@ def poisson_alpha(a: float, om: float) -> float:
 def kick_factor(a_v: float, a_x: float, a_h: float, om: float, n: float) -> float:
     """Eq. cola-kick: v_res(a_h) = v_res(a_v) + K * F_res(x at a_x).
 
-    K = (a_h^n - a_v^n) / (n a_x^(n-1) adot(a_x)).
+    K = (a_h^n - a_v^n) / (n a_x^(n-1) adot(a_x)).  For n = 0 the ansatz becomes
+    v_res = A + B ln a (the limit n -> 0 of (a^n - 1)/n) and K = a_x ln(a_h/a_v) / adot(a_x).
     """
+    if n == 0.0:
+        return math.log(a_h / a_v) * a_x / adot(a_x, om)
     return (a_h ** n - a_v ** n) / (n * a_x ** (n - 1.0) * adot(a_x, om))
 
 

@@ -66,7 +66,7 @@ struct Layout {
 int validate(const cola_params* p) {
   if (!p) return COLA_EINVAL;
   if (p->np < 2 || p->nmesh < 32 || !(p->box > 0) || !(p->omega_m > 0) || p->omega_m > 1.0 ||
-      !(p->a_init > 0) || p->n_lpt == 0.0 || !std::isfinite(p->n_lpt))
+      !(p->a_init > 0) || !std::isfinite(p->n_lpt))
     return COLA_EINVAL;
   if (!fft_size_supported(p->np)) return COLA_EUNSUPPORTED;
   if (p->nmesh % 8 != 0 || !fft_size_supported(p->nmesh) || p->nmesh < p->np) return COLA_EUNSUPPORTED;

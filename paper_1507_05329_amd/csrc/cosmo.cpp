@@ -72,6 +72,8 @@ double growth_D2(double a, double om) {
 
 double kick_factor(double a_v, double a_x, double a_h, double om, double n) {
   const double adot = a_x * hubble_E(a_x, om);
+  // n = 0: the limit of the ansatz, v_res = A + B ln a during the kick
+  if (n == 0.0) return std::log(a_h / a_v) * a_x / adot;
   return (std::pow(a_h, n) - std::pow(a_v, n)) / (n * std::pow(a_x, n - 1.0) * adot);
 }
 

@@ -173,3 +173,15 @@ def test_largest_single_gpu_workspace_fits_hbm():
     n = C.c_size_t()
     assert lib.cola_workspace_query(C.byref(p), C.byref(n)) == 0
     assert n.value < 250e9
+
+
+def test_host_step_scalars_at_n_lpt_zero():
+    lib, p = params()
+    p.n_lpt = 0.0
+    n = C.c_size_t()
+    assert lib.cola_workspace_query(C.byref(p), C.byref(n)) == 0
+    out = np.zeros(10)
+    assert lib.cola_step_scalars(C.byref(p), 0.314, 0.265, 0.412, _lib.dptr(out)) == 0
+    c = cosmo.step_coefficients(0.314, 0.265, 0.412, 0.27, 0.0)
+    np.testing.assert_allclose(out[5:7], [c["K"], c["I"]], rtol=1e-12)
+    assert np.isfinite(out).all()

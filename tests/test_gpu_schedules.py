@@ -109,3 +109,26 @@ def test_d2_from_growth_equation_matches_oracle():
     assert err.max() < 5e-3
     _, p_f, _ = run_gpu(w, step_edges())
     assert np.abs(p_f[sel] / p_g[sel] - 1).max() > 1e-7   # the flag took effect
+
+
+def test_n_lpt_zero_matches_oracle():
+    # n_LPT = 0: constant residual velocity during the drift, A + B ln a in the kick.
+    from paper_1507_05329_amd.inputs import step_edges
+    from paper_1507_05329_amd.sim import ColaSim
+    say("[gpu] n_LPT = 0")
+    w = white_noise(24, NP)
+    sim = ColaSim(NP, NM, L, n_lpt=0.0)
+    try:
+        sim.init_from_noise(torch.from_numpy(w).cuda(), *bbks_table())
+        sim.run(step_edges())
+        _, p_g, n_g = sim.pk(pk_edges())
+    finally:
+        sim.close()
+    ref = cola.init_state(w, L, NM, *bbks_table(), n_lpt=0.0)
+    cola.run(ref, step_edges())
+    k_o, p_o, n_o = pk.power_spectrum(ref.positions(), L, NM, pk_edges())
+    assert np.array_equal(n_g, n_o)
+    sel = (n_o > 0) & (k_o < np.pi * NM / L / 2)
+    err = np.abs(p_g[sel] / p_o[sel] - 1)
+    say("[gpu]   max |P_gpu/P_oracle - 1| =", err.max())
+    assert err.max() < 5e-3

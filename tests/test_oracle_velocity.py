@@ -208,3 +208,25 @@ def test_paper_d2_fit_close_to_the_growth_equation():
         assert cosmo.growth_D2(a, OM) == pytest.approx(cosmo.growth_D2_ode(a, OM), rel=5e-4)
     plain = -3.0 / 7.0 * cosmo.growth_D1(1.0, OM) ** 2
     assert abs(plain / cosmo.growth_D2_ode(1.0, OM) - 1) > 5e-3
+
+
+def test_kick_factor_continuous_at_n_lpt_zero():
+    # n = 0 is the limit of the ansatz: K(n) -> K(0) linearly in n.
+    a_v, a_x, a_h = 0.3, 0.35, 0.4
+    k0 = cosmo.kick_factor(a_v, a_x, a_h, OM, 0.0)
+    for n in (1e-3, -1e-3):
+        assert cosmo.kick_factor(a_v, a_x, a_h, OM, n) == pytest.approx(k0, rel=2e-3)
+    kp = cosmo.kick_factor(a_v, a_x, a_h, OM, 1e-4)
+    km = cosmo.kick_factor(a_v, a_x, a_h, OM, -1e-4)
+    assert 0.5 * (kp + km) == pytest.approx(k0, rel=1e-8)
+
+
+def test_n_lpt_zero_kick_follows_the_ln_a_ansatz():
+    # v_res = A + B ln a with dv/dt = F at a_x: B adot(a_x)/a_x = F, so the kick over
+    # [a_v, a_h] is F a_x ln(a_h/a_v)/adot(a_x); check dv/dt at a_x by central differences.
+    a_v, a_x, a_h = 0.3, 0.35, 0.4
+    F = 1.7
+    v = lambda a: cosmo.kick_factor(a_v, a_x, a, OM, 0.0) * F
+    h = 1e-6
+    dvda = (v(a_x + h) - v(a_x - h)) / (2 * h)
+    assert dvda * cosmo.adot(a_x, OM) == pytest.approx(F, rel=1e-8)
