@@ -173,6 +173,22 @@ int cola_density_of(cola_ctx* ctx, const float* dev_disp, float* dev_out);
 int cola_pk_of(cola_ctx* ctx, const float* dev_disp, int32_t ngrid, const double* k_edges, int32_t nbins,
                double* host_kmean, double* host_pk, int64_t* host_nmodes);
 
+/* Density and line-of-sight momentum spectra on the nmesh^3 mesh (the
+ * paper's P_gu and P_uu of Sec. 5, for the matter).  The velocity is
+ * cola_velocity's at the position time, expressed as the redshift-space
+ * shift u = v_axis / (a adot) in Mpc/h; the fields are delta and the momentum
+ * p = sum_p W u_p / nbar (nbar particles per cell on average), both by CIC
+ * through the deterministic deposit and deconvolved like cola_pk.  Per bin
+ * of k_edges (as cola_pk, same half space and |k| <= pi nmesh / box):
+ * mean |k|, P_dd = <|delta|^2>/V, P_du = <sign(k_axis) Im(delta p*)>/V (the
+ * line-of-sight cross term is odd in mu; folded onto mu >= 0, negative for
+ * infall), P_uu = <|p|^2>/V, and the mode count; a bin without modes
+ * reports count 0 and NaN.  axis in {0, 1, 2}; nbins <= 2048.  Runs the
+ * force pipeline when a_v != a_x; overwrites the force meshes; synchronises
+ * the stream. */
+int cola_pk_velocity(cola_ctx* ctx, int32_t axis, const double* k_edges, int32_t nbins, double* host_kmean,
+                     double* host_p_dd, double* host_p_du, double* host_p_uu, int64_t* host_nmodes);
+
 /* PM force F (mesh units) at the current positions, 3 * np^3 float32 into
  * dev_force; no state change (the force of Sec. 2.2 as used by cola_step). */
 int cola_force(cola_ctx* ctx, float* dev_force);

@@ -512,11 +512,11 @@ int cola_force(cola_ctx* c, float* out) {
   return COLA_OK;
 }
 
-int cola_velocity(cola_ctx* c, float* vel, float* sdisp, int32_t axis) {
-  if (!c || !vel) return fail(c, COLA_EINVAL, "null argument");
-  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
-  if (sdisp && (axis < 0 || axis > 2)) return fail(c, COLA_EINVAL, "rsd_axis must be 0, 1 or 2");
-  if (sdisp == vel) return fail(c, COLA_EINVAL, "dev_vel and dev_sdisp must differ");
+namespace {
+
+// Coefficients of the velocity at the position time; runs the force pipeline
+// into the force meshes (g) when the kick from a_v to a_x is not zero.
+VelCoef velocity_coef_and_forces(cola_ctx* c, const float* g[3]) {
   const double om = c->p.omega_m, n = c->p.n_lpt, a = c->a_x;
   const double adot = a * hubble_E(a, om), alpha = 1.5 * om / a;
   const double D1 = growth_D1(a, om), D2 = D2_of(&c->p, a);
@@ -527,7 +527,7 @@ int cola_velocity(cola_ctx* c, float* vel, float* sdisp, int32_t axis) {
   k.u1 = (float)(a * a * adot * growth_D1_prime(a, om) - K * alpha * D1);
   k.u2 = (float)(a * a * adot * D2_prime_of(&c->p, a) - K * alpha * (D2 - D1 * D1));
   k.rsd = (float)(1.0 / (a * adot));
-  const float* g[3] = {nullptr, nullptr, nullptr};
+  g[0] = g[1] = g[2] = nullptr;
   if (K != 0.0) {
     StepCoef v{};
     v.gscale = (float)green_scale(c->p.nmesh, alpha);
@@ -535,6 +535,18 @@ int cola_velocity(cola_ctx* c, float* vel, float* sdisp, int32_t axis) {
     force_meshes(c, c->disp);
     for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<const float*>(c->mesh[d]);
   }
+  return k;
+}
+
+}  // namespace
+
+int cola_velocity(cola_ctx* c, float* vel, float* sdisp, int32_t axis) {
+  if (!c || !vel) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  if (sdisp && (axis < 0 || axis > 2)) return fail(c, COLA_EINVAL, "rsd_axis must be 0, 1 or 2");
+  if (sdisp == vel) return fail(c, COLA_EINVAL, "dev_vel and dev_sdisp must differ");
+  const float* g[3];
+  const VelCoef k = velocity_coef_and_forces(c, g);
   {
     StageTimer t(c, COLA_STAGE_VELOCITY);
     launch_velocity(g[0], g[1], g[2], 2 * padded_cols(c->p.nmesh), c->disp, c->vres, c->psi1, c->psi2, c->p.np,
@@ -637,6 +649,51 @@ int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double*
   if (!c || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
   return pk_of(c, c->disp, ng, edges, nbins, kmean, pk, nmodes);
+}
+
+int cola_pk_velocity(cola_ctx* c, int32_t axis, const double* edges, int32_t nbins, double* kmean,
+                     double* pdd, double* pdu, double* puu, int64_t* nmodes) {
+  if (!c || !edges || !kmean || !pdd || !pdu || !puu || !nmodes) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  if (axis < 0 || axis > 2) return fail(c, COLA_EINVAL, "axis must be 0, 1 or 2");
+  if (nbins < 1 || nbins > kMaxBins / 2) return fail(c, COLA_EINVAL, "nbins out of range");
+  for (int i = 0; i < nbins; ++i)
+    if (!(edges[i + 1] > edges[i])) return fail(c, COLA_EINVAL, "edges must increase");
+  const int nm = c->p.nmesh;
+  int r = ensure_twiddles(c, nm);
+  if (r != COLA_OK) return r;
+  HIP_TRY(c, hipMemcpyAsync(c->pk_edges, edges, (nbins + 1) * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  const float* g[3];
+  const VelCoef k = velocity_coef_and_forces(c, g);
+  const double a = c->a_x, adot = a * hubble_E(a, c->p.omega_m);
+  const double nbar = (double)c->np3 / ((double)nm * nm * nm);
+  const long rs = 2 * padded_cols(nm);
+  // weights: 1/nbar (density 1 + delta) and the line-of-sight shift v / (a adot) in
+  // Mpc/h over nbar (momentum)
+  launch_los_weights(g[0], g[1], g[2], rs, c->disp, c->vres, c->psi1, c->psi2, c->p.np, nm, k, axis,
+                     (float)(1.0 / nbar), (float)(c->p.box / nm / (a * adot) / nbar), c->fbar, c->stream);
+  tile_sort(c, nm, c->disp);
+  launch_deposit3_weighted(c->disp, c->perm, c->offsets, c->p.np, nm, c->fbar,
+                           reinterpret_cast<float*>(c->mesh[0]), rs, 2 * c->mesh_stride, c->stream);
+  fft3d_forward(c->mesh[0], nm, c->tw, c->stream);
+  fft3d_forward(c->mesh[1], nm, c->tw, c->stream);
+  launch_pk_cross(c->mesh[0], c->mesh[1], nm, c->p.box, c->pk_edges, nbins, axis, c->pk_partial, kPkChunks,
+                  c->pk_out, c->stream);
+  LAUNCH_CHECK(c, "cola_pk_velocity");
+  std::vector<double> h(5 * (size_t)nbins);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), c->pk_out, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < nbins; ++b) {
+    const double n = h[5 * b + 4];
+    nmodes[b] = (int64_t)llround(n);
+    kmean[b] = n > 0 ? h[5 * b] / n : NAN;
+    pdd[b] = n > 0 ? h[5 * b + 1] / n : NAN;
+    pdu[b] = n > 0 ? h[5 * b + 2] / n : NAN;
+    puu[b] = n > 0 ? h[5 * b + 3] / n : NAN;
+  }
+  return COLA_OK;
 }
 
 int cola_pk_of(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32_t nbins, double* kmean,

@@ -172,6 +172,14 @@ void launch_axpby(float* y, const float* x, float a, float b, long n, hipStream_
 void launch_pk_bin(const float2* spec, int ng, double box, const double* edges, int nbins,
                    double* partial, int nchunk, hipStream_t s);
 void launch_pk_reduce(const double* partial, int nbins, int nchunk, double* out, hipStream_t s);
+// Density / line-of-sight momentum spectra: partial holds 5 doubles per (bin, chunk),
+// out 5 per bin (sum |k|, P_dd, P_du, P_uu, count).
+void launch_pk_cross(const float2* sd, const float2* sp, int ng, double box, const double* edges, int nbins,
+                     int axis, double* partial, int nchunk, double* out, hipStream_t s);
+// Weights of that deposit (k_velocity.hip): 1/nbar, the scaled velocity along axis, 0.
+void launch_los_weights(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+                        const float* vres, const float* psi1, const float* psi2, int np, int nm,
+                        const VelCoef& k, int axis, float w0, float scale, float* wt, hipStream_t s);
 // Adjoint kernels (k_adjoint.hip).
 void launch_adj_readout_kick(const float* disp, const float* g0, const float* g1, const float* g2,
                              long row_stride, int np, int nm, const KickDrift& kd, float* dbar,

@@ -97,6 +97,91 @@ __global__ void k_pk_reduce(const double* __restrict__ partial, int nbins, int n
   out[3 * b + 2] = s2;
 }
 
+// Density / line-of-sight momentum spectra over the same modes and bins:
+// per bin, sums of |k|, |d|^2, sign(n_axis) Im(d p*), |p|^2 (each scaled and
+// deconvolved like P(k)) and the count; the same fixed-order reduction.
+__global__ __launch_bounds__(kPT) void k_pk_cross(const float2* __restrict__ sd, const float2* __restrict__ sp,
+                                                  int ng, long cols, double kf, double kmax, double vol_fac,
+                                                  const double* __restrict__ edges, int nbins, int axis,
+                                                  double* __restrict__ partial, int nchunk) {
+  __shared__ double acc[5][kPT];
+  const int b = blockIdx.y;
+  const int c = blockIdx.x;
+  const double e0 = edges[b], e1 = edges[b + 1];
+  const double lo2 = (e0 / kf) * (e0 / kf), hi2 = (e1 / kf) * (e1 / kf);
+  const long nrows = (long)ng * ng;
+  const long per = (nrows + nchunk - 1) / nchunk;
+  const long r0 = (long)c * per, r1 = r0 + per < nrows ? r0 + per : nrows;
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int h = ng / 2;
+  for (long r = r0 + threadIdx.x; r < r1; r += kPT) {
+    const int ix = (int)(r / ng), iy = (int)(r - (long)ix * ng);
+    const int nx = ix < h ? ix : ix - ng, ny = iy < h ? iy : iy - ng;
+    const double p2 = (double)nx * nx + (double)ny * ny;
+    if (p2 >= hi2) continue;
+    int zlo = 0;
+    if (lo2 > p2) zlo = (int)floor(sqrt(lo2 - p2)) - 1;
+    if (zlo < 0) zlo = 0;
+    int zhi = (int)ceil(sqrt(hi2 - p2)) + 1;
+    if (zhi > h) zhi = h;
+    const double wxy = sinc_pi((double)nx / ng) * sinc_pi((double)ny / ng);
+    for (int nz = zlo; nz <= zhi; ++nz) {
+      if (nz == 0 && !(ny > 0 || (ny == 0 && nx > 0))) continue;
+      const double n2 = p2 + (double)nz * nz;
+      const double kk = kf * sqrt(n2);
+      if (kk > kmax) continue;
+      if (!(kk >= e0 && kk < e1)) continue;
+      const int na = axis == 0 ? nx : axis == 1 ? ny : nz;
+      const double sg = na > 0 ? 1.0 : na < 0 ? -1.0 : 0.0;
+      const float2 d = sd[r * cols + nz], p = sp[r * cols + nz];
+      double w = wxy * sinc_pi((double)nz / ng);
+      w = w * w;
+      const double f = vol_fac / (w * w);
+      const double dr = d.x, di = d.y, pr = p.x, pi = p.y;
+      a[0] += kk;
+      a[1] += (dr * dr + di * di) * f;
+      a[2] += sg * (di * pr - dr * pi) * f;
+      a[3] += (pr * pr + pi * pi) * f;
+      a[4] += 1.0;
+    }
+  }
+  for (int q = 0; q < 5; ++q) acc[q][threadIdx.x] = a[q];
+  __syncthreads();
+  for (int o = kPT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int q = 0; q < 5; ++q) acc[q][threadIdx.x] += acc[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = partial + ((long)b * nchunk + c) * 5;
+    for (int q = 0; q < 5; ++q) o[q] = acc[q][0];
+  }
+}
+
+__global__ void k_pk_cross_reduce(const double* __restrict__ partial, int nbins, int nchunk,
+                                  double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < nchunk; ++c)
+    for (int q = 0; q < 5; ++q) s[q] += partial[((long)b * nchunk + c) * 5 + q];
+  for (int q = 0; q < 5; ++q) out[5 * b + q] = s[q];
+}
+
+void launch_pk_cross(const float2* sd, const float2* sp, int ng, double box, const double* edges, int nbins,
+                     int axis, double* partial, int nchunk, double* out, hipStream_t s) {
+  const double pi = 3.14159265358979323846;
+  const double kf = 2.0 * pi / box;
+  const double kmax = pi * ng / box;
+  const double v = box * box * box;
+  const double n3 = (double)ng * ng * ng;
+  const double vol_fac = (v / n3) * (v / n3) / v;
+  hipLaunchKernelGGL(k_pk_cross, dim3((unsigned)nchunk, (unsigned)nbins), dim3(kPT), 0, s, sd, sp, ng,
+                     padded_cols(ng), kf, kmax, vol_fac, edges, nbins, axis, partial, nchunk);
+  hipLaunchKernelGGL(k_pk_cross_reduce, dim3((unsigned)((nbins + 63) / 64)), dim3(64), 0, s, partial, nbins,
+                     nchunk, out);
+}
+
 void launch_pk_bin(const float2* spec, int ng, double box, const double* edges, int nbins,
                    double* partial, int nchunk, hipStream_t s) {
   const double pi = 3.14159265358979323846;

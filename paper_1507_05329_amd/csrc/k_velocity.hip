@@ -127,6 +127,55 @@ void launch_snapshot(const float* g0, const float* g1, const float* g2, long row
                        np, nm, np3, k, dout, vout, sdisp, axis);
 }
 
+// Weights of the density / line-of-sight momentum deposit: wt[0] = w0 (1/nbar),
+// wt[1] = scale * v_axis (the velocity of k_velocity, scaled to the shift per
+// particle over nbar), wt[2] = 0.
+template <bool KICK>
+__global__ __launch_bounds__(256) void k_los_weights(const float* __restrict__ g0, const float* __restrict__ g1,
+                                                     const float* __restrict__ g2, long row_stride,
+                                                     const float* __restrict__ disp, const float* __restrict__ vres,
+                                                     const float* __restrict__ psi1, const float* __restrict__ psi2,
+                                                     int np, int nm, long np3, VelCoef k, int axis, float w0,
+                                                     float scale, float* __restrict__ wt) {
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  if (i >= np3) return;
+  const long j = axis * np3 + i;
+  float F = 0.f;
+  if constexpr (KICK) {
+    int c[3];
+    float f[3];
+    home_cell(disp, np3, (uint32_t)i, np, nm, 1.0f, c, f);
+    const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
+    const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
+    const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
+    const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
+                          ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
+    const float* g = axis == 0 ? g0 : axis == 1 ? g1 : g2;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const long idx = rows[s >> 1] + ((s & 1) ? cz1 : c[2]);
+      F += cic_weight(f, s) * g[idx];
+    }
+  }
+  const float v = vres[j] + k.K * F + k.u1 * psi1[j] + k.u2 * psi2[j];
+  wt[i] = w0;
+  wt[np3 + i] = scale * v;
+  wt[2 * np3 + i] = 0.f;
+}
+
+void launch_los_weights(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+                        const float* vres, const float* psi1, const float* psi2, int np, int nm,
+                        const VelCoef& k, int axis, float w0, float scale, float* wt, hipStream_t s) {
+  const long np3 = (long)np * np * np;
+  const dim3 grid((unsigned)((np3 + 255) / 256));
+  if (g0)
+    hipLaunchKernelGGL(k_los_weights<true>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2,
+                       np, nm, np3, k, axis, w0, scale, wt);
+  else
+    hipLaunchKernelGGL(k_los_weights<false>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+                       psi2, np, nm, np3, k, axis, w0, scale, wt);
+}
+
 void launch_velocity(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
                      const float* vres, const float* psi1, const float* psi2, int np, int nm,
                      const VelCoef& k, float* vel, float* sdisp, int axis, hipStream_t s) {

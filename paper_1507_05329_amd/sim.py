@@ -148,6 +148,17 @@ class ColaSim:
                                          -1 if rsd_axis is None else int(rsd_axis)), "snapshot")
         return (d, v) if sd is None else (d, v, sd)
 
+    def pk_velocity(self, edges, axis=2):
+        """Density and line-of-sight momentum spectra on the PM mesh:
+        (kmean, P_dd, P_du, P_uu, counts)."""
+        edges = np.ascontiguousarray(edges, np.float64)
+        nb = len(edges) - 1
+        out = [np.zeros(nb) for _ in range(4)]
+        cnt = np.zeros(nb, np.int64)
+        self._chk(self.lib.cola_pk_velocity(self.ctx, int(axis), dptr(edges), nb, *[dptr(o) for o in out],
+                                            cnt.ctypes.data_as(C.POINTER(C.c_int64))), "pk_velocity")
+        return (*out, cnt)
+
     def pk(self, edges, ngrid=None, disp=None):
         """Binned P(k) of the current positions, or of the displacement field
         ``disp`` (3 x np^3, mesh units) on the same particle lattice."""

@@ -260,3 +260,31 @@ def test_snapshot_matches_oracle_and_ends_on_the_step(small):
     for bad in [(e[3], e[2] - 0.01), (e[3], e[3] + 0.01), (e[2], e[2])]:
         with pytest.raises(ColaError):
             small.snapshot(*bad)
+
+
+@pytest.mark.parametrize("nsteps,axis", [(0, 0), (2, 2)])
+def test_velocity_power_matches_oracle(small, nsteps, axis):
+    # cola_pk_velocity against the oracle's spectra of the same particles with the
+    # oracle's velocities (initial state: no kick; after 2 steps: kick to a_x).
+    from oracle import pk
+    say(f"[gpu] velocity spectra after {nsteps} steps, axis {axis}")
+    L, nm = 100.0, 64
+    small.init_from_noise(torch.from_numpy(white_noise(16, 32)).cuda(), *bbks_table())
+    e = step_edges()
+    for i in range(nsteps):
+        small.step(e[i], e[i + 1])
+    st = small.get_state()
+    o = oracle_state(st, 32, nm, L)
+    edges = pk.linear_edges(L, nm, dk=2 * np.pi / L)
+    km, pdd, pdu, puu, n = small.pk_velocity(edges, axis=axis)
+    v = velocity.full_velocity(o)
+    u = v[axis] / (o.a_x * cosmo.adot(o.a_x, OM))
+    k_o, dd_o, du_o, uu_o, n_o = pk.velocity_power(o.positions(), u, L, nm, edges, axis)
+    assert np.array_equal(n, n_o)
+    ok = n_o > 0
+    assert np.abs(km[ok] / k_o[ok] - 1).max() < 1e-12
+    assert np.abs(pdd[ok] / dd_o[ok] - 1).max() < 1e-4
+    assert np.abs(puu[ok] / uu_o[ok] - 1).max() < 1e-4
+    assert (np.abs(pdu[ok] - du_o[ok]) / np.sqrt(dd_o[ok] * uu_o[ok])).max() < 1e-4
+    assert (pdu[ok][:5] < 0).all()                          # infall at large scales
+    assert np.isnan(pdd[~ok]).all()
