@@ -88,10 +88,29 @@ def velocity_leg(sim, cfg, reps=3):
     ms_k = ms / max(cnt, 1)
     n_p, M = cfg.np_side ** 3, cfg.nmesh ** 3
     nbytes = 72 * n_p + 12 * min(M, 8 * n_p)   # state reads 48, outputs 24, CIC gathers
+    # a snapshot half way through a following step, and the velocity spectra
+    st = sim.get_state(which=())
+    a1 = st["a_x"] + 0.098
+    sim.snapshot(a1, st["a_x"] + 0.049)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.snapshot(a1, st["a_x"] + 0.049)
+    torch.cuda.synchronize()
+    ms_snap = (time.perf_counter() - t0) / reps * 1e3
+    import numpy as np
+    edges = np.linspace(2 * np.pi / cfg.box, np.pi * cfg.nmesh / cfg.box, 41)
+    sim.pk_velocity(edges, axis=2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.pk_velocity(edges, axis=2)
+    ms_pkv = (time.perf_counter() - t0) / reps * 1e3
     return {"ms_call": round(ms_call, 3), "ms_kernel": round(ms_k, 4), "bytes_alg": nbytes,
             "GB/s": round(nbytes / (ms_k * 1e-3) / 1e9, 1),
+            "ms_snapshot_call": round(ms_snap, 3), "ms_pk_velocity_call": round(ms_pkv, 3),
             "note": "velocity at the position time plus the redshift-space displacement (axis 2); "
-                    "the call includes the force pipeline at the current positions"}
+                    "each call includes the force pipeline at the current positions; pk_velocity "
+                    "adds the weighted deposit, 2 FFTs and 40-bin spectra (synchronous)"}
 
 
 def measured_traffic(stage, workload):
