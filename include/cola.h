@@ -189,6 +189,24 @@ int cola_pk_of(cola_ctx* ctx, const float* dev_disp, int32_t ngrid, const double
 int cola_pk_velocity(cola_ctx* ctx, int32_t axis, const double* k_edges, int32_t nbins, double* host_kmean,
                      double* host_p_dd, double* host_p_du, double* host_p_uu, int64_t* host_nmodes);
 
+/* Friends-of-friends groups of the current positions (Sec. 2.3: haloes
+ * with linking length 0.2 times the mean interparticle separation).  Two
+ * particles are friends when their nearest-image separation is at most
+ * b = b_frac * nmesh / np mesh cells (0 < b_frac < 0.5; the paper's 0.2);
+ * groups are the connected components.  dev_labels (np^3 int32, device)
+ * receives for every particle the smallest particle id of its group, so the
+ * output is unique and reproducible.  The decision "separation <= b" is made
+ * in float32: q = float(i nmesh)/float(np), x = q + d, dx = x_a - x_b,
+ * dx -= nmesh rint(dx/nmesh), r2 = (dx0^2 + dx1^2) + dx2^2 <= float(b^2),
+ * one rounding per operation.  dev_work: cola_fof_workspace_bytes bytes of
+ * 256-byte aligned device memory, owned by the caller.  Overwrites the tile
+ * sort's scratch (rebuilt by every deposit); synchronises the stream.
+ * Errors: COLA_EINVAL (NULL pointers, b_frac out of range, misaligned
+ * work), COLA_ENOMEM (work too small), COLA_ESTATE (no particle state, or a
+ * union that exceeded its retry bound). */
+int cola_fof_workspace_bytes(const cola_ctx* ctx, size_t* bytes);
+int cola_fof(cola_ctx* ctx, double b_frac, int32_t* dev_labels, void* dev_work, size_t work_bytes);
+
 /* PM force F (mesh units) at the current positions, 3 * np^3 float32 into
  * dev_force; no state change (the force of Sec. 2.2 as used by cola_step). */
 int cola_force(cola_ctx* ctx, float* dev_force);

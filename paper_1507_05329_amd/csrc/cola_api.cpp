@@ -696,6 +696,42 @@ int cola_pk_velocity(cola_ctx* c, int32_t axis, const double* edges, int32_t nbi
   return COLA_OK;
 }
 
+namespace {
+
+size_t fof_part(long np3, int i) {  // byte offsets of count, start, scan scratch; i = 3: total
+  const size_t n1 = align256((size_t)(np3 + 1) * sizeof(uint32_t));
+  const size_t n2 = align256((size_t)((np3 + 1) / 4096 + 2) * sizeof(uint32_t));
+  const size_t off[4] = {0, n1, 2 * n1, 2 * n1 + n2};
+  return off[i];
+}
+
+}  // namespace
+
+int cola_fof_workspace_bytes(const cola_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return COLA_EINVAL;
+  *bytes = fof_part(c->np3, 3);
+  return COLA_OK;
+}
+
+int cola_fof(cola_ctx* c, double b_frac, int32_t* labels, void* work, size_t work_bytes) {
+  if (!c || !labels || !work) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  if (!(b_frac > 0.0 && b_frac < 0.5)) return fail(c, COLA_EINVAL, "b_frac must lie in (0, 0.5)");
+  if (((uintptr_t)work & 255) != 0) return fail(c, COLA_EINVAL, "dev_work must be 256-byte aligned");
+  if (work_bytes < fof_part(c->np3, 3)) return fail(c, COLA_ENOMEM, "dev_work smaller than cola_fof_workspace_bytes");
+  char* w = static_cast<char*>(work);
+  launch_fill_u32(c->flag, 1, 0u, c->stream);
+  launch_fof(c->disp, c->p.np, c->p.nmesh, b_frac, reinterpret_cast<uint32_t*>(labels),
+             reinterpret_cast<uint32_t*>(w + fof_part(c->np3, 0)), reinterpret_cast<uint32_t*>(w + fof_part(c->np3, 1)),
+             reinterpret_cast<uint32_t*>(w + fof_part(c->np3, 2)), c->pkey, c->prank, c->perm, c->flag, c->stream);
+  LAUNCH_CHECK(c, "cola_fof");
+  uint32_t h = 0;
+  HIP_TRY(c, hipMemcpyAsync(&h, c->flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h) return fail(c, COLA_ESTATE, "friends-of-friends: a union exceeded its retry bound");
+  return COLA_OK;
+}
+
 int cola_pk_of(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32_t nbins, double* kmean,
                double* pk, int64_t* nmodes) {
   if (!c || !disp || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");

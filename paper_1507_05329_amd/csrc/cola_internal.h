@@ -176,6 +176,12 @@ void launch_pk_reduce(const double* partial, int nbins, int nchunk, double* out,
 // out 5 per bin (sum |k|, P_dd, P_du, P_uu, count).
 void launch_pk_cross(const float2* sd, const float2* sp, int ng, double box, const double* edges, int nbins,
                      int axis, double* partial, int nchunk, double* out, hipStream_t s);
+// Friends-of-friends labels (k_fof.hip): labels[i] = smallest id of i's group.
+// count and start hold np^3 + 1 entries, scan_scratch (np^3 + 1) / 4096 + 2;
+// key, rank, sorted np^3 each; flag is set if a union exceeded its retry bound.
+void launch_fof(const float* disp, int np, int nm, double b_frac, uint32_t* labels, uint32_t* count,
+                uint32_t* start, uint32_t* scan_scratch, uint32_t* key, uint32_t* rank, uint32_t* sorted,
+                uint32_t* flag, hipStream_t s);
 // Weights of that deposit (k_velocity.hip): 1/nbar, the scaled velocity along axis, 0.
 void launch_los_weights(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
                         const float* vres, const float* psi1, const float* psi2, int np, int nm,

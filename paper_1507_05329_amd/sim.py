@@ -148,6 +148,18 @@ class ColaSim:
                                          -1 if rsd_axis is None else int(rsd_axis)), "snapshot")
         return (d, v) if sd is None else (d, v, sd)
 
+    def fof(self, b_frac=0.2, out=None):
+        """Friends-of-friends labels (np^3 int32: smallest id of each particle's group)."""
+        n = C.c_size_t()
+        self._chk(self.lib.cola_fof_workspace_bytes(self.ctx, C.byref(n)), "fof_workspace_bytes")
+        work = torch.empty((n.value + 255) // 4 + 64, dtype=torch.int32, device=self.device)
+        off = (-work.data_ptr()) % 256
+        wptr = C.c_void_p(work.data_ptr() + off)
+        if out is None:
+            out = torch.empty(self.n_particles, dtype=torch.int32, device=self.device)
+        self._chk(self.lib.cola_fof(self.ctx, float(b_frac), _ptr(out), wptr, n.value), "fof")
+        return out
+
     def pk_velocity(self, edges, axis=2):
         """Density and line-of-sight momentum spectra on the PM mesh:
         (kmean, P_dd, P_du, P_uu, counts)."""

@@ -1,0 +1,128 @@
+"""GPU friends-of-friends groups (cola_fof, Sec. 2.3 haloes) against the
+oracle: labels bit-exact on evolved clustered states at 32^3/64^3 and
+64^3/128^3; at 256^3/768^3 (the bench's workload) the label invariants and,
+for sampled particles, every friend found by the oracle's float32 test
+shares the label.
+
+All compute goes through the C ABI (paper_1507_05329_amd.sim -> libcola.so).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import fof  # noqa: E402
+from paper_1507_05329_amd._lib import ColaError  # noqa: E402
+from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges, white_noise  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def evolved_sim(np_side, nm, box, seed, nsteps=10):
+    from paper_1507_05329_amd.sim import ColaSim
+    sim = ColaSim(np_side, nm, box)
+    sim.init_from_noise(torch.from_numpy(white_noise(seed, np_side)).cuda(), *bbks_table())
+    e = step_edges()
+    for i in range(nsteps):
+        sim.step(e[i], e[i + 1])
+    return sim
+
+
+@pytest.mark.parametrize("np_side,nm,box,b_frac", [
+    (32, 64, 100.0, 0.2), (32, 64, 100.0, 0.1), (32, 64, 100.0, 0.45), (64, 128, 100.0, 0.2)])
+def test_fof_labels_bit_exact(np_side, nm, box, b_frac):
+    say(f"[gpu] fof {np_side}^3/{nm}^3 b = {b_frac}")
+    sim = evolved_sim(np_side, nm, box, 31)
+    try:
+        lab = sim.fof(b_frac).cpu().numpy()
+        disp = sim.get_state()["disp"].cpu().numpy()
+        again = sim.fof(b_frac).cpu().numpy()
+    finally:
+        sim.close()
+    ref = fof.fof_labels(disp, np_side, nm, b_frac)
+    assert np.array_equal(lab, ref)
+    assert np.array_equal(lab, again)
+    sizes = np.bincount(lab)
+    say(f"[gpu]   groups >= 32 particles: {(sizes >= 32).sum()}, largest {sizes.max()}")
+    if b_frac == 0.2:
+        assert (sizes >= 32).sum() > 0
+
+
+def test_fof_initial_lattice_is_all_singletons():
+    # at a = 0.02 neighbours are about one separation apart, far beyond b = 0.2 of it
+    from paper_1507_05329_amd.sim import ColaSim
+    sim = ColaSim(32, 64, 100.0)
+    try:
+        sim.init_from_noise(torch.from_numpy(white_noise(32, 32)).cuda(), *bbks_table())
+        lab = sim.fof().cpu().numpy()
+    finally:
+        sim.close()
+    assert np.array_equal(lab, np.arange(32 ** 3))
+
+
+def test_fof_rejects_bad_arguments():
+    from paper_1507_05329_amd.sim import ColaSim
+    sim = ColaSim(32, 64, 100.0)
+    try:
+        sim.init_from_noise(torch.from_numpy(white_noise(33, 32)).cuda(), *bbks_table())
+        for b in (0.0, 0.5, -0.1):
+            with pytest.raises(ColaError):
+                sim.fof(b)
+        import ctypes as C
+        out = torch.empty(32 ** 3, dtype=torch.int32, device="cuda")
+        work = torch.empty(1024, dtype=torch.int32, device="cuda")
+        code = sim.lib.cola_fof(sim.ctx, 0.2, C.c_void_p(out.data_ptr()), C.c_void_p(work.data_ptr()), 4096)
+        assert code != 0
+        assert bool((sim.fof() >= 0).all())                       # usable after the errors
+    finally:
+        sim.close()
+
+
+def test_fof_production_size_invariants_and_sampled_friends():
+    cfg = CONFIGS["production"]
+    NP, NM, L = cfg.np_side, cfg.nmesh, cfg.box
+    say(f"[gpu] fof at {NP}^3/{NM}^3 after 10 steps")
+    sim = evolved_sim(NP, NM, L, cfg.seed)
+    try:
+        lab = sim.fof(0.2).cpu().numpy().astype(np.int64)
+        disp = sim.get_state()["disp"].cpu().numpy()
+    finally:
+        sim.close()
+    ids = np.arange(NP ** 3)
+    assert (lab <= ids).all() and (lab >= 0).all()
+    assert (lab[lab] == lab).all()
+    sizes = np.bincount(lab)
+    nh = int((sizes >= 32).sum())
+    say(f"[gpu]   groups >= 32 particles: {nh}, largest {sizes.max()}, in groups >= 32: "
+        f"{sizes[sizes >= 32].sum() / NP ** 3:.3f}")
+    assert nh > 100
+    # sampled particles: every friend (float32 test) carries the same label
+    from scipy.spatial import cKDTree
+    x = fof.positions_fp32(disp, NP, NM)
+    say("[gpu]   building the k-d tree")
+    xw = np.mod(x.astype(np.float64), NM)
+    xw[xw >= NM] = 0.0
+    tree = cKDTree(xw.T, boxsize=NM)
+    rng = np.random.default_rng(0)
+    sample = np.r_[rng.integers(0, NP ** 3, 3000), np.flatnonzero(lab != ids)[:: max(1, (lab != ids).sum() // 3000)]]
+    b2 = fof.link_length_sq(0.2, NP, NM)
+    r = float(np.sqrt(np.float64(b2))) * (1 + 1e-5) + 1e-6
+    nfriends = 0
+    for i in sample:
+        cand = np.array([j for j in tree.query_ball_point(xw[:, i], r) if j != i], dtype=np.int64)
+        if not len(cand):
+            continue
+        a = np.minimum(cand, i)
+        b = np.maximum(cand, i)
+        fr = cand[fof.r2_fp32(x, a, b, NM) <= b2]
+        nfriends += len(fr)
+        assert (lab[fr] == lab[i]).all()
+    say(f"[gpu]   {len(sample)} sampled particles, {nfriends} friends checked")
+    assert nfriends > 1000
