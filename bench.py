@@ -19,7 +19,8 @@ dominant kernel's achieved bandwidth against the 8 TB/s HBM peak (roofline;
 `traffic` comes from the committed counter summary while its kernel source
 is unchanged), followed by the particle velocities at the final position
 time with their redshift-space displacement (velocity: whole call with its
-force pipeline, and the velocity kernel against its algorithmic bytes).  The FP64 CPU oracle is timed on one step of the same
+force pipeline, and the velocity kernel against its algorithmic bytes), the
+snapshot and velocity-spectra calls, and the friends-of-friends groups (fof).  The FP64 CPU oracle is timed on one step of the same
 workload on the host cores (cpu_baseline).
 
 Prints one JSON line.
@@ -111,6 +112,22 @@ def velocity_leg(sim, cfg, reps=3):
             "note": "velocity at the position time plus the redshift-space displacement (axis 2); "
                     "each call includes the force pipeline at the current positions; pk_velocity "
                     "adds the weighted deposit, 2 FFTs and 40-bin spectra (synchronous)"}
+
+
+def fof_leg(sim, reps=3):
+    """cola_fof (b = 0.2 of the mean separation) at the final positions: time per
+    call (the call synchronises) and the groups of at least 32 particles."""
+    import torch
+    lab = sim.fof(0.2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.fof(0.2, out=lab)
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    sizes = torch.bincount(lab.long())
+    big = sizes >= 32
+    return {"ms_call": round(ms, 3), "b_frac": 0.2, "groups_ge_32": int(big.sum()),
+            "frac_in_groups_ge_32": round(float(sizes[big].sum()) / lab.numel(), 4),
+            "largest": int(sizes.max())}
 
 
 def measured_traffic(stage, workload):
@@ -347,6 +364,7 @@ def main():
         simt.step(e[i], e[i + 1])
     st = simt.stage_times()
     snapshot = None if args.no_velocity else velocity_leg(simt, cfg)
+    halos = None if args.no_velocity else fof_leg(simt)
     simt.close()
     sb = stage_bytes(cfg.np_side, cfg.nmesh)
     stages = {}
@@ -397,6 +415,7 @@ def main():
             "note": "forward steps keep their force meshes (one slot per step); the adjoint reads them"},
         "batched": batched,
         "velocity": snapshot,
+        "fof": halos,
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,

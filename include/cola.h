@@ -189,8 +189,9 @@ int cola_pk_of(cola_ctx* ctx, const float* dev_disp, int32_t ngrid, const double
 int cola_pk_velocity(cola_ctx* ctx, int32_t axis, const double* k_edges, int32_t nbins, double* host_kmean,
                      double* host_p_dd, double* host_p_du, double* host_p_uu, int64_t* host_nmodes);
 
-/* Friends-of-friends groups of the current positions (Sec. 2.3: haloes
- * with linking length 0.2 times the mean interparticle separation).  Two
+/* Friends-of-friends groups of the current positions (Sec. 2.3: the halo
+ * finder run on the fly; Sec. 3.1: linking length 0.2 times the mean
+ * particle separation, 0.37 for 2LPT).  Two
  * particles are friends when their nearest-image separation is at most
  * b = b_frac * nmesh / np mesh cells (0 < b_frac < 0.5; the paper's 0.2);
  * groups are the connected components.  dev_labels (np^3 int32, device)

@@ -19,5 +19,5 @@ Modules
   cic_fp32   float32 same-order replay of the deterministic CIC deposit
   adjoint    reverse-mode derivative of the step and of the 2LPT map
   philox     Philox4x32-10 counter-based generator (Salmon et al. 2011)
-  fof        friends-of-friends groups, b = 0.2 of the mean separation (Sec. 2.3)
+  fof        friends-of-friends groups, b = 0.2 of the mean separation (Sec. 3.1)
 """

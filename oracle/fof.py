@@ -1,6 +1,6 @@
-"""Friends-of-friends groups of the particles (Koda et al. 2015, Sec. 2.3:
-haloes found with linking length 0.2 times the mean interparticle
-separation), as a plain reference.
+"""Friends-of-friends groups of the particles (Koda et al. 2015: the halo
+finder run on the fly in Sec. 2.3, linking length 0.2 times the mean particle
+separation in Sec. 3.1), as a plain reference.
 
 Test infrastructure: the slow, plainly written reference that the GPU path is
 checked against; nothing in the library imports it.

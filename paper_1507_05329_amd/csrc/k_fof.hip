@@ -1,5 +1,6 @@
-// Friends-of-friends groups (Koda et al. 2015, Sec. 2.3: haloes found with a
-// linking length of 0.2 times the mean interparticle separation).
+// Friends-of-friends groups (Koda et al. 2015: Sec. 2.3 runs a FoF halo finder
+// on the fly; Sec. 3.1 links at 0.2 times the mean particle separation, 0.37
+// for 2LPT).
 //
 // Two particles are friends when their nearest-image separation is at most b;
 // the groups are the connected components, each labelled by its smallest

@@ -1,4 +1,4 @@
-"""GPU friends-of-friends groups (cola_fof, Sec. 2.3 haloes) against the
+"""GPU friends-of-friends groups (cola_fof; Sec. 2.3, Sec. 3.1) against the
 oracle: labels bit-exact on evolved clustered states at 32^3/64^3 and
 64^3/128^3; at 256^3/768^3 (the bench's workload) the label invariants and,
 for sampled particles, every friend found by the oracle's float32 test

@@ -1,4 +1,4 @@
-"""Pins for the oracle's friends-of-friends groups (Sec. 2.3 haloes, b = 0.2)."""
+"""Pins for the oracle's friends-of-friends groups (Sec. 2.3, Sec. 3.1: b = 0.2)."""
 import numpy as np
 import pytest
 
