@@ -21,7 +21,8 @@
 // coherent stores of a grandparent (a valid ancestor; a non-root never
 // becomes a root again, and only roots are hooked, so no hook is undone).
 // A failed compare-and-swap means another thread hooked that root first;
-// the retry count is bounded and an exceeded bound raises a flag.
+// the retry count is bounded and an exceeded bound raises a flag.  The last
+// pass writes every particle's root without halving (see fof_root).
 #include "cola_device.h"
 #include "cola_internal.h"
 
@@ -53,6 +54,17 @@ __device__ __forceinline__ void fof_pos(const float* __restrict__ disp, long np3
 __device__ __forceinline__ int fof_cell1(float x, float s_inv, int np) {
   int c = (int)floorf(x * s_inv) % np;
   return c < 0 ? c + np : c;
+}
+
+// Root without writes: the final pass must not halve paths, or a thread that
+// read par[x] before another wrote x's root there could overwrite that root
+// with an intermediate ancestor.
+__device__ __forceinline__ uint32_t fof_root(const uint32_t* par, uint32_t x) {
+  for (;;) {
+    const uint32_t p = ld_rel(par + x);
+    if (p == x) return x;
+    x = p;
+  }
 }
 
 __device__ __forceinline__ uint32_t fof_find(uint32_t* par, uint32_t x) {
@@ -138,7 +150,7 @@ __global__ __launch_bounds__(256) void k_fof_link(const float* __restrict__ disp
 __global__ __launch_bounds__(256) void k_fof_compress(uint32_t* par, long np3) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i < np3) {
-    const uint32_t r = fof_find(par, (uint32_t)i);
+    const uint32_t r = fof_root(par, (uint32_t)i);   // each thread writes only its own entry
     st_rel(par + i, r);
   }
 }
