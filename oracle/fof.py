@@ -96,3 +96,26 @@ def fof_labels_brute(disp: np.ndarray, np_side: int, nm: int, b_frac: float = 0.
     a, b = np.triu_indices(n, 1)
     keep = r2_fp32(x, a, b, nm) <= b2
     return labels_from_pairs(n, a[keep], b[keep])
+
+
+def halo_catalogue(disp: np.ndarray, vel, labels: np.ndarray, np_side: int, nm: int, min_members: int):
+    """Groups with at least ``min_members`` particles, in increasing root id:
+    root id, member count, centre of mass (mesh units, in [0, nm)) and mean
+    velocity.  The centre is the root's position plus the mean nearest-image
+    offset of the members from the root (groups may straddle the box edge);
+    float64 from the float32 positions."""
+    x = positions_fp32(disp, np_side, nm).astype(np.float64)
+    counts = np.bincount(labels, minlength=labels.size)
+    roots = np.flatnonzero(counts >= min_members)
+    com = np.zeros((3, len(roots)))
+    vmean = np.zeros((3, len(roots)))
+    order = np.argsort(labels, kind="stable")
+    starts = np.searchsorted(labels[order], roots)
+    for h, (r, s) in enumerate(zip(roots, starts)):
+        m = order[s:s + counts[r]]
+        rel = x[:, m] - x[:, [r]]
+        rel -= nm * np.rint(rel / nm)
+        com[:, h] = np.mod(x[:, r] + rel.mean(axis=1), nm)
+        if vel is not None:
+            vmean[:, h] = vel[:, m].astype(np.float64).mean(axis=1)
+    return roots.astype(np.int32), counts[roots].astype(np.int32), com, vmean

@@ -77,3 +77,25 @@ def test_labels_are_smallest_ids_of_their_groups(seed):
     a, b = np.triu_indices(len(lab), 1)
     friends = fof.r2_fp32(x, a, b, 16) <= fof.link_length_sq(0.2, 8, 16)
     assert (lab[a[friends]] == lab[b[friends]]).all()
+
+
+def test_halo_catalogue_straddling_the_edge_and_counts():
+    # a chain across the box edge: the centre is the mean of the unwrapped members
+    d = np.zeros((3, 64), np.float32)
+    d[2, 0] = np.float32(-0.1)           # x = -0.1
+    d[2, 3] = np.float32(1.95)           # x = 7.95
+    d[2, 1] = np.float32(-1.82)          # x = 0.18
+    vel = np.zeros((3, 64), np.float32)
+    vel[0, [0, 1, 3]] = [1.0, 2.0, 6.0]
+    lab = fof.fof_labels(d, 4, 8, 0.15)
+    roots, counts, com, vm = fof.halo_catalogue(d, vel, lab, 4, 8, 2)
+    assert roots.tolist() == [0] and counts.tolist() == [3]
+    want_z = np.mod((-0.1 + 0.18 - 0.05) / 3.0, 8)      # members at -0.1, 0.18, -0.05
+    assert com[2, 0] == pytest.approx(want_z, abs=1e-6)
+    assert com[0, 0] == pytest.approx(0.0, abs=1e-12) and com[1, 0] == pytest.approx(0.0, abs=1e-12)
+    assert vm[0, 0] == pytest.approx(3.0)
+    # every group of the clustered case is listed once with its size
+    d = clustered_disp(8, 16, 5)
+    lab = fof.fof_labels(d, 8, 16)
+    roots, counts, _, _ = fof.halo_catalogue(d, None, lab, 8, 16, 1)
+    assert counts.sum() == lab.size and (lab[roots] == roots).all()
