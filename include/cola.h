@@ -208,6 +208,27 @@ int cola_pk_velocity(cola_ctx* ctx, int32_t axis, const double* k_edges, int32_t
 int cola_fof_workspace_bytes(const cola_ctx* ctx, size_t* bytes);
 int cola_fof(cola_ctx* ctx, double b_frac, int32_t* dev_labels, void* dev_work, size_t work_bytes);
 
+/* Halo catalogue of cola_fof labels of the current positions (Sec. 2.3: halo
+ * catalogues generated on the fly): the groups with at least min_members
+ * particles, in increasing root id (the root is the group's smallest id).
+ * host_n_halos receives their number; the device arrays (capacity max_halos,
+ * caller-owned) receive the root, the member count, the centre of mass
+ * dev_halo_pos[3 * max_halos] (component e of halo h at e * max_halos + h,
+ * mesh units in [0, nmesh): the root's position plus the mean nearest-image
+ * offset of the members from the root) and, if dev_vel (3 * np^3, e.g.
+ * cola_velocity's output) is given, the mean velocity dev_halo_vel (same
+ * layout; both or neither may be NULL).  Sums are 64-bit fixed point
+ * (2^-20 cells, 2^-16 velocity units), so the result does not depend on the
+ * order of the atomics.  dev_work: cola_fof_halos_workspace_bytes(min_members)
+ * bytes, 256-byte aligned.  Synchronises the stream.  Errors: COLA_EINVAL
+ * (NULL pointers, min_members < 1, a label outside [0, np^3)), COLA_ENOMEM
+ * (work too small, or more halos than max_halos: host_n_halos then holds the
+ * number needed), COLA_ESTATE (no particle state). */
+int cola_fof_halos_workspace_bytes(const cola_ctx* ctx, int32_t min_members, size_t* bytes);
+int cola_fof_halos(cola_ctx* ctx, const int32_t* dev_labels, const float* dev_vel, int32_t min_members,
+                   int32_t max_halos, int32_t* host_n_halos, int32_t* dev_halo_root, int32_t* dev_halo_count,
+                   float* dev_halo_pos, float* dev_halo_vel, void* dev_work, size_t work_bytes);
+
 /* PM force F (mesh units) at the current positions, 3 * np^3 float32 into
  * dev_force; no state change (the force of Sec. 2.2 as used by cola_step). */
 int cola_force(cola_ctx* ctx, float* dev_force);

@@ -55,6 +55,9 @@ _SIGS = {
     "cola_snapshot": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, C.c_int32]),
     "cola_fof_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "cola_fof": (C.c_int, [_P, C.c_double, _P, _P, C.c_size_t]),
+    "cola_fof_halos_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
+    "cola_fof_halos": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_int32), _P, _P, _P, _P, _P,
+                                 C.c_size_t]),
     "cola_pk_velocity": (C.c_int, [_P, C.c_int32, _DP, C.c_int32, _DP, _DP, _DP, _DP, C.POINTER(C.c_int64)]),
     "cola_pk_of": (C.c_int, [_P, _P, C.c_int32, _DP, C.c_int32, _DP, _DP, C.POINTER(C.c_int64)]),
     "cola_get_state": (C.c_int, [_P, _P, _P, _P, _P, _DP, _DP]),

@@ -732,6 +732,54 @@ int cola_fof(cola_ctx* c, double b_frac, int32_t* labels, void* work, size_t wor
   return COLA_OK;
 }
 
+namespace {
+
+size_t halo_part(long np3, int32_t minm, int i) {  // count, flg, hidx, scan scratch, acc; i = 5: total
+  const size_t a = align256((size_t)np3 * sizeof(uint32_t));
+  const size_t b = align256((size_t)(np3 + 1) * sizeof(uint32_t));
+  const size_t sc = align256((size_t)((np3 + 1) / 4096 + 2) * sizeof(uint32_t));
+  const size_t ac = align256((size_t)(np3 / minm + 1) * 6 * sizeof(unsigned long long));
+  const size_t off[6] = {0, a, 2 * a, 2 * a + b, 2 * a + b + sc, 2 * a + b + sc + ac};
+  return off[i];
+}
+
+}  // namespace
+
+int cola_fof_halos_workspace_bytes(const cola_ctx* c, int32_t min_members, size_t* bytes) {
+  if (!c || !bytes || min_members < 1) return COLA_EINVAL;
+  *bytes = halo_part(c->np3, min_members, 5);
+  return COLA_OK;
+}
+
+int cola_fof_halos(cola_ctx* c, const int32_t* labels, const float* vel, int32_t min_members, int32_t max_halos,
+                   int32_t* n_halos, int32_t* root, int32_t* count, float* pos, float* vout, void* work,
+                   size_t work_bytes) {
+  if (!c || !labels || !n_halos || !root || !count || !pos || !work) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  if (min_members < 1 || max_halos < 0) return fail(c, COLA_EINVAL, "min_members >= 1, max_halos >= 0");
+  if ((vel == nullptr) != (vout == nullptr)) return fail(c, COLA_EINVAL, "dev_vel and dev_halo_vel go together");
+  if (((uintptr_t)work & 255) != 0) return fail(c, COLA_EINVAL, "dev_work must be 256-byte aligned");
+  if (work_bytes < halo_part(c->np3, min_members, 5))
+    return fail(c, COLA_ENOMEM, "dev_work smaller than cola_fof_halos_workspace_bytes");
+  char* w = static_cast<char*>(work);
+  auto u32 = [&](int i) { return reinterpret_cast<uint32_t*>(w + halo_part(c->np3, min_members, i)); };
+  launch_fill_u32(c->flag, 1, 0u, c->stream);
+  launch_halo_count(labels, c->np3, min_members, u32(0), u32(1), u32(2), u32(3), c->flag, c->stream);
+  LAUNCH_CHECK(c, "cola_fof_halos");
+  uint32_t h[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(&h[0], c->flag, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&h[1], u32(2) + c->np3, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h[0]) return fail(c, COLA_EINVAL, "a label lies outside [0, np^3)");
+  *n_halos = (int32_t)h[1];
+  if ((long)h[1] > (long)max_halos) return fail(c, COLA_ENOMEM, "more halos than max_halos (count in n_halos)");
+  launch_halo_fill(c->disp, vel, labels, u32(0), u32(1), u32(2), c->p.np, c->p.nmesh, (int)h[1], max_halos,
+                   reinterpret_cast<unsigned long long*>(u32(4)), root, count, pos, vout, c->stream);
+  LAUNCH_CHECK(c, "cola_fof_halos");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return COLA_OK;
+}
+
 int cola_pk_of(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32_t nbins, double* kmean,
                double* pk, int64_t* nmodes) {
   if (!c || !disp || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");

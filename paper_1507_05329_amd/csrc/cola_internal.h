@@ -182,6 +182,16 @@ void launch_pk_cross(const float2* sd, const float2* sp, int ng, double box, con
 void launch_fof(const float* disp, int np, int nm, double b_frac, uint32_t* labels, uint32_t* count,
                 uint32_t* start, uint32_t* scan_scratch, uint32_t* key, uint32_t* rank, uint32_t* sorted,
                 uint32_t* flag, hipStream_t s);
+// Halo catalogue of FoF labels (k_fof.hip): count per label, flags of groups with
+// >= minm members, their exclusive scan (hidx[np3] = number of halos); then roots,
+// counts, centres and mean velocities (SoA with the given stride) from 64-bit
+// fixed-point sums (acc: 6 per halo).  bad is set for a label outside [0, np3).
+void launch_halo_count(const int32_t* lab, long np3, int32_t minm, uint32_t* count, uint32_t* flg, uint32_t* hidx,
+                       uint32_t* scan_scratch, uint32_t* bad, hipStream_t s);
+void launch_halo_fill(const float* disp, const float* vel, const int32_t* lab, const uint32_t* count,
+                      const uint32_t* flg, const uint32_t* hidx, int np, int nm, int nh, int stride,
+                      unsigned long long* acc, int32_t* root, int32_t* cnt, float* pos, float* vout,
+                      hipStream_t s);
 // Weights of that deposit (k_velocity.hip): 1/nbar, the scaled velocity along axis, 0.
 void launch_los_weights(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
                         const float* vres, const float* psi1, const float* psi2, int np, int nm,

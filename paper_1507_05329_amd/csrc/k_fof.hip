@@ -173,4 +173,113 @@ void launch_fof(const float* disp, int np, int nm, double b_frac, uint32_t* labe
   hipLaunchKernelGGL(k_fof_compress, dim3(blocks), dim3(256), 0, s, labels, np3);
 }
 
+// ---------------------------------------------------------------------------
+// Halo catalogue of the groups with at least min_members particles, in
+// increasing root id: member count, centre of mass (the root's position plus
+// the mean nearest-image offset of the members from it, wrapped into
+// [0, nm)) and mean velocity.  Offsets and velocities are summed as 64-bit
+// fixed point (2^-20 cells, 2^-16 velocity units): integer sums do not
+// depend on the order of the atomics, so the catalogue is reproducible.
+
+constexpr double kPosFix = 1048576.0, kVelFix = 65536.0;
+
+__global__ __launch_bounds__(256) void k_halo_count(const int32_t* __restrict__ lab, long np3,
+                                                    uint32_t* __restrict__ count, uint32_t* bad) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= np3) return;
+  const int32_t l = lab[i];
+  if (l < 0 || (long)l >= np3) {   // not a label of this particle set
+    atomicOr(bad, 1u);
+    return;
+  }
+  atomicAdd(&count[l], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_halo_flag(const uint32_t* __restrict__ count, long np3, uint32_t minm,
+                                                   uint32_t* __restrict__ flg) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < np3) flg[i] = count[i] >= minm ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_halo_roots(const uint32_t* __restrict__ count,
+                                                    const uint32_t* __restrict__ flg,
+                                                    const uint32_t* __restrict__ hidx, long np3,
+                                                    int32_t* __restrict__ root, int32_t* __restrict__ cnt) {
+  const long r = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (r < np3 && flg[r]) {
+    root[hidx[r]] = (int32_t)r;
+    cnt[hidx[r]] = (int32_t)count[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_halo_accum(const float* __restrict__ disp, const float* __restrict__ vel,
+                                                    const int32_t* __restrict__ lab,
+                                                    const uint32_t* __restrict__ flg,
+                                                    const uint32_t* __restrict__ hidx, int np, int nm, long np3,
+                                                    unsigned long long* __restrict__ acc) {
+#pragma clang fp contract(off)
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= np3) return;
+  const int32_t l = lab[i];
+  if (l < 0 || (long)l >= np3) return;
+  const uint32_t r = (uint32_t)l;
+  if (!flg[r]) return;
+  const long h = hidx[r];
+  float xi[3], xr[3];
+  fof_pos(disp, np3, (uint32_t)i, np, nm, xi);
+  fof_pos(disp, np3, r, np, nm, xr);
+  const float nmf = (float)nm;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    float dx = __fsub_rn(xi[e], xr[e]);
+    dx = __fsub_rn(dx, __fmul_rn(nmf, rintf(__fdiv_rn(dx, nmf))));
+    atomicAdd(acc + h * 6 + e, (unsigned long long)llrint((double)dx * kPosFix));
+    if (vel) atomicAdd(acc + h * 6 + 3 + e, (unsigned long long)llrint((double)vel[e * np3 + i] * kVelFix));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_halo_final(const float* __restrict__ disp,
+                                                    const int32_t* __restrict__ root,
+                                                    const int32_t* __restrict__ cnt,
+                                                    const unsigned long long* __restrict__ acc, int np, int nm,
+                                                    long np3, int nh, int stride, float* __restrict__ pos,
+                                                    float* __restrict__ vout) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= nh) return;
+  float xr[3];
+  fof_pos(disp, np3, (uint32_t)root[h], np, nm, xr);
+  const double n = (double)cnt[h];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    double c = (double)xr[e] + (double)(long long)acc[(long)h * 6 + e] / kPosFix / n;
+    c -= nm * floor(c / nm);
+    if (c >= nm) c -= nm;
+    pos[(long)e * stride + h] = (float)c;
+    if (vout) vout[(long)e * stride + h] = (float)((double)(long long)acc[(long)h * 6 + 3 + e] / kVelFix / n);
+  }
+}
+
+void launch_halo_count(const int32_t* lab, long np3, int32_t minm, uint32_t* count, uint32_t* flg, uint32_t* hidx,
+                       uint32_t* scan_scratch, uint32_t* bad, hipStream_t s) {
+  const unsigned blocks = (unsigned)((np3 + 255) / 256);
+  launch_fill_u32(count, np3, 0u, s);
+  hipLaunchKernelGGL(k_halo_count, dim3(blocks), dim3(256), 0, s, lab, np3, count, bad);
+  hipLaunchKernelGGL(k_halo_flag, dim3(blocks), dim3(256), 0, s, count, np3, (uint32_t)minm, flg);
+  launch_exclusive_scan(flg, hidx, np3, scan_scratch, s);
+}
+
+void launch_halo_fill(const float* disp, const float* vel, const int32_t* lab, const uint32_t* count,
+                      const uint32_t* flg, const uint32_t* hidx, int np, int nm, int nh, int stride,
+                      unsigned long long* acc, int32_t* root, int32_t* cnt, float* pos, float* vout,
+                      hipStream_t s) {
+  const long np3 = (long)np * np * np;
+  const unsigned blocks = (unsigned)((np3 + 255) / 256);
+  if (nh > 0) launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 12L * nh, 0u, s);
+  hipLaunchKernelGGL(k_halo_roots, dim3(blocks), dim3(256), 0, s, count, flg, hidx, np3, root, cnt);
+  hipLaunchKernelGGL(k_halo_accum, dim3(blocks), dim3(256), 0, s, disp, vel, lab, flg, hidx, np, nm, np3, acc);
+  if (nh > 0)
+    hipLaunchKernelGGL(k_halo_final, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, s, disp, root, cnt, acc,
+                       np, nm, np3, nh, stride, pos, vout);
+}
+
 }  // namespace cola

@@ -160,6 +160,29 @@ class ColaSim:
         self._chk(self.lib.cola_fof(self.ctx, float(b_frac), _ptr(out), wptr, n.value), "fof")
         return out
 
+    def fof_halos(self, labels, vel=None, min_members=32, max_halos=None):
+        """Halo catalogue of FoF labels: dict of root, count (int32), pos and
+        (with vel) vel, (3, n) float32 in mesh units, in increasing root id."""
+        n = C.c_size_t()
+        self._chk(self.lib.cola_fof_halos_workspace_bytes(self.ctx, int(min_members), C.byref(n)),
+                  "fof_halos_workspace_bytes")
+        work = torch.empty((n.value + 255) // 4 + 64, dtype=torch.int32, device=self.device)
+        wptr = C.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        cap = int(max_halos) if max_halos is not None else self.n_particles // int(min_members) + 1
+        root = torch.empty(cap, dtype=torch.int32, device=self.device)
+        cnt = torch.empty(cap, dtype=torch.int32, device=self.device)
+        pos = torch.empty((3, cap), dtype=torch.float32, device=self.device)
+        hv = torch.empty((3, cap), dtype=torch.float32, device=self.device) if vel is not None else None
+        nh = C.c_int32()
+        self._chk(self.lib.cola_fof_halos(self.ctx, _ptr(labels), _ptr(vel) if vel is not None else None,
+                                          int(min_members), cap, C.byref(nh), _ptr(root), _ptr(cnt), _ptr(pos),
+                                          _ptr(hv) if hv is not None else None, wptr, n.value), "fof_halos")
+        k = nh.value
+        out = {"root": root[:k], "count": cnt[:k], "pos": pos[:, :k]}
+        if hv is not None:
+            out["vel"] = hv[:, :k]
+        return out
+
     def pk_velocity(self, edges, axis=2):
         """Density and line-of-sight momentum spectra on the PM mesh:
         (kmean, P_dd, P_du, P_uu, counts)."""

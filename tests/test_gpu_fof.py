@@ -128,3 +128,41 @@ def test_fof_production_size_invariants_and_sampled_friends():
         assert (lab[fr] == lab[i]).all()
     say(f"[gpu]   {len(sample)} sampled particles, {nfriends} friends checked")
     assert nfriends > 1000
+
+
+def test_halo_catalogue_matches_oracle():
+    # 64^3/128^3 after 10 steps: roots and counts exact, centres of mass (nearest image,
+    # wrapped) and mean velocities against the oracle on the same labels and velocities
+    say("[gpu] halo catalogue 64^3/128^3")
+    np_side, nm = 64, 128
+    sim = evolved_sim(np_side, nm, 100.0, 34)
+    try:
+        lab = sim.fof(0.2)
+        vel = sim.velocity()
+        cat = sim.fof_halos(lab, vel, min_members=20)
+        disp = sim.get_state()["disp"].cpu().numpy()
+        again = sim.fof_halos(lab, vel, min_members=20)
+        # capacity too small: an error that reports the number needed
+        with pytest.raises(ColaError):
+            sim.fof_halos(lab, vel, min_members=20, max_halos=3)
+        bad = lab.clone()
+        bad[7] = np_side ** 3
+        with pytest.raises(ColaError):
+            sim.fof_halos(bad, None, min_members=20)
+        none = sim.fof_halos(lab, None, min_members=10 ** 6)
+    finally:
+        sim.close()
+    lab = lab.cpu().numpy()
+    vel = vel.cpu().numpy()
+    roots, counts, com, vm = fof.halo_catalogue(disp, vel, lab, np_side, nm, 20)
+    say(f"[gpu]   {len(roots)} halos with >= 20 members")
+    assert len(roots) > 50
+    assert np.array_equal(cat["root"].cpu().numpy(), roots)
+    assert np.array_equal(cat["count"].cpu().numpy(), counts)
+    d = cat["pos"].cpu().numpy().astype(np.float64) - com
+    d -= nm * np.rint(d / nm)
+    assert np.abs(d).max() < 1e-4
+    assert np.abs(cat["vel"].cpu().numpy() - vm).max() < 1e-4 * np.abs(vm).max()
+    for k in ("root", "count", "pos", "vel"):
+        assert torch.equal(cat[k], again[k])
+    assert none["root"].numel() == 0
