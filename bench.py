@@ -125,7 +125,15 @@ def fof_leg(sim, reps=3):
     ms = (time.perf_counter() - t0) / reps * 1e3
     sizes = torch.bincount(lab.long())
     big = sizes >= 32
-    return {"ms_call": round(ms, 3), "b_frac": 0.2, "groups_ge_32": int(big.sum()),
+    vel = sim.velocity()
+    sim.fof_halos(lab, vel, min_members=32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cat = sim.fof_halos(lab, vel, min_members=32)
+    ms_cat = (time.perf_counter() - t0) / reps * 1e3
+    return {"ms_call": round(ms, 3), "ms_catalogue_call": round(ms_cat, 3), "halos": int(cat["root"].numel()),
+            "b_frac": 0.2, "groups_ge_32": int(big.sum()),
             "frac_in_groups_ge_32": round(float(sizes[big].sum()) / lab.numel(), 4),
             "largest": int(sizes.max())}
 
