@@ -70,7 +70,7 @@ def step_adjoint(state, a1: float, dbar1: np.ndarray, vbar1: np.ndarray):
     Psi1, Psi2.  Returns (dbar0, vbar0, psi1bar, psi2bar) where the Psi bars
     are this step's contributions.
     """
-    c = cosmo.step_coefficients(state.a_x, state.a_v, a1, state.om, state.n_lpt)
+    c = cosmo.step_coefficients(state.a_x, state.a_v, a1, state.om, state.n_lpt, state.d2_ode)
     K, I, al, D1, D2 = c["K"], c["I"], c["alpha"], c["D1"], c["D2"]
     vt = vbar1 + I * dbar1
     psi1bar = c["dD1"] * dbar1 - K * al * D1 * vt
@@ -181,10 +181,10 @@ def ic_adjoint(noise: np.ndarray, box: float, ktab, ptab, psi1bar, psi2bar) -> n
 
 
 def run_adjoint(noise, box, nmesh, ktab, ptab, edges, dbar_final, vbar_final=None,
-                a_init=0.02, om=0.27, n_lpt=-2.5):
+                a_init=0.02, om=0.27, n_lpt=-2.5, d2_ode=False):
     """Gradient of a loss on the final state w.r.t. the white noise (stores every step)."""
     from . import cola
-    st = cola.init_state(noise, box, nmesh, ktab, ptab, a_init, om, n_lpt)
+    st = cola.init_state(noise, box, nmesh, ktab, ptab, a_init, om, n_lpt, d2_ode)
     saved = []
     for a1 in edges[1:]:
         saved.append((st.d.copy(), st.v.copy(), st.a_x, st.a_v))
@@ -200,5 +200,5 @@ def run_adjoint(noise, box, nmesh, ktab, ptab, edges, dbar_final, vbar_final=Non
         p2b += q2
     # d0 = D1 Psi1 + D2 Psi2, v0 = 0
     p1b += cosmo.growth_D1(a_init, om) * dbar
-    p2b += cosmo.growth_D2(a_init, om) * dbar
+    p2b += cosmo.D2_of(a_init, om, d2_ode) * dbar
     return ic_adjoint(noise, box, ktab, ptab, p1b, p2b), st

@@ -56,12 +56,14 @@ def small_state(a=0.3, seed=4):
 
 def _copy(st):
     return cola.State(st.np_side, st.nmesh, st.box, st.om, st.n_lpt, st.q, st.d.copy(), st.v.copy(),
-                      st.psi1.copy(), st.psi2.copy(), st.a_x, st.a_v)
+                      st.psi1.copy(), st.psi2.copy(), st.a_x, st.a_v, st.d2_ode)
 
 
-@pytest.mark.parametrize("which", ["d", "v", "psi1", "psi2"])
-def test_step_adjoint_directional_derivative(which):
+@pytest.mark.parametrize("which,d2_ode", [("d", False), ("v", False), ("psi1", False), ("psi2", False),
+                                          ("psi2", True), ("d", True)])
+def test_step_adjoint_directional_derivative(which, d2_ode):
     st = small_state()
+    st.d2_ode = d2_ode          # D2 from its growth equation: the same adjoint with its coefficients
     a1 = st.a_x + 0.098
     rng = np.random.default_rng(3)
     dbar, vbar = rng.standard_normal((2,) + st.d.shape)
