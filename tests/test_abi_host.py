@@ -185,3 +185,25 @@ def test_host_step_scalars_at_n_lpt_zero():
     c = cosmo.step_coefficients(0.314, 0.265, 0.412, 0.27, 0.0)
     np.testing.assert_allclose(out[5:7], [c["K"], c["I"]], rtol=1e-12)
     assert np.isfinite(out).all()
+
+
+def test_new_entry_points_reject_a_null_context_without_a_device():
+    # argument checks come before any device access
+    lib = _lib.load()
+    n = C.c_size_t()
+    nh = C.c_int32()
+    e = (C.c_double * 3)(0.1, 0.2, 0.3)
+    out = [(C.c_double * 2)() for _ in range(4)]
+    cnt = (C.c_int64 * 2)()
+    calls = [
+        lib.cola_velocity(None, None, None, 0),
+        lib.cola_snapshot(None, 0.5, 0.4, None, None, None, 0),
+        lib.cola_density_of(None, None, None),
+        lib.cola_pk_of(None, None, 32, e, 2, out[0], out[1], cnt),
+        lib.cola_pk_velocity(None, 0, e, 2, out[0], out[1], out[2], out[3], cnt),
+        lib.cola_fof_workspace_bytes(None, C.byref(n)),
+        lib.cola_fof(None, 0.2, None, None, 0),
+        lib.cola_fof_halos_workspace_bytes(None, 32, C.byref(n)),
+        lib.cola_fof_halos(None, None, None, 32, 0, C.byref(nh), None, None, None, None, None, 0),
+    ]
+    assert all(c == _lib.COLA_EINVAL for c in calls), calls
