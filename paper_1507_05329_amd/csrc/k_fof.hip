@@ -13,7 +13,8 @@
 // Search: particles are counted into cells of the mean separation s = nm/np
 // (np^3 cells); b < s/2, so friends sit in the same or adjacent cells even
 // where rounding moves a particle across a cell face.  Cell lists come from a
-// counting sort (count, exclusive scan, scatter).
+// counting sort (count, exclusive scan, scatter); each particle scans its own
+// cell and half of the neighbouring ones.
 //
 // Union-find over the label array: parent[x] <= x always (a root is only ever
 // hooked under a smaller root, by compare-and-swap), so every parent chain
@@ -114,14 +115,17 @@ __global__ __launch_bounds__(256) void k_fof_link(const float* __restrict__ disp
   const int c0 = (int)(c / (uint32_t)(unp * unp)), c1 = (int)((c / (uint32_t)unp) % (uint32_t)unp),
             c2 = (int)(c % (uint32_t)unp);
   const float nmf = (float)nm;
-  for (int o = 0; o < 27; ++o) {
+  // half shell: the own cell (o = 13, pairs j > i) and the 13 offsets that
+  // follow (0, 0, 0) in lexicographic order; every unordered pair of adjacent
+  // cells is then visited from exactly one side (np >= 3)
+  for (int o = 13; o < 27; ++o) {
     const int a0 = (c0 + o / 9 - 1 + unp) % unp, a1 = (c1 + (o / 3) % 3 - 1 + unp) % unp,
               a2 = (c2 + o % 3 - 1 + unp) % unp;
     const uint32_t nc = ((uint32_t)a0 * (uint32_t)unp + (uint32_t)a1) * (uint32_t)unp + (uint32_t)a2;
     const uint32_t s0 = start[nc], s1 = start[nc + 1];
     for (uint32_t s = s0; s < s1; ++s) {
       const uint32_t j = sorted[s];
-      if (j <= i) continue;
+      if (o == 13 && j <= i) continue;
       float xj[3];
       fof_pos(disp, np3, j, np, nm, xj);
       float r2 = 0.f;
