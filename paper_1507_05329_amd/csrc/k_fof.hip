@@ -257,8 +257,9 @@ __global__ __launch_bounds__(256) void k_halo_final(const float* __restrict__ di
   for (int e = 0; e < 3; ++e) {
     double c = (double)xr[e] + (double)(long long)acc[(long)h * 6 + e] / kPosFix / n;
     c -= nm * floor(c / nm);
-    if (c >= nm) c -= nm;
-    pos[(long)e * stride + h] = (float)c;
+    float fc = (float)c;                 // rounding can reach nm itself
+    if (fc >= (float)nm) fc -= (float)nm;
+    pos[(long)e * stride + h] = fc;
     if (vout) vout[(long)e * stride + h] = (float)((double)(long long)acc[(long)h * 6 + 3 + e] / kVelFix / n);
   }
 }

@@ -159,7 +159,9 @@ def test_halo_catalogue_matches_oracle():
     assert len(roots) > 50
     assert np.array_equal(cat["root"].cpu().numpy(), roots)
     assert np.array_equal(cat["count"].cpu().numpy(), counts)
-    d = cat["pos"].cpu().numpy().astype(np.float64) - com
+    pos = cat["pos"].cpu().numpy()
+    assert (pos >= 0).all() and (pos < nm).all()
+    d = pos.astype(np.float64) - com
     d -= nm * np.rint(d / nm)
     assert np.abs(d).max() < 1e-4
     assert np.abs(cat["vel"].cpu().numpy() - vm).max() < 1e-4 * np.abs(vm).max()
