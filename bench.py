@@ -318,8 +318,8 @@ def main():
         print(json.dumps({"copy_mib": args.copy_calibration_mib, "launches": 3}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(--gpus must be 1)", file=sys.stderr)
+        print("bench.py: the library runs one context per GPU and this benchmark measures one GPU; "
+              "multi-GPU runs are not supported (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if not (1 <= args.steps <= 10) or not (0 <= args.warmup <= 10):
         print("bench.py: --steps and --warmup must lie in [1, 10] and [0, 10] "
