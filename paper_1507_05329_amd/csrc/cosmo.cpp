@@ -136,21 +136,34 @@ void growth_ode_raw(double a_end, double om, double y[4]) {
   }
 }
 
+// Unnormalised D1 at a = 1 for the last Omega_m this thread asked for (the
+// normalisation of every ODE value; the same integration, done once).
+double growth_ode_norm(double om) {
+  thread_local double last_om = -1.0, last_n1 = 0.0;
+  if (om != last_om) {
+    double y1[4];
+    growth_ode_raw(1.0, om, y1);
+    last_om = om;
+    last_n1 = y1[0];
+  }
+  return last_n1;
+}
+
 }  // namespace
 
 // D2 from its growth equation, normalised with D1(1) = 1 (D2 scales as D1^2).
 double growth_D2_ode(double a, double om) {
-  double y[4], y1[4];
+  double y[4];
   growth_ode_raw(a, om, y);
-  growth_ode_raw(1.0, om, y1);
-  return y[2] / (y1[0] * y1[0]);
+  const double n1 = growth_ode_norm(om);
+  return y[2] / (n1 * n1);
 }
 
 double growth_D2_ode_prime(double a, double om) {
-  double y[4], y1[4];
+  double y[4];
   growth_ode_raw(a, om, y);
-  growth_ode_raw(1.0, om, y1);
-  return y[3] / a / (y1[0] * y1[0]);
+  const double n1 = growth_ode_norm(om);
+  return y[3] / a / (n1 * n1);
 }
 
 double D2_of(const cola_params* p, double a) {
