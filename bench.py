@@ -1,27 +1,38 @@
 """Throughput of the COLA PM step on one MI355X.
 
-Workload: 256^3 particles, 768^3 PM mesh (3x the particle grid), 600 Mpc/h
-box, flat LCDM Omega_m = 0.27, BBKS P(k) with sigma_8 = 0.8, Gaussian
-white-noise initial conditions (GPU Philox, seed 2) displaced by 2LPT,
-10 COLA steps uniform in a from 0.02 to 1.  A "step" is one cola_step: tile
-sort, deterministic CIC deposit, r2c FFT, Green's function x ik and the
-inverse FFTs of the three force components, CIC readout fused with the
-kick/drift.
+Workload (default): 1024^3 particles, 2048^3 PM mesh (2x the particle grid),
+1200 Mpc/h box, flat LCDM Omega_m = 0.27, BBKS P(k) with sigma_8 = 0.8,
+Gaussian white-noise initial conditions (GPU Philox, seed 5) displaced by
+2LPT, 10 COLA steps uniform in a from 0.02 to 1.  A "step" is one
+cola_step: tile sort, deterministic CIC deposit, r2c FFT, Green's function
+x ik and the inverse FFTs of the three force components, CIC readout fused
+with the kick/drift.  ``--config production`` selects 256^3 / 768^3 / 600
+Mpc/h instead.
 
-Timed region: K consecutive steps of the 10-step schedule (K <= 10) after a
-fresh initial condition, inputs resident in HBM, bracketed by
-torch.cuda.synchronize().  Then, each in its own pass: the adjoint of the
-same K steps (fwd_adjoint: each adjoint step recomputes its forces;
-fwd_adjoint_kept: the forward steps store them, one force slot per step,
-where the slots fit in HBM), the 96-mock ensemble batched and one by one
-(batched), and the library's per-stage HIP event timers, which give the
-dominant kernel's achieved bandwidth against the 8 TB/s HBM peak (roofline;
-`traffic` comes from the committed counter summary while its kernel source
-is unchanged), followed by the particle velocities at the final position
-time with their redshift-space displacement (velocity: whole call with its
-force pipeline, and the velocity kernel against its algorithmic bytes), the
-snapshot and velocity-spectra calls, and the friends-of-friends groups (fof).  The FP64 CPU oracle is timed on one step of the same
-workload on the host cores (cpu_baseline).
+Timed region: K steps of the 10-step schedule, cycled: every pass of up to
+10 steps starts from fresh initial conditions (cola_init_2lpt, outside the
+timer), inputs resident in HBM, each pass bracketed by
+torch.cuda.synchronize(); the timed passes are summed.  W untimed warm-up
+steps come first, in the same cycle.
+
+Then, each in its own pass:
+* fwd_adjoint -- the gradient of the final P(k) (40 log bins, seeded
+  cotangents) with respect to the white noise.  Large runs use the lean
+  driver (autograd.pk_noise_gradient: one position buffer, step starts
+  recomputed from the initial conditions); smaller ones reverse K steps from
+  stored starts, and also store the forces instead of recomputing them
+  (fwd_adjoint_kept) where the slots fit in HBM.
+* roofline -- the library's per-stage HIP event timers (on the library's
+  stream) over the 10-step schedule give each stage's average launch time;
+  the dominant kernel's algorithmic bytes over that time, against 8 TB/s.
+  ``traffic`` comes from the committed rocprofv3 counter summary of this
+  workload while its kernel sources are unchanged.
+* production -- with the large workload, the same measurements at
+  256^3 / 768^3 (velocity, snapshot, velocity spectra, friends-of-friends
+  legs included).
+* batched -- the 96-mock ensemble batched and one by one.
+* cpu_baseline -- one FP64 oracle step on a sub-volume of the workload at
+  its resolution (host cores).
 
 Prints one JSON line.
 """
@@ -38,6 +49,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# host memory the full FP64 oracle run of a workload needs (particles, two
+# meshes and temporaries in FP64), for the P(k) parity note
+ORACLE_HOST_BYTES_PER_NODE = 40.0
 
 
 def stage_bytes(np_side: int, nm: int) -> dict:
@@ -59,10 +73,6 @@ def stage_bytes(np_side: int, nm: int) -> dict:
     }
 
 
-# Counter-measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# scaled by a plain copy of known size) for the production workload, with the
-# sha256 of the kernel sources they were taken on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256p_768m.txt")
 STAGE_SOURCES = {
     "sort": ["k_sort.hip"], "deposit": ["k_deposit.hip"], "fft_z": ["k_fft.hip"],
     "fft_y": ["k_fft.hip"], "fft_x_green": ["k_fft.hip"], "ifft_y": ["k_fft.hip"],
@@ -70,11 +80,127 @@ STAGE_SOURCES = {
 }
 
 
+def traffic_file(np_side, nm):
+    """Committed counter summary (rocprofv3 FETCH_SIZE / WRITE_SIZE) of a workload."""
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{np_side}p_{nm}m.txt")
+
+
+def measured_traffic(stage, np_side, nm):
+    """HBM bytes per launch of a stage from the committed counter summary, or
+    None when there is none for this workload or the kernel source changed."""
+    import hashlib
+    path = traffic_file(np_side, nm)
+    if not os.path.exists(path):
+        return None
+    sha, traffic = {}, {}
+    for line in open(path):
+        f = line.split()
+        if len(f) == 3 and f[0] == "sha256":
+            sha[f[1]] = f[2]
+        elif len(f) >= 3 and f[0] == "traffic":
+            traffic[f[1]] = int(f[2])
+    if stage not in traffic:
+        return None
+    csrc = os.path.join(ROOT, "paper_1507_05329_amd", "csrc")
+    for name in STAGE_SOURCES.get(stage, []) + ["cola_device.h"]:
+        h = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
+        if sha.get(name) != h:
+            return None
+    return traffic[stage]
+
+
+def host_info():
+    """CPU model, host RAM and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                ram = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "ram_GB": None if ram is None else round(ram / 1e9, 1),
+            "cores": len(os.sched_getaffinity(0))}
+
+
+def cycled_steps(sim, cfg, table, e, nsteps):
+    """Runs nsteps steps of the cfg.nstep-step schedule, cycled: each pass of
+    up to cfg.nstep steps starts from fresh initial conditions (untimed).
+    Returns the summed wall time of the passes (device synchronised)."""
+    import torch
+    total = 0.0
+    done = 0
+    while done < nsteps:
+        sim.init_2lpt(cfg.seed, *table)
+        n = min(cfg.nstep, nsteps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            sim.step(e[i], e[i + 1])
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+        done += n
+    return total
+
+
+def stage_pass(cfg, table, e, dev, with_outputs):
+    """Per-stage averages over the whole schedule from the library's HIP event
+    timers; optionally the velocity / snapshot / spectra / FoF legs at the end."""
+    from paper_1507_05329_amd import _lib
+    from paper_1507_05329_amd.sim import ColaSim
+    simt = ColaSim(cfg.np_side, cfg.nmesh, cfg.box, omega_m=cfg.omega_m, n_lpt=cfg.n_lpt,
+                   a_init=cfg.a_init, device=dev, flags=_lib.COLA_F_STAGE_TIMERS)
+    try:
+        simt.init_2lpt(cfg.seed, *table)
+        simt.synchronize()
+        simt.stage_times()
+        for i in range(cfg.nstep):
+            simt.step(e[i], e[i + 1])
+        st = simt.stage_times()
+        extra = {}
+        if with_outputs:
+            extra["velocity"] = velocity_leg(simt, cfg)
+            extra["fof"] = fof_leg(simt)
+    finally:
+        simt.close()
+    sb = stage_bytes(cfg.np_side, cfg.nmesh)
+    stages = {}
+    for name, (ms, cnt) in st.items():
+        if cnt == 0 or name not in sb:
+            continue
+        avg = ms / cnt
+        stages[name] = {"ms": round(avg, 4), "launches": cnt,
+                        "GB/s": round(sb[name] / (avg * 1e-3) / 1e9, 1)}
+    return stages, extra
+
+
+def roofline_of(stages, cfg, ms_step):
+    sb = stage_bytes(cfg.np_side, cfg.nmesh)
+    dom = max(stages, key=lambda n: stages[n]["ms"])
+    dom_gbs = sb[dom] / (stages[dom]["ms"] * 1e-3) / 1e9
+    step_bytes = sum(sb.values())
+    return {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, cfg.np_side, cfg.nmesh),
+            "bytes_alg": sb[dom], "ms_per_launch": stages[dom]["ms"],
+            "step_bytes_alg": step_bytes,
+            "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def velocity_leg(sim, cfg, reps=3):
     """cola_velocity at the final state (a_v != a_x, so the call runs the force
     pipeline, then the velocity kernel with a redshift-space output): whole-call
     time and the kernel's own time from the stage timers (HIP events on the
     library's stream) against its algorithmic bytes."""
+    import numpy as np
     import torch
     vel, sdisp = sim.particles(), sim.particles()
     sim.velocity(vel, rsd_axis=2, sdisp=sdisp)
@@ -89,7 +215,6 @@ def velocity_leg(sim, cfg, reps=3):
     ms_k = ms / max(cnt, 1)
     n_p, M = cfg.np_side ** 3, cfg.nmesh ** 3
     nbytes = 72 * n_p + 12 * min(M, 8 * n_p)   # state reads 48, outputs 24, CIC gathers
-    # a snapshot half way through a following step, and the velocity spectra
     st = sim.get_state(which=())
     a1 = st["a_x"] + 0.098
     sim.snapshot(a1, st["a_x"] + 0.049)
@@ -99,7 +224,6 @@ def velocity_leg(sim, cfg, reps=3):
         sim.snapshot(a1, st["a_x"] + 0.049)
     torch.cuda.synchronize()
     ms_snap = (time.perf_counter() - t0) / reps * 1e3
-    import numpy as np
     edges = np.linspace(2 * np.pi / cfg.box, np.pi * cfg.nmesh / cfg.box, 41)
     sim.pk_velocity(edges, axis=2)
     t0 = time.perf_counter()
@@ -138,34 +262,11 @@ def fof_leg(sim, reps=3):
             "largest": int(sizes.max())}
 
 
-def measured_traffic(stage, workload):
-    """HBM bytes per launch of a stage from the committed counter summary, or
-    None when there is none for this workload or the kernel source changed."""
-    import hashlib
-    if workload != "production" or not os.path.exists(TRAFFIC_FILE):
-        return None
-    sha, traffic = {}, {}
-    for line in open(TRAFFIC_FILE):
-        f = line.split()
-        if len(f) == 3 and f[0] == "sha256":
-            sha[f[1]] = f[2]
-        elif len(f) >= 3 and f[0] == "traffic":
-            traffic[f[1]] = int(f[2])
-    if stage not in traffic:
-        return None
-    csrc = os.path.join(ROOT, "paper_1507_05329_amd", "csrc")
-    for name in STAGE_SOURCES.get(stage, []) + ["cola_device.h"]:
-        h = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
-        if sha.get(name) != h:
-            return None
-    return traffic[stage]
-
-
 def batch_leg(steps, table, dev):
     """The 96-mock uneven ensemble (32 x 48^3/96^3, 32 x 64^3/128^3,
     32 x 96^3/192^3 particles/mesh, boxes 150/200/300 Mpc/h, distinct seeds):
-    K batched steps (one graph per step) against the same mocks stepped one
-    by one with plain contexts."""
+    the 10-step run batched (one graph per step) against the same mocks
+    stepped one by one with plain contexts."""
     import torch
     from paper_1507_05329_amd.inputs import batch_configs, step_edges
     from paper_1507_05329_amd.sim import ColaBatch, ColaSim
@@ -215,12 +316,13 @@ def batch_leg(steps, table, dev):
 
 
 def adjoint_leg(sim, cfg, table, e, steps):
-    """Average adjoint step (ms): reverse the K steps from their stored starts."""
+    """Average adjoint step (ms): reverse the first `steps` steps from their
+    stored starts (displacements only)."""
     import torch
     sim.init_2lpt(cfg.seed, *table)
     starts = []
     for i in range(steps):
-        st = sim.get_state()
+        st = sim.get_state(("disp",))
         starts.append((st["disp"], st["a_v"]))
         sim.step(e[i], e[i + 1])
     dbar = torch.randn_like(starts[0][0])
@@ -236,8 +338,8 @@ def adjoint_leg(sim, cfg, table, e, steps):
 
 
 def kept_leg(sim, cfg, table, e, steps):
-    """Store instead of recompute: the K forward steps keep their force
-    meshes (cola_step_keep, one slot per step) and the adjoint reads them
+    """Store instead of recompute: the forward steps keep their force meshes
+    (cola_step_keep, one slot per step) and the adjoint reads them
     (cola_step_adjoint_kept).  Returns (ms per forward step, ms per adjoint
     step, GB of slots), or None when the slots do not fit in free HBM."""
     import torch
@@ -252,7 +354,7 @@ def kept_leg(sim, cfg, table, e, steps):
     torch.cuda.synchronize()
     t_fwd = 0.0
     for i in range(steps):
-        st = sim.get_state()
+        st = sim.get_state(("disp",))
         starts.append((st["disp"], st["a_v"]))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -276,37 +378,149 @@ def kept_leg(sim, cfg, table, e, steps):
     return t_fwd / steps * 1e3, t_adj / steps * 1e3, gb
 
 
-def cpu_baseline(cfg, table, seed):
-    """One oracle step of the same workload on the host (FP64, NumPy/SciPy)."""
+def lean_gradient_leg(sim, cfg, table, e, ms_step):
+    """The gradient of sum_b c_b P_b (40 log bins from 2 pi / L to the mesh
+    Nyquist, c_b ~ N(0, 1) seed 5) with respect to the white noise through the
+    lean driver: forward run, then for every step (last first) its start
+    recomputed from the initial conditions and its adjoint."""
+    import numpy as np
+    import torch
+    from paper_1507_05329_amd.autograd import pk_noise_gradient
+    from paper_1507_05329_amd.inputs import seeded_normal
+    kf, kny = 2 * np.pi / cfg.box, np.pi * cfg.nmesh / cfg.box
+    kedges = np.exp(np.linspace(np.log(kf), np.log(kny), 41))
+    cbar = seeded_normal(5, (40,)).astype(np.float64)
+    noise = sim.noise(cfg.seed)
+    times = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, _ = pk_noise_gradient(sim, noise, table[0], table[1], e, kedges, cbar, times=times)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    finite = bool(torch.isfinite(g).all().item())
+    del g, noise
+    torch.cuda.empty_cache()
+    n = cfg.nstep
+    ms_adj = times["adjoint"] / n * 1e3
+    backward = total - times["forward"]
+    return {"value": cfg.n_particles / ((ms_step + backward / n * 1e3) * 1e-3), "unit": "particle-updates/s",
+            "ms_adjoint_step": round(ms_adj, 3), "adjoint_over_forward": round(ms_adj / ms_step, 3),
+            "ms_backward_per_step_amortised": round(backward / n * 1e3, 3),
+            "s_gradient_total": round(total, 3), "s_forward": round(times["forward"], 3),
+            "s_recompute": round(times["recompute"], 3), "recomputed_steps": times["recomputed_steps"],
+            "gradient_finite": finite,
+            "note": "lean driver: step starts recomputed from the initial conditions, no checkpoints; "
+                    "value = particles / (forward step + amortised backward per step)"}
+
+
+def workload_block(cfg, steps, warmup, dev, with_adjoint, with_outputs, lean):
+    """Forward throughput, adjoint and per-stage timing of one workload."""
+    import torch
+    from paper_1507_05329_amd.inputs import bbks_table, step_edges
+    from paper_1507_05329_amd.sim import ColaSim
+    table = bbks_table(cfg.omega_m, cfg.h, cfg.n_s, cfg.sigma8)
+    e = step_edges(cfg.a_init, cfg.a_final, cfg.nstep)
+    sim = ColaSim(cfg.np_side, cfg.nmesh, cfg.box, omega_m=cfg.omega_m, n_lpt=cfg.n_lpt,
+                  a_init=cfg.a_init, device=dev)
+    out = {}
+    try:
+        if warmup:
+            cycled_steps(sim, cfg, table, e, warmup)
+        dt = cycled_steps(sim, cfg, table, e, steps)
+        ms_step = dt / steps * 1e3
+        out.update(value=cfg.n_particles * steps / dt, ms_per_step=ms_step)
+        if with_adjoint:
+            if lean:
+                out["fwd_adjoint"] = lean_gradient_leg(sim, cfg, table, e, ms_step)
+            else:
+                n = cfg.nstep
+                ms_adj = adjoint_leg(sim, cfg, table, e, n)
+                out["fwd_adjoint"] = {"value": cfg.n_particles / ((ms_step + ms_adj) * 1e-3),
+                                      "unit": "particle-updates/s", "ms_adjoint_step": ms_adj,
+                                      "adjoint_over_forward": ms_adj / ms_step,
+                                      "note": f"the {n} adjoint steps from stored step starts"}
+                kept = kept_leg(sim, cfg, table, e, n)
+                out["fwd_adjoint_kept"] = None if kept is None else {
+                    "value": cfg.n_particles / ((kept[0] + kept[1]) * 1e-3), "unit": "particle-updates/s",
+                    "ms_forward_step": kept[0], "ms_adjoint_step": kept[1], "slots_GB": kept[2],
+                    "note": "forward steps keep their force meshes (one slot per step); the adjoint reads them"}
+    finally:
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    stages, extra = stage_pass(cfg, table, e, dev, with_outputs)
+    torch.cuda.empty_cache()
+    out["stages"] = stages
+    out["roofline"] = roofline_of(stages, cfg, out["ms_per_step"])
+    out.update(extra)
+    return out
+
+
+def cpu_baseline(cfg):
+    """One FP64 oracle COLA step (NumPy/SciPy) on the host: the workload
+    itself when it has at most 256^3 particles, else a sub-volume at the
+    same particle and mesh spacing (256^3 particles, box scaled down)."""
     from oracle import cola
-    from paper_1507_05329_amd.inputs import white_noise, step_edges
-    cores = len(os.sched_getaffinity(0))
-    w = white_noise(seed, cfg.np_side)
-    st = cola.init_state(w, cfg.box, cfg.nmesh, *table)
-    e = step_edges()
+    from paper_1507_05329_amd.inputs import bbks_table, step_edges, white_noise
+    table = bbks_table(cfg.omega_m, cfg.h, cfg.n_s, cfg.sigma8)
+    n, m, box = cfg.np_side, cfg.nmesh, cfg.box
+    if n > 256:
+        f = n // 256
+        n, m, box = n // f, m // f, box / f
+    w = white_noise(cfg.seed, n)
+    st = cola.init_state(w, box, m, *table)
+    e = step_edges(cfg.a_init, cfg.a_final, cfg.nstep)
     t0 = time.perf_counter()
     cola.step(st, e[1])
     dt = time.perf_counter() - t0
-    return {"value": cfg.n_particles / dt, "unit": "particle-updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"one FP64 oracle COLA step (a {e[0]:.3f}->{e[1]:.3f}) of the full "
-                      f"{cfg.np_side}^3/{cfg.nmesh}^3 workload, {dt:.1f} s, scipy.fft workers={cores}"}
+    info = host_info()
+    sub = "" if (n, m) == (cfg.np_side, cfg.nmesh) else \
+        f" (a 1/{(cfg.np_side // n) ** 3} sub-volume of the {cfg.np_side}^3/{cfg.nmesh}^3 workload at its " \
+        f"particle and mesh spacing)"
+    return {"value": n ** 3 / dt, "unit": "particle-updates/s", "cores": info["cores"],
+            "kind": "oracle", "cpu_model": info["cpu_model"], "ram_GB": info["ram_GB"],
+            "config": {"np": n, "nmesh": m, "box": box},
+            "sample": f"one FP64 oracle COLA step (a {e[0]:.3f}->{e[1]:.3f}) of {n}^3 particles on a "
+                      f"{m}^3 mesh, box {box:g} Mpc/h{sub}: {dt:.1f} s, scipy.fft workers={info['cores']}"}
 
 
-def main():
+def pk_parity_note(cfg):
+    need = ORACLE_HOST_BYTES_PER_NODE * cfg.nmesh ** 3
+    ram = host_info()["ram_GB"]
+    if ram is not None and need / 1e9 < 0.8 * ram:
+        return None
+    return (f"final P(k) parity with the FP64 oracle unverified at this size: the full oracle run needs "
+            f"about {need / 1e9:.0f} GB of host memory, this host has {ram} GB; the same kernels are "
+            f"parity-tested at every other length and the sampled-node / growth checks run here")
+
+
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="production")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="large", choices=["small", "production", "diff", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-ensemble leg")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
-    ap.add_argument("--no-velocity", action="store_true", help="skip the velocity / redshift-space leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint legs")
+    ap.add_argument("--no-velocity", action="store_true", help="skip the velocity / redshift-space / FoF legs")
+    ap.add_argument("--no-production", action="store_true",
+                    help="with the large workload, skip the secondary 256^3/768^3 block")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (for HBM counter "
                          "calibration under rocprofv3) and exit")
-    args = ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this benchmark measures one GPU; --gpus {args.gpus} is not supported "
+              "(the library runs one context per GPU and has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("bench.py: --steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration_mib:
         import torch
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -317,115 +531,60 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_mib": args.copy_calibration_mib, "launches": 3}))
         return
-    if args.gpus != 1:
-        print("bench.py: the library runs one context per GPU and this benchmark measures one GPU; "
-              "multi-GPU runs are not supported (--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
-    if not (1 <= args.steps <= 10) or not (0 <= args.warmup <= 10):
-        print("bench.py: --steps and --warmup must lie in [1, 10] and [0, 10] "
-              "(the workload is a 10-step run)", file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1507_05329_amd import _lib
-    from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges
-    from paper_1507_05329_amd.sim import ColaSim
+    from paper_1507_05329_amd.inputs import CONFIGS, bbks_table
 
+    _lib.load()
     cfg = CONFIGS[args.config]
-    table = bbks_table(cfg.omega_m, cfg.h, cfg.n_s, cfg.sigma8)
-    e = step_edges(cfg.a_init, cfg.a_final, cfg.nstep)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    large = cfg.n_particles > 256 ** 3
 
-    sim = ColaSim(cfg.np_side, cfg.nmesh, cfg.box, omega_m=cfg.omega_m, n_lpt=cfg.n_lpt,
-                  a_init=cfg.a_init, device=dev)
-    # warm-up (also first-touch of the workspace and code objects)
-    sim.init_2lpt(cfg.seed, *table)
-    for i in range(args.warmup):
-        sim.step(e[i], e[i + 1])
-    sim.init_2lpt(cfg.seed, *table)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        sim.step(e[i], e[i + 1])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
-    value = cfg.n_particles * args.steps / dt
-
-    # adjoint: reverse the same K steps from their stored start positions
-    ms_adj = kept = None
-    if not args.no_adjoint:
-        ms_adj = adjoint_leg(sim, cfg, table, e, args.steps)
-        kept = kept_leg(sim, cfg, table, e, args.steps)
-    sim.close()
-    del sim
-
-    # per-stage timing pass (HIP events on the library's stream)
-    simt = ColaSim(cfg.np_side, cfg.nmesh, cfg.box, omega_m=cfg.omega_m, n_lpt=cfg.n_lpt,
-                   a_init=cfg.a_init, device=dev, flags=_lib.COLA_F_STAGE_TIMERS)
-    simt.init_2lpt(cfg.seed, *table)
-    simt.step(e[0], e[1])
-    simt.stage_times()
-    for i in range(1, args.steps if args.steps > 1 else 2):
-        simt.step(e[i], e[i + 1])
-    st = simt.stage_times()
-    snapshot = None if args.no_velocity else velocity_leg(simt, cfg)
-    halos = None if args.no_velocity else fof_leg(simt)
-    simt.close()
-    sb = stage_bytes(cfg.np_side, cfg.nmesh)
-    stages = {}
-    for name, (ms, cnt) in st.items():
-        if cnt == 0:
-            continue
-        avg = ms / cnt
-        stages[name] = {"ms": round(avg, 4), "GB/s": round(sb[name] / (avg * 1e-3) / 1e9, 1)}
-    dom = max(stages, key=lambda n: stages[n]["ms"])
-    dom_gbs = sb[dom] / (stages[dom]["ms"] * 1e-3) / 1e9
-    step_bytes = sum(sb.values())
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, args.config),
-                "bytes_alg": sb[dom],
-                "step_bytes_alg": step_bytes,
-                "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    main_block = workload_block(cfg, args.steps, args.warmup, dev, not args.no_adjoint,
+                                with_outputs=not large and not args.no_velocity, lean=large)
+    production = None
+    if large and not args.no_production:
+        pcfg = CONFIGS["production"]
+        production = workload_block(pcfg, min(args.steps, pcfg.nstep), min(args.warmup, 3), dev,
+                                    not args.no_adjoint, with_outputs=not args.no_velocity, lean=False)
+        production["config"] = {"workload": pcfg.name, "np": pcfg.np_side, "nmesh": pcfg.nmesh,
+                                "box": pcfg.box}
+        production["steps"] = min(args.steps, pcfg.nstep)
 
     batched = None
     if not args.no_batch:
-        batched = batch_leg(args.steps, bbks_table(), dev)
+        batched = batch_leg(10, bbks_table(), dev)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, table, cfg.seed)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
 
     out = {
-        "metric": "particle-updates/s per COLA PM step (fwd; fwd+adjoint in fwd_adjoint)",
-        "value": value,
+        "metric": "particle-updates/s per COLA PM step (fwd; fwd+adjoint in fwd_adjoint) + % HBM roofline",
+        "value": main_block["value"],
         "unit": "particle-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": main_block["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (BBKS Gaussian random field, GPU Philox seed %d)" % cfg.seed,
         "config": {"workload": cfg.name, "np": cfg.np_side, "nmesh": cfg.nmesh, "box": cfg.box,
-                   "nstep": cfg.nstep, "a": [cfg.a_init, cfg.a_final]},
-        "fwd_adjoint": None if ms_adj is None else {
-            "value": cfg.n_particles / ((ms_step + ms_adj) * 1e-3), "unit": "particle-updates/s",
-            "ms_adjoint_step": ms_adj, "adjoint_over_forward": ms_adj / ms_step},
-        "fwd_adjoint_kept": None if kept is None else {
-            "value": cfg.n_particles / ((kept[0] + kept[1]) * 1e-3), "unit": "particle-updates/s",
-            "ms_forward_step": kept[0], "ms_adjoint_step": kept[1], "slots_GB": kept[2],
-            "note": "forward steps keep their force meshes (one slot per step); the adjoint reads them"},
+                   "nstep": cfg.nstep, "a": [cfg.a_init, cfg.a_final],
+                   "schedule": "the 10-step schedule cycled; fresh initial conditions (untimed) "
+                               "before every pass of 10 steps"},
+        "fwd_adjoint": main_block.get("fwd_adjoint"),
+        "fwd_adjoint_kept": main_block.get("fwd_adjoint_kept"),
+        "stages": main_block["stages"],
+        "roofline": main_block["roofline"],
+        "pk_parity": pk_parity_note(cfg),
+        "velocity": main_block.get("velocity"),
+        "fof": main_block.get("fof"),
+        "production": production,
         "batched": batched,
-        "velocity": snapshot,
-        "fof": halos,
-        "stages": stages,
-        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

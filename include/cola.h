@@ -70,7 +70,8 @@ typedef struct cola_ctx cola_ctx;
 /* Run parameters.  Cosmology is flat LCDM, Omega_Lambda = 1 - omega_m
  * (Sec. 1).  np and nmesh must be one of the compiled FFT sizes
  * {16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048}
- * (COLA_EUNSUPPORTED otherwise), with nmesh >= 32 and nmesh >= np. */
+ * (COLA_EUNSUPPORTED otherwise), with nmesh >= 32 and nmesh >= np, and at
+ * most 2^30 particles (np <= 1024; COLA_EUNSUPPORTED otherwise). */
 typedef struct cola_params {
   int32_t np;              /* particles per side                                   */
   int32_t nmesh;           /* PM mesh per side                                     */
@@ -232,6 +233,17 @@ int cola_fof_halos(cola_ctx* ctx, const int32_t* dev_labels, const float* dev_ve
 /* PM force F (mesh units) at the current positions, 3 * np^3 float32 into
  * dev_force; no state change (the force of Sec. 2.2 as used by cola_step). */
 int cola_force(cola_ctx* ctx, float* dev_force);
+
+/* The PM force meshes of a given density contrast (Sec. 2.2: F = -grad phi,
+ * laplacian phi = (3/2) Omega_m a^-1 delta; the Green's function and
+ * gradient readings of cola_step): g_d = IDFT[i k_d alpha DFT[delta] / k^2],
+ * k = 0 -> 0, k_d zeroed on the Nyquist plane of axis d, in mesh units (the
+ * meshes cola_step reads the force from).  dev_delta: nmesh^3 float32, C
+ * order.  dev_g0, dev_g1, dev_g2: nmesh^3 float32 each, C order, for the
+ * x, y, z components; any may be NULL (not written).  Uses the context's
+ * meshes as scratch (no state change). */
+int cola_pm_gradient(cola_ctx* ctx, double a, const float* dev_delta, float* dev_g0, float* dev_g1,
+                     float* dev_g2);
 
 /* Canonical particle velocity v = a^2 dx/dt at the position time a_x (Koda
  * et al. 2015, Sec. 2.1: residual velocity plus the time derivative of the

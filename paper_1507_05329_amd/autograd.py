@@ -111,14 +111,27 @@ class ColaPowerSpectrum(torch.autograd.Function):
         return wbar, None, None, None, None, None, None, None, None
 
 
-def pk_noise_gradient(sim: ColaSim, noise, k, pk, edges, kedges, cbar, ngrid=None, every=None):
+def pk_noise_gradient(sim: ColaSim, noise, k, pk, edges, kedges, cbar, ngrid=None, every=None,
+                      times=None):
     """d(sum_b cbar_b P_b) / d(noise) for P(k) of the final particles, in the
     least device memory: one position buffer, the four cotangent arrays and
     a (displacement, velocity) checkpoint every ``every`` steps (None: none;
     the initial conditions are rebuilt from the noise instead).  Each step's
     start positions are recomputed from the nearest earlier checkpoint; the
     step is deterministic, so they equal the forward's bit for bit.
+    ``times``: a dict that receives the wall seconds of the forward run
+    ("forward"), of the recomputed steps ("recompute") and of the adjoint
+    steps ("adjoint"), the device synchronised around each phase.
     Returns (gradient, P(k) of the forward run)."""
+    import time
+
+    def mark():
+        if times is not None:
+            torch.cuda.synchronize(sim.device)
+        return time.perf_counter()
+
+    if times is not None:
+        times.update(forward=0.0, recompute=0.0, adjoint=0.0, recomputed_steps=0)
     kedges = np.asarray(kedges, np.float64)
     nstep = len(edges) - 1
     every = nstep if every is None else max(1, int(every))
@@ -136,12 +149,15 @@ def pk_noise_gradient(sim: ColaSim, noise, k, pk, edges, kedges, cbar, ngrid=Non
         for i in range(base, i0):
             sim.step(edges[i], edges[i + 1])
 
+    t0 = mark()
     sim.init_from_noise(noise, k, pk)
     for i in range(nstep):
         if i > 0 and i % every == 0:
             st = sim.get_state(("disp", "vres"))
             ckpt[i] = (st["disp"], st["vres"], st["a_x"], st["a_v"])
         sim.step(edges[i], edges[i + 1])
+    if times is not None:
+        times["forward"] = mark() - t0
     _, p, n = sim.pk(kedges, ngrid)
     pos = sim.get_state(("disp",))["disp"]
     dbar = torch.zeros_like(pos)
@@ -150,9 +166,16 @@ def pk_noise_gradient(sim: ColaSim, noise, k, pk, edges, kedges, cbar, ngrid=Non
     p1b = torch.zeros_like(dbar)
     p2b = torch.zeros_like(dbar)
     for i in reversed(range(nstep)):
+        t0 = mark()
         restart(i)
         st = sim.get_state(("disp",), out={"disp": pos})
+        t1 = mark()
         sim.step_adjoint(edges[i], edges[i + 1], st["a_v"], pos, dbar, vbar, p1b, p2b)
+        if times is not None:
+            t2 = mark()
+            times["recompute"] += t1 - t0
+            times["adjoint"] += t2 - t1
+            times["recomputed_steps"] += i
     del pos, vbar
     return sim.init_adjoint(noise, dbar, p1b, p2b), np.where(n > 0, p, 0.0)
 

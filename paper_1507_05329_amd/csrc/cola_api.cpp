@@ -70,7 +70,8 @@ int validate(const cola_params* p) {
     return COLA_EINVAL;
   if (!fft_size_supported(p->np)) return COLA_EUNSUPPORTED;
   if (p->nmesh % 8 != 0 || !fft_size_supported(p->nmesh) || p->nmesh < p->np) return COLA_EUNSUPPORTED;
-  if ((long)p->np * p->np * p->np >= (1L << 32) - 1) return COLA_EUNSUPPORTED;
+  // particle ids fill 30 bits of the deposit's sort keys: at most 2^30 particles
+  if ((long)p->np * p->np * p->np > (1L << 30)) return COLA_EUNSUPPORTED;
   return COLA_OK;
 }
 
@@ -192,10 +193,9 @@ double green_scale(int nm, double alpha) { return alpha * nm / (2.0 * kPi) / ((d
 // y pass turns the second into the y and z components (k_y and k_z are
 // constant along x, so phi needs only two inverse x transforms).  The Green
 // scale is read from the device coefficients c->coef (set by set_coef).
-void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 0) {
+// The spectral part alone: c->mesh[0] holds delta on entry (padded r2c layout).
+void fft_forces(cola_ctx* c, int nmock = 1, long mstride = 0) {
   const int nm = c->p.nmesh;
-  const long rs = 2 * padded_cols(nm);
-  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1, disp, nmock, mstride);
   {
     StageTimer t(c, COLA_STAGE_FFT_Z);
     fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream, nmock, mstride);
@@ -228,6 +228,13 @@ void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 
     StageTimer t(c, COLA_STAGE_IFFT_Z);
     fft_c2r_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream, nmock, mstride);
   }
+}
+
+void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 0) {
+  const int nm = c->p.nmesh;
+  const long rs = 2 * padded_cols(nm);
+  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1, disp, nmock, mstride);
+  fft_forces(c, nmock, mstride);
 }
 
 // The whole PM step on the device (no host decisions, no host reads): the
@@ -509,6 +516,23 @@ int cola_force(cola_ctx* c, float* out) {
                             reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
                             c->psi2, c->p.np, c->p.nmesh, c->coef, out, c->stream);
   LAUNCH_CHECK(c, "cola_force");
+  return COLA_OK;
+}
+
+int cola_pm_gradient(cola_ctx* c, double a, const float* delta, float* g0, float* g1, float* g2) {
+  if (!c || !delta) return fail(c, COLA_EINVAL, "null argument");
+  if (!(a > 0) || !std::isfinite(a)) return fail(c, COLA_EINVAL, "a must be positive and finite");
+  const int nm = c->p.nmesh;
+  const long rs = 2 * padded_cols(nm);
+  StepCoef v{};
+  v.gscale = (float)green_scale(nm, 1.5 * c->p.omega_m / a);
+  launch_set_coef(c->coef, v, 1, 0, c->stream);
+  launch_copy_to_mesh(delta, nm, reinterpret_cast<float*>(c->mesh[0]), rs, c->stream);
+  fft_forces(c);
+  float* g[3] = {g0, g1, g2};
+  for (int d = 0; d < 3; ++d)
+    if (g[d]) launch_copy_from_mesh(reinterpret_cast<const float*>(c->mesh[d]), nm, rs, g[d], 1.0f, c->stream);
+  LAUNCH_CHECK(c, "cola_pm_gradient");
   return COLA_OK;
 }
 

@@ -126,6 +126,14 @@ class ColaSim:
         self._chk(self.lib.cola_force(self.ctx, _ptr(out)), "force")
         return out
 
+    def pm_gradient(self, a: float, delta: torch.Tensor, comps=(0, 1, 2)):
+        """Force meshes g_d (mesh units) of the density contrast ``delta``
+        (nmesh^3) at scale factor a; returns {d: (nmesh,)*3 tensor} for d in comps."""
+        out = {d: torch.empty((self.nmesh,) * 3, dtype=torch.float32, device=self.device) for d in comps}
+        ptrs = [_ptr(out[d]) if d in out else None for d in range(3)]
+        self._chk(self.lib.cola_pm_gradient(self.ctx, float(a), _ptr(delta), *ptrs), "pm_gradient")
+        return out
+
     def velocity(self, out=None, rsd_axis=None, sdisp=None):
         """Canonical particle velocity at the position time a_x (3 x np^3, mesh
         units); with rsd_axis also the redshift-space displacement along that

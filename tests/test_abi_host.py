@@ -75,6 +75,7 @@ def test_host_step_scalars_with_d2_from_its_growth_equation():
     (64, 32, _lib.COLA_EUNSUPPORTED),    # mesh coarser than the particle grid
     (32, 8, _lib.COLA_EINVAL),           # mesh too small
     (16, 16, _lib.COLA_EINVAL),          # the deposit needs two 16^3 tiles per side
+    (1536, 2048, _lib.COLA_EUNSUPPORTED),  # more than 2^30 particles (30-bit ids in the sort keys)
 ])
 def test_workspace_query_rejects_bad_sizes(np_side, nmesh, code):
     lib, p = params(np_side, nmesh)

@@ -1,0 +1,171 @@
+"""Oracle parity of the configurations the other GPU tests cover only
+against the GPU itself or at other sizes.
+
+* The batched ensemble: two mocks of each size group (48^3/96^3 at 150 Mpc/h,
+  64^3/128^3 at 200, 96^3/192^3 at 300) stepped together by the batch; for
+  one mock per group, one batched step against the FP64 oracle step from the
+  same state, and the final P(k) after 10 batched steps against the oracle's
+  own 10-step run from the same noise.
+* The differentiable configuration, 128^3 particles on a 256^3 mesh in
+  300 Mpc/h: PM force at an evolved state, the 10-step P(k) and one adjoint
+  step against the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint, cola, cosmology as cosmo, ic, pk, pm  # noqa: E402
+from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges, white_noise  # noqa: E402
+
+OM = 0.27
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_state(st, np_side, nm, box):
+    s = box / nm
+    return cola.State(np_side, nm, box, OM, -2.5, ic.lattice(np_side, box), host(st["disp"]) * s,
+                      host(st["vres"]) * s, host(st["psi1"]) * s, host(st["psi2"]) * s, st["a_x"], st["a_v"])
+
+
+def final_pk_parity(p_gpu, n_gpu, ref_state, box, nm):
+    edges = pk.log_edges(box, nm, 40)
+    k_o, p_o, n_o = pk.power_spectrum(ref_state.positions(), box, nm, edges)
+    assert np.array_equal(n_gpu, n_o)
+    sel = (n_o > 0) & (k_o < np.pi * nm / box / 2)
+    return float(np.abs(p_gpu[sel] / p_o[sel] - 1).max())
+
+
+GROUPS = [(48, 96, 150.0), (64, 128, 200.0), (96, 192, 300.0)]
+
+
+@pytest.mark.timeout(900)
+def test_batched_mocks_match_oracle():
+    from paper_1507_05329_amd.sim import ColaBatch
+    table = bbks_table()
+    e = step_edges()
+    specs = []
+    for g, (n, m, box) in enumerate(GROUPS):
+        for r in range(2):
+            specs.append(dict(np=n, nmesh=m, box=box + 10.0 * r, seed=2000 + 10 * g + r))
+    say(f"[gpu] batch of {len(specs)} mocks against the oracle")
+    b = ColaBatch(specs)
+    try:
+        noises = [white_noise(sp["seed"], sp["np"]) for sp in specs]
+        for mk, w in zip(b.mocks, noises):
+            mk.init_from_noise(dev(w), *table)
+        for i in range(3):
+            b.step(e[i], e[i + 1])
+        checked = [0, 2, 4]                          # first mock of each size group
+        before = {j: b.mocks[j].get_state() for j in checked}
+        b.step(e[3], e[4])
+        for j in checked:
+            sp = specs[j]
+            n, nm, box = sp["np"], sp["nmesh"], sp["box"]
+            o = oracle_state(before[j], n, nm, box)
+            d0, v0 = o.d.copy(), o.v.copy()
+            cola.step(o, e[4])
+            after = b.mocks[j].get_state()
+            s = box / nm
+            err_d = rel_l2(host(after["disp"]) * s - d0, o.d - d0)
+            err_v = rel_l2(host(after["vres"]) * s - v0, o.v - v0)
+            say(f"[gpu]   mock {j} ({n}^3/{nm}^3): batched step increments rel-L2 d {err_d:.2e} v {err_v:.2e}")
+            assert err_d < 1e-4 and err_v < 1e-4
+            # the batched run's force field equals the oracle's at these positions
+            f = host(b.mocks[j].force())
+            ref = pm.pm_force(oracle_state(after, n, nm, box).positions(), nm, box,
+                              cosmo.poisson_alpha(after["a_x"], OM)) * (nm / box)
+            err_f = rel_l2(f, ref)
+            say(f"[gpu]   mock {j}: force rel-L2 {err_f:.2e}")
+            assert err_f <= 1e-5
+        for i in range(4, len(e) - 1):
+            b.step(e[i], e[i + 1])
+        for j in checked:
+            sp = specs[j]
+            n, nm, box = sp["np"], sp["nmesh"], sp["box"]
+            edges = pk.log_edges(box, nm, 40)
+            _, p_g, n_g = b.mocks[j].pk(edges)
+            ref = cola.init_state(noises[j], box, nm, *table)
+            cola.run(ref, e)
+            err = final_pk_parity(p_g, n_g, ref, box, nm)
+            say(f"[gpu]   mock {j}: final P(k) max rel diff (k < k_Nyq/2) {err:.2e}")
+            assert err < 5e-3
+    finally:
+        b.close()
+
+
+@pytest.fixture(scope="module")
+def diff_run():
+    from paper_1507_05329_amd.sim import ColaSim
+    cfg = CONFIGS["diff"]
+    table = bbks_table()
+    say(f"[gpu] differentiable configuration {cfg.np_side}^3/{cfg.nmesh}^3")
+    s = ColaSim(cfg.np_side, cfg.nmesh, cfg.box)
+    w = white_noise(cfg.seed, cfg.np_side)
+    yield s, cfg, table, w
+    s.close()
+
+
+def test_diff_config_force_and_adjoint_step(diff_run):
+    s, cfg, table, w = diff_run
+    n, nm, box = cfg.np_side, cfg.nmesh, cfg.box
+    e = step_edges()
+    s.init_from_noise(dev(w), *table)
+    for i in range(3):
+        s.step(e[i], e[i + 1])
+    st = s.get_state()
+    o = oracle_state(st, n, nm, box)
+    f = host(s.force())
+    ref = pm.pm_force(o.positions(), nm, box, cosmo.poisson_alpha(st["a_x"], OM)) * (nm / box)
+    err = rel_l2(f, ref)
+    say(f"[gpu]   force rel-L2 {err:.2e}")
+    assert err <= 1e-5
+    rng = np.random.default_rng(7)
+    db, vb = rng.standard_normal((2, 3, n ** 3)).astype(np.float32)
+    sc = box / nm
+    od, ov, o1, o2 = adjoint.step_adjoint(o, e[4], db / sc, vb / sc)
+    dbar, vbar = dev(db), dev(vb)
+    p1, p2 = torch.zeros_like(dbar), torch.zeros_like(dbar)
+    s.step_adjoint(e[3], e[4], st["a_v"], st["disp"], dbar, vbar, p1, p2)
+    for got, want, name in ((dbar, od * sc, "dbar"), (vbar, ov * sc, "vbar"), (p1, o1 * sc, "psi1bar"),
+                            (p2, o2 * sc, "psi2bar")):
+        err = rel_l2(host(got), want)
+        say(f"[gpu]   adjoint {name} rel-L2 {err:.2e}")
+        assert err < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_diff_config_final_power_spectrum(diff_run):
+    s, cfg, table, w = diff_run
+    n, nm, box = cfg.np_side, cfg.nmesh, cfg.box
+    e = step_edges()
+    s.init_from_noise(dev(w), *table)
+    s.run(e)
+    edges = pk.log_edges(box, nm, 40)
+    _, p_g, n_g = s.pk(edges)
+    say("[gpu]   oracle 10-step run 128^3/256^3")
+    ref = cola.init_state(w, box, nm, *table)
+    cola.run(ref, e)
+    err = final_pk_parity(p_g, n_g, ref, box, nm)
+    say(f"[gpu]   final P(k) max rel diff (k < k_Nyq/2) {err:.2e}")
+    assert err < 5e-3
