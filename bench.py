@@ -49,6 +49,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    """Progress of the legs on stderr (the JSON line is the only stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
 # host memory the full FP64 oracle run of a workload needs (particles, two
 # meshes and temporaries in FP64), for the P(k) parity note
 ORACLE_HOST_BYTES_PER_NODE = 40.0
@@ -426,9 +431,11 @@ def workload_block(cfg, steps, warmup, dev, with_adjoint, with_outputs, lean):
     try:
         if warmup:
             cycled_steps(sim, cfg, table, e, warmup)
+        log(f"{cfg.np_side}^3/{cfg.nmesh}^3: {warmup} warm-up steps done")
         dt = cycled_steps(sim, cfg, table, e, steps)
         ms_step = dt / steps * 1e3
         out.update(value=cfg.n_particles * steps / dt, ms_per_step=ms_step)
+        log(f"{cfg.np_side}^3/{cfg.nmesh}^3: {steps} timed steps, {ms_step:.2f} ms/step")
         if with_adjoint:
             if lean:
                 out["fwd_adjoint"] = lean_gradient_leg(sim, cfg, table, e, ms_step)
@@ -444,12 +451,14 @@ def workload_block(cfg, steps, warmup, dev, with_adjoint, with_outputs, lean):
                     "value": cfg.n_particles / ((kept[0] + kept[1]) * 1e-3), "unit": "particle-updates/s",
                     "ms_forward_step": kept[0], "ms_adjoint_step": kept[1], "slots_GB": kept[2],
                     "note": "forward steps keep their force meshes (one slot per step); the adjoint reads them"}
+            log(f"{cfg.np_side}^3/{cfg.nmesh}^3: adjoint legs done")
     finally:
         sim.close()
         del sim
         torch.cuda.empty_cache()
     stages, extra = stage_pass(cfg, table, e, dev, with_outputs)
     torch.cuda.empty_cache()
+    log(f"{cfg.np_side}^3/{cfg.nmesh}^3: stage timers done")
     out["stages"] = stages
     out["roofline"] = roofline_of(stages, cfg, out["ms_per_step"])
     out.update(extra)
@@ -556,8 +565,10 @@ def main():
     batched = None
     if not args.no_batch:
         batched = batch_leg(10, bbks_table(), dev)
+        log("batched ensemble done")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
+    log("cpu baseline done")
 
     out = {
         "metric": "particle-updates/s per COLA PM step (fwd; fwd+adjoint in fwd_adjoint) + % HBM roofline",

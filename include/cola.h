@@ -143,6 +143,19 @@ int cola_density(cola_ctx* ctx, float* dev_out);
 int cola_pk(cola_ctx* ctx, int32_t ngrid, const double* k_edges, int32_t nbins,
             double* host_kmean, double* host_pk, int64_t* host_nmodes);
 
+/* The same spectrum corrected for the CIC smoothing and aliasing together
+ * by the procedure of Jing (2005, ApJ 620, 559), which Sec. 3.3 applies:
+ * per bin, the mean raw |delta_k|^2 / V (no window division) over the mean,
+ * over the bin's modes, of the window's image sum
+ *   C(k; s) = sum_m W^2(k + 2 k_N m) (|k + 2 k_N m| / |k|)^s,
+ * W = prod sinc^2 (CIC), k_N = pi ngrid / box, |m_e| <= 2 images per axis,
+ * s the local log-log slope of the corrected spectrum between the bin's
+ * non-empty neighbours (one-sided at the ends, 0 for a lone bin) limited to
+ * [-3, 1], starting from 0 and iterated 8 times.  Same arguments, outputs,
+ * empty-bin NaNs and synchronisation as cola_pk. */
+int cola_pk_jing(cola_ctx* ctx, int32_t ngrid, const double* k_edges, int32_t nbins,
+                 double* host_kmean, double* host_pk, int64_t* host_nmodes);
+
 /* Snapshot at a_s inside the coming step a_x -> a1 (a_x <= a_s <= a1),
  * without changing the state (Sec. 2.2, eqs. ansatz-drift and cola-drift;
  * the paper interpolates its snapshots this way): the step's kick takes

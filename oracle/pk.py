@@ -7,8 +7,9 @@ Steps, in the paper's order:
 3. P(k) = V^-1 <|delta(k)|^2>, with delta(k) = (V/Ng^3) DFT[delta] the
    continuum-normalised transform, averaged in bins; report the mean |k|.
 4. Correct for the CIC smoothing by dividing delta(k) by
-   W(k) = prod_e sinc^2(pi n_e / Ng).  (The paper also applies Jing's
-   iterative aliasing correction; that is not done here.)
+   W(k) = prod_e sinc^2(pi n_e / Ng) (``power_spectrum``), or for the
+   smoothing and the aliasing together by Jing's (2005) procedure
+   (``power_spectrum_jing``, the last sentence of Sec. 3.3).
 
 Readings: signed mode indices follow the DFT layout (n in [-Ng/2, Ng/2-1] on
 x and y, n_z in [0, Ng/2]); only modes with |k| <= k_Nyq = pi Ng / L are
@@ -116,3 +117,109 @@ def velocity_power(pos: np.ndarray, u: np.ndarray, box: float, ng: int, edges, a
     _, p_du, _ = bin_modes(np.sign(n) * (d.imag * p.real - d.real * p.imag) / V, ng, box, edges)
     _, p_uu, _ = bin_modes((p.real ** 2 + p.imag ** 2) / V, ng, box, edges)
     return k, p_dd, p_du, p_uu, cnt
+
+
+# ---------------------------------------------------------------------------
+# Smoothing and aliasing correction of Jing (2005, ApJ 620, 559), Sec. 3.3.
+#
+# The grid spectrum of a field assigned with window W holds every image of a
+# mode: <|delta_grid(k)|^2> = sum_m |W(k + 2 k_N m)|^2 P(|k + 2 k_N m|), m in
+# Z^3, k_N = pi Ng / L.  Jing approximates P near |k| by a local power law of
+# index s, P(|k'|) = P(|k|) (|k'| / |k|)^s, so that per |k| bin
+#     P_b = <|delta_grid|^2 / V>_b / <C(k; s_b)>_b,
+#     C(k; s) = sum_m |W(k + 2 k_N m)|^2 (|k + 2 k_N m| / |k|)^s,
+# and finds s_b by iteration from the corrected spectrum itself.
+# Readings (the paper names the procedure only): W is the CIC window
+# prod_e sinc^2(pi n_e / Ng) continued to the images; the image sum runs over
+# |m_e| <= JING_IMAGES (terms fall as |m|^(s-4) per axis; at s = 0 the
+# truncation leaves at most 0.13% at the Nyquist frequency); s_b starts at 0
+# and is the log-log slope of the corrected P between the neighbouring
+# non-empty bins (one-sided at the ends, 0 for a lone bin), limited to
+# [JING_SLOPE_MIN, JING_SLOPE_MAX] (the slopes of a CDM spectrum, between its
+# primordial n_s ~ 1 and the small-scale -3; a noisy bin cannot drive the
+# image sum, which diverges along an axis for s >= 3); the iteration runs
+# JING_ITERATIONS times.  No shot-noise term is subtracted.
+
+JING_IMAGES = 2
+JING_ITERATIONS = 8
+JING_SLOPE_MIN = -3.0
+JING_SLOPE_MAX = 1.0
+
+
+def _signed_modes(ng: int):
+    nx = np.fft.fftfreq(ng, d=1.0 / ng).reshape(ng, 1, 1)
+    ny = np.fft.fftfreq(ng, d=1.0 / ng).reshape(1, ng, 1)
+    nz = np.arange(ng // 2 + 1, dtype=np.float64).reshape(1, 1, ng // 2 + 1)
+    return nx, ny, nz
+
+
+def alias_window_sum(ng: int, slope, images: int = JING_IMAGES) -> np.ndarray:
+    """C(k; s) at every half-spectrum mode of an Ng^3 grid, s = ``slope``
+    (scalar or an array broadcastable to (Ng, Ng, Ng/2+1)); the k = 0 entry
+    is the m = 0 term alone (1)."""
+    nx, ny, nz = _signed_modes(ng)
+    n2 = nx * nx + ny * ny + nz * nz
+    n2 = np.where(n2 == 0, 1.0, n2)
+    half_s = 0.5 * np.asarray(slope, dtype=np.float64)
+    out = np.zeros(np.broadcast_shapes(n2.shape, np.shape(half_s)))
+    rng_m = range(-images, images + 1)
+    for mx in rng_m:
+        wx = np.sinc(nx / ng + mx) ** 4
+        for my in rng_m:
+            wy = np.sinc(ny / ng + my) ** 4
+            for mz in rng_m:
+                wz = np.sinc(nz / ng + mz) ** 4
+                w = wx * wy * wz
+                k2 = (nx + ng * mx) ** 2 + (ny + ng * my) ** 2 + (nz + ng * mz) ** 2
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    ratio = np.where(w > 0, (k2 / n2) ** half_s, 0.0)
+                out = out + w * ratio
+    return out
+
+
+def local_slopes(kmean: np.ndarray, p: np.ndarray, cnt: np.ndarray) -> np.ndarray:
+    """d ln P / d ln k of each non-empty bin from its non-empty neighbours."""
+    s = np.zeros(len(p))
+    idx = np.flatnonzero(cnt > 0)
+    for j, b in enumerate(idx):
+        lo = idx[j - 1] if j > 0 else b
+        hi = idx[j + 1] if j + 1 < len(idx) else b
+        if lo != hi and p[lo] > 0 and p[hi] > 0:
+            s[b] = np.log(p[hi] / p[lo]) / np.log(kmean[hi] / kmean[lo])
+    return s
+
+
+def mode_bins(ng: int, box: float, edges) -> np.ndarray:
+    """Bin index of every half-spectrum mode under bin_modes' selection, -1 where unbinned."""
+    edges = np.asarray(edges, dtype=np.float64)
+    kmag = mode_kmag(ng, box)
+    keep = halfspace_mask(ng) & (kmag <= np.pi * ng / box)
+    b = np.searchsorted(edges, kmag, side="right") - 1
+    b[(b < 0) | (b >= len(edges) - 1) | ~keep] = -1
+    return b
+
+
+def power_from_delta_jing(delta: np.ndarray, box: float, edges, images: int = JING_IMAGES,
+                          iterations: int = JING_ITERATIONS):
+    """Binned P(k) of a grid density contrast, corrected by Jing's procedure:
+    (kmean, P, count)."""
+    ng = delta.shape[0]
+    dk = sfft.rfftn(delta, workers=-1) * (box ** 3 / ng ** 3)
+    raw = (dk.real ** 2 + dk.imag ** 2) / box ** 3
+    kmean, praw, cnt = bin_modes(raw, ng, box, edges)
+    bins = mode_bins(ng, box, edges)
+    s = np.zeros(len(cnt))
+    p = praw
+    for _ in range(iterations):
+        smode = np.where(bins >= 0, s[np.maximum(bins, 0)], 0.0)
+        _, cbar, _ = bin_modes(alias_window_sum(ng, smode, images), ng, box, edges)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            p = praw / cbar
+        s = np.clip(local_slopes(kmean, p, cnt), JING_SLOPE_MIN, JING_SLOPE_MAX)
+    return kmean, p, cnt
+
+
+def power_spectrum_jing(pos: np.ndarray, box: float, ng: int, edges, images: int = JING_IMAGES,
+                        iterations: int = JING_ITERATIONS):
+    """Binned P(k) of the particles at ``pos`` with Jing's smoothing and aliasing correction."""
+    return power_from_delta_jing(pm.density_contrast(pos, ng, box), box, edges, images, iterations)

@@ -49,6 +49,7 @@ _SIGS = {
     "cola_step": (C.c_int, [_P, _D, _D]),
     "cola_density": (C.c_int, [_P, _P]),
     "cola_pk": (C.c_int, [_P, _I, _DP, _I, _DP, _DP, C.POINTER(C.c_int64)]),
+    "cola_pk_jing": (C.c_int, [_P, _I, _DP, _I, _DP, _DP, C.POINTER(C.c_int64)]),
     "cola_force": (C.c_int, [_P, _P]),
     "cola_pm_gradient": (C.c_int, [_P, _D, _P, _P, _P, _P]),
     "cola_velocity": (C.c_int, [_P, _P, _P, C.c_int32]),

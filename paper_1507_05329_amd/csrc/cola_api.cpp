@@ -666,7 +666,83 @@ int pk_of(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32
   return COLA_OK;
 }
 
+// Jing (2005) correction (Sec. 3.3): raw bin power over the bin average of
+// the CIC window's image sum at the local slope of the corrected spectrum,
+// iterated from slope 0.  The slope of a bin is the log-log slope between
+// its non-empty neighbours (one-sided at the ends, 0 alone), limited to
+// [kJingSlopeMin, kJingSlopeMax]; kJingIterations passes.
+constexpr int kJingIterations = 8;
+constexpr double kJingSlopeMin = -3.0, kJingSlopeMax = 1.0;
+
+void jing_slopes(const std::vector<double>& km, const std::vector<double>& p, const std::vector<double>& cnt,
+                 std::vector<double>* s) {
+  const int nb = (int)p.size();
+  std::vector<int> idx;
+  for (int b = 0; b < nb; ++b)
+    if (cnt[b] > 0) idx.push_back(b);
+  s->assign(nb, 0.0);
+  for (size_t j = 0; j < idx.size(); ++j) {
+    const int b = idx[j];
+    const int lo = j > 0 ? idx[j - 1] : b, hi = j + 1 < idx.size() ? idx[j + 1] : b;
+    double v = 0.0;
+    if (lo != hi && p[lo] > 0 && p[hi] > 0) v = std::log(p[hi] / p[lo]) / std::log(km[hi] / km[lo]);
+    (*s)[b] = std::min(kJingSlopeMax, std::max(kJingSlopeMin, v));
+  }
+}
+
+int pk_jing_of(cola_ctx* c, const float* disp, int32_t ng, const double* edges, int32_t nbins, double* kmean,
+               double* pk, int64_t* nmodes) {
+  if (nbins < 1 || nbins > kMaxBins) return fail(c, COLA_EINVAL, "nbins out of range");
+  if (ng < 32 || ng > c->p.nmesh || !fft_size_supported(ng))
+    return fail(c, COLA_EUNSUPPORTED, "ngrid must be a supported size in [32, nmesh]");
+  for (int i = 0; i < nbins; ++i)
+    if (!(edges[i + 1] > edges[i])) return fail(c, COLA_EINVAL, "edges must increase");
+  int r = ensure_twiddles(c, ng);
+  if (r != COLA_OK) return r;
+  HIP_TRY(c, hipMemcpyAsync(c->pk_edges, edges, (nbins + 1) * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  float2* m = c->mesh[0];
+  deposit(c, ng, reinterpret_cast<float*>(m), 2 * padded_cols(ng), 1, disp);
+  fft3d_forward(m, ng, c->tw, c->stream);
+  launch_pk_bin(m, ng, c->p.box, c->pk_edges, nbins, c->pk_partial, kPkChunks, c->stream, 0);
+  launch_pk_reduce(c->pk_partial, nbins, kPkChunks, c->pk_out, c->stream);
+  LAUNCH_CHECK(c, "cola_pk_jing");
+  std::vector<double> h(3 * (size_t)nbins);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), c->pk_out, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<double> km(nbins), raw(nbins), cnt(nbins), p(nbins), s(nbins, 0.0), csum(nbins);
+  for (int b = 0; b < nbins; ++b) {
+    cnt[b] = h[3 * b + 2];
+    km[b] = cnt[b] > 0 ? h[3 * b] / cnt[b] : NAN;
+    raw[b] = cnt[b] > 0 ? h[3 * b + 1] / cnt[b] : NAN;
+  }
+  for (int it = 0; it < kJingIterations; ++it) {
+    // slopes go to the P(k) cotangent buffer (free outside cola_pk_adjoint)
+    HIP_TRY(c, hipMemcpyAsync(c->pk_cbar, s.data(), nbins * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    launch_pk_alias(ng, c->p.box, c->pk_edges, nbins, c->pk_cbar, c->pk_partial, kPkChunks, c->pk_out, c->stream);
+    LAUNCH_CHECK(c, "cola_pk_jing");
+    HIP_TRY(c, hipMemcpyAsync(csum.data(), c->pk_out, nbins * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < nbins; ++b) p[b] = cnt[b] > 0 ? raw[b] / (csum[b] / cnt[b]) : NAN;
+    jing_slopes(km, p, cnt, &s);
+  }
+  for (int b = 0; b < nbins; ++b) {
+    nmodes[b] = (int64_t)llround(cnt[b]);
+    kmean[b] = km[b];
+    pk[b] = p[b];
+  }
+  return COLA_OK;
+}
+
 }  // namespace
+
+int cola_pk_jing(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double* kmean, double* pk,
+                 int64_t* nmodes) {
+  if (!c || !edges || !kmean || !pk || !nmodes) return fail(c, COLA_EINVAL, "null argument");
+  if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
+  return pk_jing_of(c, c->disp, ng, edges, nbins, kmean, pk, nmodes);
+}
 
 int cola_pk(cola_ctx* c, int32_t ng, const double* edges, int32_t nbins, double* kmean, double* pk,
             int64_t* nmodes) {

@@ -26,6 +26,13 @@ bool fft_size_supported(int n);   // transform sizes with compiled kernels
 inline long padded_cols(int n) { return ((long)(n / 2 + 1) + 15) / 16 * 16; }
 inline long mesh_complex_count(int n) { return (long)n * n * padded_cols(n); }
 
+// Workgroups of 256 for a grid-stride loop over n items: a dispatch holds at
+// most 2^32 - 1 work-items, so the grid is capped and each thread loops.
+inline unsigned grid_1d(long n) {
+  const long b = (n + 255) / 256;
+  return (unsigned)(b < (1L << 22) ? (b > 0 ? b : 1) : (1L << 22));
+}
+
 // Twiddle tables: one per distinct length, tw[k] = exp(-2 pi i k / n).
 struct TwiddleSet {
   int n[4] = {0, 0, 0, 0};
@@ -170,7 +177,10 @@ void launch_init_particles(float* disp, float* vres, const float* psi1, const fl
 void launch_axpby(float* y, const float* x, float a, float b, long n, hipStream_t s);
 // Power spectrum binning (k_pk.hip).
 void launch_pk_bin(const float2* spec, int ng, double box, const double* edges, int nbins,
-                   double* partial, int nchunk, hipStream_t s);
+                   double* partial, int nchunk, hipStream_t s, int deconvolve = 1);
+// Jing (2005) image sums of the CIC window per bin at the per-bin slopes (out: nbins sums).
+void launch_pk_alias(int ng, double box, const double* edges, int nbins, const double* slope, double* partial,
+                     int nchunk, double* out, hipStream_t s);
 void launch_pk_reduce(const double* partial, int nbins, int nchunk, double* out, hipStream_t s);
 // Density / line-of-sight momentum spectra: partial holds 5 doubles per (bin, chunk),
 // out 5 per bin (sum |k|, P_dd, P_du, P_uu, count).

@@ -115,18 +115,19 @@ void launch_adj_deposit_grad(const float* disp, const float* field, long row_str
 __global__ void k_axpy_to_mesh(const float* __restrict__ a, const float* __restrict__ b, float alpha,
                                int n, long n3, float* __restrict__ mesh, long row_stride,
                                long mesh_stride) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const long row = p / n, col = p - row * n;
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-    mesh[q * mesh_stride + row * row_stride + col] = a[q * n3 + p] + alpha * (b ? b[q * n3 + p] : 0.f);
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
+       p += (long)gridDim.x * blockDim.x) {
+    const long row = p / n, col = p - row * n;
+  #pragma unroll
+    for (int q = 0; q < 3; ++q)
+      mesh[q * mesh_stride + row * row_stride + col] = a[q * n3 + p] + alpha * (b ? b[q * n3 + p] : 0.f);
+  }
 }
 
 void launch_axpy_to_mesh(const float* a, const float* b, float alpha, int n, float* mesh,
                          long row_stride, long mesh_stride_floats, hipStream_t s) {
   const long n3 = (long)n * n * n;
-  hipLaunchKernelGGL(k_axpy_to_mesh, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, a, b, alpha,
+  hipLaunchKernelGGL(k_axpy_to_mesh, dim3(grid_1d(n3)), dim3(256), 0, s, a, b, alpha,
                      n, n3, mesh, row_stride, mesh_stride_floats);
 }
 
@@ -134,38 +135,40 @@ void launch_axpy_to_mesh(const float* a, const float* b, float alpha, int n, flo
 // diagonal: (a, b, c) <- Sbar (b + c, a + c, a + b); off-diagonal: a <- -2 Sbar a.
 __global__ void k_phibar_diag(float* __restrict__ a, float* __restrict__ b, float* __restrict__ c,
                               const float* __restrict__ sbar, int n, long n3, long row_stride) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const long row = p / n, col = p - row * n;
-  const long j = row * row_stride + col;
-  const float x = a[j], y = b[j], z = c[j], sb = sbar[j];
-  a[j] = sb * (y + z);
-  b[j] = sb * (x + z);
-  c[j] = sb * (x + y);
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
+       p += (long)gridDim.x * blockDim.x) {
+    const long row = p / n, col = p - row * n;
+    const long j = row * row_stride + col;
+    const float x = a[j], y = b[j], z = c[j], sb = sbar[j];
+    a[j] = sb * (y + z);
+    b[j] = sb * (x + z);
+    c[j] = sb * (x + y);
+  }
 }
 
 __global__ void k_phibar_off(float* __restrict__ a, const float* __restrict__ sbar, int n, long n3,
                              long row_stride, long mesh_stride) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const long row = p / n, col = p - row * n;
-  const long j = row * row_stride + col;
-  const float sb = sbar[j];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) a[q * mesh_stride + j] = -2.0f * sb * a[q * mesh_stride + j];
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
+       p += (long)gridDim.x * blockDim.x) {
+    const long row = p / n, col = p - row * n;
+    const long j = row * row_stride + col;
+    const float sb = sbar[j];
+  #pragma unroll
+    for (int q = 0; q < 3; ++q) a[q * mesh_stride + j] = -2.0f * sb * a[q * mesh_stride + j];
+  }
 }
 
 void launch_phibar_diag(float* a, float* b, float* c, const float* sbar, int n, long row_stride,
                         hipStream_t s) {
   const long n3 = (long)n * n * n;
-  hipLaunchKernelGGL(k_phibar_diag, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, a, b, c, sbar,
+  hipLaunchKernelGGL(k_phibar_diag, dim3(grid_1d(n3)), dim3(256), 0, s, a, b, c, sbar,
                      n, n3, row_stride);
 }
 
 void launch_phibar_off(float* a, const float* sbar, int n, long row_stride, long mesh_stride_floats,
                        hipStream_t s) {
   const long n3 = (long)n * n * n;
-  hipLaunchKernelGGL(k_phibar_off, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, a, sbar, n, n3,
+  hipLaunchKernelGGL(k_phibar_off, dim3(grid_1d(n3)), dim3(256), 0, s, a, sbar, n, n3,
                      row_stride, mesh_stride_floats);
 }
 
@@ -185,36 +188,36 @@ __global__ void k_pk_adj_modes(const float2* __restrict__ X, float2* __restrict_
                                double kf, double kmax, double vol_fac,
                                const double* __restrict__ edges, int nbins,
                                const double* __restrict__ cbar, const double* __restrict__ sums) {
-  const long m = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const int h = ng / 2;
   const long nmode = (long)ng * ng * (h + 1);
-  if (m >= nmode) return;
-  const int iz = (int)(m % (h + 1));
-  const long r = m / (h + 1);
-  const int ix = (int)(r / ng), iy = (int)(r % ng);
-  const int nx = ix < h ? ix : ix - ng, ny = iy < h ? iy : iy - ng, nz = iz;
-  if (nz == 0 && !(ny > 0 || (ny == 0 && nx > 0))) return;
-  const double n2 = (double)nx * nx + (double)ny * ny + (double)nz * nz;
-  const double kk = kf * sqrt(n2);
-  if (kk > kmax) return;
-  // bin: last edge <= kk
-  int lo = 0, hi = nbins;  // edges[0..nbins]
-  if (!(kk >= edges[0] && kk < edges[nbins])) return;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) / 2;
-    if (edges[mid] <= kk) lo = mid; else hi = mid;
-  }
-  const double cnt = sums[3 * lo + 2];
-  if (cnt <= 0) return;
-  double w = sinc_pi_d((double)nx / ng) * sinc_pi_d((double)ny / ng) * sinc_pi_d((double)nz / ng);
-  w = w * w;
-  const double u = cbar[lo] / cnt * vol_fac / (w * w);
-  const float2 x = X[r * cols + iz];
-  const double fac = (nz == h) ? 2.0 * u : u;
-  Z[r * cols + iz] = make_float2((float)(fac * x.x), (float)(fac * x.y));
-  if (nz == 0) {
-    const int jx = (ng - ix) % ng, jy = (ng - iy) % ng;
-    Z[((long)jx * ng + jy) * cols] = make_float2((float)(u * x.x), (float)(-u * x.y));
+  for (long m = blockIdx.x * (long)blockDim.x + threadIdx.x; m < nmode; m += (long)gridDim.x * blockDim.x) {
+    const int iz = (int)(m % (h + 1));
+    const long r = m / (h + 1);
+    const int ix = (int)(r / ng), iy = (int)(r % ng);
+    const int nx = ix < h ? ix : ix - ng, ny = iy < h ? iy : iy - ng, nz = iz;
+    if (nz == 0 && !(ny > 0 || (ny == 0 && nx > 0))) continue;
+    const double n2 = (double)nx * nx + (double)ny * ny + (double)nz * nz;
+    const double kk = kf * sqrt(n2);
+    if (kk > kmax) continue;
+    // bin: last edge <= kk
+    if (!(kk >= edges[0] && kk < edges[nbins])) continue;
+    int lo = 0, hi = nbins;  // edges[0..nbins]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (edges[mid] <= kk) lo = mid; else hi = mid;
+    }
+    const double cnt = sums[3 * lo + 2];
+    if (cnt <= 0) continue;
+    double w = sinc_pi_d((double)nx / ng) * sinc_pi_d((double)ny / ng) * sinc_pi_d((double)nz / ng);
+    w = w * w;
+    const double u = cbar[lo] / cnt * vol_fac / (w * w);
+    const float2 x = X[r * cols + iz];
+    const double fac = (nz == h) ? 2.0 * u : u;
+    Z[r * cols + iz] = make_float2((float)(fac * x.x), (float)(fac * x.y));
+    if (nz == 0) {
+      const int jx = (ng - ix) % ng, jy = (ng - iy) % ng;
+      Z[((long)jx * ng + jy) * cols] = make_float2((float)(u * x.x), (float)(-u * x.y));
+    }
   }
 }
 
@@ -225,7 +228,7 @@ void launch_pk_adj_modes(const float2* X, float2* Z, int ng, double box, const d
   const double v = box * box * box, n3 = (double)ng * ng * ng;
   const double vol_fac = (v / n3) * (v / n3) / v;
   const long nmode = (long)ng * ng * (ng / 2 + 1);
-  hipLaunchKernelGGL(k_pk_adj_modes, dim3((unsigned)((nmode + 255) / 256)), dim3(256), 0, s, X, Z, ng,
+  hipLaunchKernelGGL(k_pk_adj_modes, dim3(grid_1d(nmode)), dim3(256), 0, s, X, Z, ng,
                      padded_cols(ng), kf, kmax, vol_fac, edges, nbins, cbar, sums);
 }
 

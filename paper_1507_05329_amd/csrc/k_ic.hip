@@ -54,65 +54,69 @@ void launch_philox_noise(uint64_t seed, int np, float* out, long row_stride, hip
 
 __global__ void k_copy_to_mesh(const float* __restrict__ src, int n, long n3, float* __restrict__ mesh,
                                long row_stride) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const long row = p / n, col = p - row * n;
-  mesh[row * row_stride + col] = src[p];
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
+       p += (long)gridDim.x * blockDim.x) {
+    const long row = p / n, col = p - row * n;
+    mesh[row * row_stride + col] = src[p];
+  }
 }
 
 void launch_copy_to_mesh(const float* src, int n, float* mesh, long row_stride, hipStream_t s) {
   const long n3 = (long)n * n * n;
-  hipLaunchKernelGGL(k_copy_to_mesh, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, src, n, n3,
+  hipLaunchKernelGGL(k_copy_to_mesh, dim3(grid_1d(n3)), dim3(256), 0, s, src, n, n3,
                      mesh, row_stride);
 }
 
 __global__ void k_copy_from_mesh(const float* __restrict__ mesh, int n, long n3, long row_stride,
                                  float* __restrict__ dst, float scale) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const long row = p / n, col = p - row * n;
-  dst[p] = scale * mesh[row * row_stride + col];
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
+       p += (long)gridDim.x * blockDim.x) {
+    const long row = p / n, col = p - row * n;
+    dst[p] = scale * mesh[row * row_stride + col];
+  }
 }
 
 void launch_copy_from_mesh(const float* mesh, int n, long row_stride, float* dst, float scale,
                            hipStream_t s) {
   const long n3 = (long)n * n * n;
-  hipLaunchKernelGGL(k_copy_from_mesh, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, mesh, n,
+  hipLaunchKernelGGL(k_copy_from_mesh, dim3(grid_1d(n3)), dim3(256), 0, s, mesh, n,
                      n3, row_stride, dst, scale);
 }
 
 // 2LPT source, diagonal part: a <- a b + b c + c a (a, b, c = phi_xx, phi_yy, phi_zz).
 __global__ void k_source_diag(float* __restrict__ a, const float* __restrict__ b,
                               const float* __restrict__ c, int n, long n3, long row_stride) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const long row = p / n, col = p - row * n;
-  const long j = row * row_stride + col;
-  const float x = a[j], y = b[j], z = c[j];
-  a[j] = x * y + y * z + z * x;
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
+       p += (long)gridDim.x * blockDim.x) {
+    const long row = p / n, col = p - row * n;
+    const long j = row * row_stride + col;
+    const float x = a[j], y = b[j], z = c[j];
+    a[j] = x * y + y * z + z * x;
+  }
 }
 
 void launch_source_diag(float* a, const float* b, const float* c, int n, long row_stride,
                         hipStream_t s) {
   const long n3 = (long)n * n * n;
-  hipLaunchKernelGGL(k_source_diag, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, a, b, c, n,
+  hipLaunchKernelGGL(k_source_diag, dim3(grid_1d(n3)), dim3(256), 0, s, a, b, c, n,
                      n3, row_stride);
 }
 
 // 2LPT source, off-diagonal part: a <- a - b^2.
 __global__ void k_source_sub_sq(float* __restrict__ a, const float* __restrict__ b, int n, long n3,
                                 long row_stride) {
-  const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (p >= n3) return;
-  const long row = p / n, col = p - row * n;
-  const long j = row * row_stride + col;
-  const float y = b[j];
-  a[j] = a[j] - y * y;
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
+       p += (long)gridDim.x * blockDim.x) {
+    const long row = p / n, col = p - row * n;
+    const long j = row * row_stride + col;
+    const float y = b[j];
+    a[j] = a[j] - y * y;
+  }
 }
 
 void launch_source_sub_sq(float* a, const float* b, int n, long row_stride, hipStream_t s) {
   const long n3 = (long)n * n * n;
-  hipLaunchKernelGGL(k_source_sub_sq, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, a, b, n,
+  hipLaunchKernelGGL(k_source_sub_sq, dim3(grid_1d(n3)), dim3(256), 0, s, a, b, n,
                      n3, row_stride);
 }
 
@@ -120,26 +124,28 @@ void launch_source_sub_sq(float* a, const float* b, int n, long row_stride, hipS
 __global__ void k_init_particles(float* __restrict__ disp, float* __restrict__ vres,
                                  const float* __restrict__ psi1, const float* __restrict__ psi2,
                                  long n, float D1, float D2) {
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  disp[i] = D1 * psi1[i] + D2 * psi2[i];
-  vres[i] = 0.0f;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    disp[i] = D1 * psi1[i] + D2 * psi2[i];
+    vres[i] = 0.0f;
+  }
 }
 
 void launch_init_particles(float* disp, float* vres, const float* psi1, const float* psi2, long np3,
                            float D1, float D2, hipStream_t s) {
   const long n = 3 * np3;
-  hipLaunchKernelGGL(k_init_particles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, disp, vres,
+  hipLaunchKernelGGL(k_init_particles, dim3(grid_1d(n)), dim3(256), 0, s, disp, vres,
                      psi1, psi2, n, D1, D2);
 }
 
 __global__ void k_axpby(float* __restrict__ y, const float* __restrict__ x, float a, float b, long n) {
-  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * y[i] + b * x[i];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    y[i] = a * y[i] + b * x[i];
 }
 
 void launch_axpby(float* y, const float* x, float a, float b, long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, a, b, n);
+  hipLaunchKernelGGL(k_axpby, dim3(grid_1d(n)), dim3(256), 0, s, y, x, a, b, n);
 }
 
 }  // namespace cola

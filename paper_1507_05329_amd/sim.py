@@ -202,15 +202,22 @@ class ColaSim:
                                             cnt.ctypes.data_as(C.POINTER(C.c_int64))), "pk_velocity")
         return (*out, cnt)
 
-    def pk(self, edges, ngrid=None, disp=None):
+    def pk(self, edges, ngrid=None, disp=None, jing=False):
         """Binned P(k) of the current positions, or of the displacement field
-        ``disp`` (3 x np^3, mesh units) on the same particle lattice."""
+        ``disp`` (3 x np^3, mesh units) on the same particle lattice.  jing:
+        the smoothing and aliasing correction of Jing (2005) instead of the
+        plain window division (current positions only)."""
         edges = np.ascontiguousarray(edges, np.float64)
         nb = len(edges) - 1
         km, p = np.zeros(nb), np.zeros(nb)
         nm = np.zeros(nb, np.int64)
         cnt = nm.ctypes.data_as(C.POINTER(C.c_int64))
-        if disp is None:
+        if jing:
+            if disp is not None:
+                raise ValueError("the Jing-corrected spectrum is of the current positions")
+            self._chk(self.lib.cola_pk_jing(self.ctx, ngrid or self.nmesh, dptr(edges), nb, dptr(km), dptr(p),
+                                            cnt), "pk_jing")
+        elif disp is None:
             self._chk(self.lib.cola_pk(self.ctx, ngrid or self.nmesh, dptr(edges), nb, dptr(km), dptr(p), cnt),
                       "pk")
         else:
