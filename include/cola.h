@@ -133,6 +133,23 @@ int cola_step(cola_ctx* ctx, double a0, double a1);
  * cells in a fixed order. */
 int cola_density(cola_ctx* ctx, float* dev_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * density contrast of cola_density_of, computed without a context.  The
+ * tile sort's buffers live in a static device array of 3.4 MB that each
+ * device holds until the process ends; the call makes no allocation
+ * (no hipMalloc, hipFree or host allocator) and enqueues the tile sort and
+ * deposit kernels on hip_stream (a hipStream_t of the current device;
+ * NULL = the default stream).  dev_disp: 3 * np^3 float32
+ * displacements in mesh cells, the layout of cola_get_state; dev_out:
+ * nmesh^3 float32, C order.  np a multiple of 16, nmesh a multiple of 16
+ * with 32 <= nmesh and np <= nmesh (COLA_EINVAL otherwise); at most 64^3
+ * particles and a 256^3 mesh (COLA_ENOMEM beyond).  Bitwise equal to
+ * cola_density_of of a context with the same np and nmesh.  Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, or two host threads) race and must be serialised by the caller. */
+int cola_density_noalloc(const float* dev_disp, int32_t np, int32_t nmesh, float* dev_out, void* hip_stream);
+
 /* Matter power spectrum (Sec. 3.3): CIC onto ngrid^3 (a supported size,
  * 32 <= ngrid <= nmesh), FFT, divide by the CIC window, P = |delta_k|^2
  * / V over the half space {kz>0} U {kz=0,ky>0} U {kz=0,ky=0,kx>0} with

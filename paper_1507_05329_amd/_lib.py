@@ -54,6 +54,7 @@ _SIGS = {
     "cola_pm_gradient": (C.c_int, [_P, _D, _P, _P, _P, _P]),
     "cola_velocity": (C.c_int, [_P, _P, _P, C.c_int32]),
     "cola_density_of": (C.c_int, [_P, _P, _P]),
+    "cola_density_noalloc": (C.c_int, [_P, _I, _I, _P, _P]),
     "cola_snapshot": (C.c_int, [_P, C.c_double, C.c_double, _P, _P, _P, C.c_int32]),
     "cola_fof_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "cola_fof": (C.c_int, [_P, C.c_double, _P, _P, C.c_size_t]),

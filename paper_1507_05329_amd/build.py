@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcola.so")
 SOURCES = ["cola_api.cpp", "cosmo.cpp", "k_sort.hip", "k_deposit.hip", "k_fft.hip",
            "k_particles.hip", "k_ic.hip", "k_pk.hip", "k_adjoint.hip",
-           "k_velocity.hip", "k_fof.hip"]
+           "k_velocity.hip", "k_fof.hip", "cola_noalloc.hip"]
 # translation units whose float results must follow the written order bit for bit
 STRICT = {"k_sort.hip", "k_deposit.hip"}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
