@@ -1,9 +1,13 @@
-"""Float32 same-order replay of the deterministic CIC deposit (Sec. 3.3 CIC).
+"""Float32 replay of the deterministic CIC mass deposit (Sec. 3.3 CIC).
+
+Test infrastructure: only tests, the smoke check and the benchmark's CPU
+baseline use this module.
 
 The FP64 oracle (``pm.cic_deposit``) fixes *what* the deposit computes.  This
-module fixes, in addition, the exact float32 rounding sequence, so that a
-float32 implementation that follows the same order can be checked bit for
-bit.  The order is a reading (the paper does not state one):
+module fixes, in addition, every float32 rounding, so that a float32
+implementation that follows the same rule can be checked bit for bit.  The
+rule is a reading (the paper states no summation order); it is chosen so
+that the result does not depend on any order at all:
 
 Positions are stored as float32 displacements d (in mesh cells) from the
 Lagrangian lattice; particle id p = (i*N + j)*N + k, lattice point of axis e
@@ -17,21 +21,23 @@ coordinate of a particle is u = i_e Nm / Np - 1/2 + d_e.  Per axis e:
     fl  = floor(u);  f = u - fl                     (float32)
     c_e = (qi + fl) mod Nm                          (home cell)
     w_0 = 1 - f,  w_1 = f                           (float32)
-For the 8 offsets s = (sx, sy, sz), taken in the order k = 4 sx + 2 sy + sz:
+For the 8 offsets s = (sx, sy, sz), k = 4 sx + 2 sy + sz:
     w_s = (w_sx(fx) * w_sy(fy)) * w_sz(fz)          (float32, no fused multiply-add)
-Per home cell c and offset s, the partial sum P_s(c) adds w_s of the cell's
-particles in ascending particle id, starting from 0.0f.
-Node n then adds its 8 source cells in ascending cell order, i.e.
-rho(n) = 0.0f + P_s7(n - s7) + P_s6(n - s6) + ... + P_s0(n - s0), offsets
-k = 7 .. 0 (a cell without particles contributes +0.0f).
-The density contrast is delta = rho * c_inv - 1.0f, c_inv = float32(Nm^3 / Np)
-(two float32 roundings, no fused multiply-add).
+    q_s = rint(w_s * 2^32)                          (unsigned 64-bit; ties to even)
+Node n = c + s holds the integer sum S(n) of the q_s of every particle and
+offset that reach it (exact, so independent of the order of the terms), and
+    rho(n)   = float32(S(n)) * 2^-32                (one rounding to nearest even)
+    delta(n) = rho(n) * c_inv - 1.0f,  c_inv = float32(Nm^3 / Np)
+(two float32 roundings, no fused multiply-add).  A weight w >= 2^-9 is a
+multiple of 2^-32, so q_s is exact and rho(n) is the correctly rounded exact
+sum of the node's float32 weights; smaller weights are rounded to 2^-32.
 """
 from __future__ import annotations
 
 import numpy as np
 
 F32 = np.float32
+FIX_SCALE = 2.0 ** 32
 
 
 def _axis_terms(np_side: int, nm: int):
@@ -60,7 +66,7 @@ def home_cells(disp: np.ndarray, np_side: int, nm: int, pid=None):
 
 
 def weights(f: np.ndarray):
-    """(8, Np) float32 weights in offset order k = 4 sx + 2 sy + sz."""
+    """(8, n) float32 weights in offset order k = 4 sx + 2 sy + sz."""
     one = F32(1.0)
     w = [[one - f[e], f[e]] for e in range(3)]
     out = np.empty((8, f.shape[1]), dtype=F32)
@@ -71,113 +77,70 @@ def weights(f: np.ndarray):
     return out
 
 
-def cell_partials(disp, np_side: int, nm: int):
-    """P_s(c) for all cells: (8, nm, nm, nm) float32, sums in ascending id."""
-    cells, f = home_cells(disp, np_side, nm)
-    w = weights(f)
-    flat = (cells[0] * nm + cells[1]) * nm + cells[2]
-    order = np.argsort(flat, kind="stable")          # ascending id within a cell
-    fs = flat[order]
-    first = np.r_[0, np.flatnonzero(np.diff(fs)) + 1]
-    rank = np.arange(len(fs)) - np.repeat(first, np.diff(np.r_[first, len(fs)]))
-    P = np.zeros((8, nm ** 3), dtype=F32)
-    for r in range(int(rank.max()) + 1 if len(rank) else 0):
-        sel = order[rank == r]
-        cidx = flat[sel]                              # unique at a given rank
-        for k in range(8):
-            P[k, cidx] = P[k, cidx] + w[k, sel]
-    return P.reshape(8, nm, nm, nm)
+def fixed_point(w: np.ndarray) -> np.ndarray:
+    """q = rint(w * 2^32) as uint64 (w float32 in [0, 1]; the product is exact)."""
+    return np.rint(w.astype(np.float64) * FIX_SCALE).astype(np.uint64)
+
+
+def _node_index(cells: np.ndarray, k: int, nm: int) -> np.ndarray:
+    s = ((k >> 2) & 1, (k >> 1) & 1, k & 1)
+    return (((cells[0] + s[0]) % nm) * nm + (cells[1] + s[1]) % nm) * nm + (cells[2] + s[2]) % nm
+
+
+def _to_rho(S: np.ndarray) -> np.ndarray:
+    """float32(S) * 2^-32 with one rounding of S (exact through float64 below 2^53)."""
+    assert S.size == 0 or int(S.max()) < (1 << 53)
+    return (S.astype(np.float64).astype(F32) * F32(2.0 ** -32)).astype(F32)
+
+
+def _contrast(rho: np.ndarray, np_side: int, nm: int) -> np.ndarray:
+    c_inv = F32(nm ** 3 / np_side ** 3)
+    return ((rho * c_inv).astype(F32) - F32(1.0)).astype(F32)
+
+
+def node_sums(disp, np_side: int, nm: int, pid=None) -> np.ndarray:
+    """S(n) for every node (nm^3 uint64, flat C order) of the particles pid."""
+    cells, f = home_cells(disp, np_side, nm, pid)
+    q = fixed_point(weights(f))
+    S = np.zeros(nm ** 3, dtype=np.uint64)
+    for k in range(8):
+        np.add.at(S, _node_index(cells, k, nm), q[k])
+    return S
 
 
 def density(disp, np_side: int, nm: int, contrast=True) -> np.ndarray:
-    """rho (or delta) on the nm^3 mesh, float32, in the documented order."""
-    P = cell_partials(disp, np_side, nm)
-    rho = np.zeros((nm, nm, nm), dtype=F32)
-    for k in range(7, -1, -1):
-        s = ((k >> 2) & 1, (k >> 1) & 1, k & 1)
-        rho = rho + np.roll(P[k], shift=s, axis=(0, 1, 2))
-    if not contrast:
-        return rho
-    c_inv = F32(nm ** 3 / np_side ** 3)
-    return (rho * c_inv).astype(F32) - F32(1.0)
-
-
-def density_at_nodes(disp, np_side: int, nm: int, nodes: np.ndarray, contrast=True):
-    """Same result as ``density`` but only at the given nodes ((M, 3) int)."""
-    cells, f = home_cells(disp, np_side, nm)
-    w = weights(f)
-    flat = (cells[0] * nm + cells[1]) * nm + cells[2]
-    order = np.argsort(flat, kind="stable")
-    fs = flat[order]
-    out = np.empty(len(nodes), dtype=F32)
-    for j, n in enumerate(np.asarray(nodes)):
-        rho = F32(0.0)
-        for k in range(7, -1, -1):
-            s = np.array([(k >> 2) & 1, (k >> 1) & 1, k & 1])
-            c = np.mod(n - s, nm)
-            cf = (c[0] * nm + c[1]) * nm + c[2]
-            lo, hi = np.searchsorted(fs, cf, "left"), np.searchsorted(fs, cf, "right")
-            part = F32(0.0)
-            for p in order[lo:hi]:
-                part = F32(part + w[k, p])
-            rho = F32(rho + part)
-        out[j] = rho
-    if contrast:
-        c_inv = F32(nm ** 3 / np_side ** 3)
-        out = (out * c_inv).astype(F32) - F32(1.0)
-    return out
+    """rho (or delta) on the nm^3 mesh, float32."""
+    rho = _to_rho(node_sums(disp, np_side, nm)).reshape(nm, nm, nm)
+    return _contrast(rho, np_side, nm) if contrast else rho
 
 
 def density_at_nodes_chunked(disp, np_side: int, nm: int, nodes, contrast=True, chunk=1 << 26,
                              progress=None):
-    """``density_at_nodes`` for particle counts too large to hold every
-    temporary at once: particles are scanned in id order, ``chunk`` at a
-    time, keeping only those whose home cell feeds one of the nodes; the
-    kept ones (still in ascending id) then go through the same replay.
-    ``progress(done, total)`` is called after every chunk when given."""
-    nodes = np.asarray(nodes, dtype=np.int64)
-    feed = set()
-    for n in nodes:
-        for k in range(8):
-            s = np.array([(k >> 2) & 1, (k >> 1) & 1, k & 1])
-            c = np.mod(n - s, nm)
-            feed.add(int((c[0] * nm + c[1]) * nm + c[2]))
-    feed = np.array(sorted(feed), dtype=np.int64)
+    """The same result at the given nodes ((M, 3) int) only, scanning the
+    particles ``chunk`` at a time (for counts whose temporaries do not fit in
+    host memory at once).  ``progress(done, total)`` is called after every
+    chunk when given."""
+    nodes = np.asarray(nodes, dtype=np.int64).reshape(-1, 3)
+    want = (nodes[:, 0] * nm + nodes[:, 1]) * nm + nodes[:, 2]
+    uniq, inv = np.unique(want, return_inverse=True)
+    S = np.zeros(len(uniq), dtype=np.uint64)
     n_all = disp.shape[1]
-    keep_id, keep_cells, keep_f = [], [], []
     for a in range(0, n_all, chunk):
         b = min(n_all, a + chunk)
         pid = np.arange(a, b, dtype=np.int64)
         cells, f = home_cells(disp[:, a:b], np_side, nm, pid)
-        flat = (cells[0] * nm + cells[1]) * nm + cells[2]
-        pos = np.minimum(np.searchsorted(feed, flat), len(feed) - 1)
-        m = feed[pos] == flat
-        keep_id.append(pid[m])
-        keep_cells.append(cells[:, m])
-        keep_f.append(f[:, m])
+        q = fixed_point(weights(f))
+        for k in range(8):
+            idx = _node_index(cells, k, nm)
+            pos = np.minimum(np.searchsorted(uniq, idx), len(uniq) - 1)
+            m = uniq[pos] == idx
+            np.add.at(S, pos[m], q[k][m])
         if progress is not None:
             progress(b, n_all)
-    cells = np.concatenate(keep_cells, axis=1)
-    f = np.concatenate(keep_f, axis=1)
-    w = weights(f)
-    flat = (cells[0] * nm + cells[1]) * nm + cells[2]
-    order = np.argsort(flat, kind="stable")      # ids ascend within a cell
-    fs = flat[order]
-    out = np.empty(len(nodes), dtype=F32)
-    for j, n in enumerate(nodes):
-        rho = F32(0.0)
-        for k in range(7, -1, -1):
-            s = np.array([(k >> 2) & 1, (k >> 1) & 1, k & 1])
-            c = np.mod(n - s, nm)
-            cf = (c[0] * nm + c[1]) * nm + c[2]
-            lo, hi = np.searchsorted(fs, cf, "left"), np.searchsorted(fs, cf, "right")
-            part = F32(0.0)
-            for q in order[lo:hi]:
-                part = F32(part + w[k, q])
-            rho = F32(rho + part)
-        out[j] = rho
-    if contrast:
-        c_inv = F32(nm ** 3 / np_side ** 3)
-        out = (out * c_inv).astype(F32) - F32(1.0)
-    return out
+    rho = _to_rho(S)[inv]
+    return _contrast(rho, np_side, nm) if contrast else rho
 
+
+def density_at_nodes(disp, np_side: int, nm: int, nodes: np.ndarray, contrast=True):
+    """``density`` at the given nodes only ((M, 3) int)."""
+    return density_at_nodes_chunked(disp, np_side, nm, nodes, contrast, chunk=1 << 62)

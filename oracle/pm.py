@@ -7,9 +7,12 @@ Paper passages followed (Koda et al. 2015):
   Sec. 3.3: Cloud-in-Cell (CIC) mass assignment.
 
 Readings where the paper is silent:
-* CIC nodes sit at i * dx, dx = L/Nm.  A particle at mesh coordinate u
-  (periodic) has home cell i = floor(u), fraction f = u - i, and gives weight
-  prod_e w_{s_e}(f_e), w_0(f) = 1 - f, w_1(f) = f, to node i + s, s in {0,1}^3.
+* CIC nodes sit at cell centres, (i + 1/2) dx, dx = L/Nm.  A particle at
+  position x has node coordinate u = x / dx - 1/2 (periodic), home cell
+  i = floor(u), fraction f = u - i, and gives weight prod_e w_{s_e}(f_e),
+  w_0(f) = 1 - f, w_1(f) = f, to node i + s, s in {0,1}^3.  (With nodes at
+  i dx every lattice particle of a mesh 2x or 3x the particle grid would sit
+  exactly on a node, on the kink of the CIC kernel.)
 * Green's function -1/k^2 (continuous), spectral gradient i k, no CIC
   deconvolution in the force, k = 0 -> 0, and the gradient component k_d is
   zeroed on the Nyquist plane of axis d.

@@ -5,13 +5,21 @@
 // One workgroup owns a 16^3 tile of nodes.  The cells that feed those nodes
 // are the tile's 16^3 cells plus the one-cell layer below it on each axis
 // (a 17^3 region); their particles come from the tile's buckets and from the
-// face/edge/corner buckets of the 7 lower neighbour tiles.  Particles are
-// keyed (region cell, particle id, LDS slot) and sorted in LDS, so each
+// face/edge/corner buckets of the 7 lower neighbour tiles.
+//
+// Mass (k_deposit_mass): every weight is taken to 64-bit fixed point,
+// q = rint(w 2^32), and the tile's nodes add them with integer LDS atomics;
+// the integer sum is exact, so the node mass float32(sum) 2^-32 does not
+// depend on the order of the particles, the buckets or the workgroups.  The
+// particles are streamed, never held, so a region of any size takes one pass.
+//
+// Weighted deposits (k_deposit, NC = 3: the transpose of the
+// three-component readout; weights of either sign and any size): particles
+// are keyed (region cell, particle id, LDS slot) and sorted in LDS, so each
 // cell's 8 partial sums add its particles' weights in ascending id.  Nodes
 // then receive the partial sums of their 8 source cells in ascending
 // source-cell order, in 8 phases (offset k = 7 .. 0) that are each
-// conflict-free (distinct cells -> distinct nodes).  The result is independent of launch
-// order, atomics and the order inside the buckets.  Regions holding more
+// conflict-free (distinct cells -> distinct nodes).  Regions holding more
 // particles than fit in LDS are processed in contiguous ranges of their
 // cells (halved until they fit), a single overfull cell by an ordered
 // selection, keeping the same order.
@@ -370,26 +378,14 @@ __device__ void accumulate_select(S& sh, const float* __restrict__ disp,
   }
 }
 
-template <int NC, int CAP, int kDT>
-__global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
-                                                 const uint32_t* __restrict__ perm,
-                                                 const uint32_t* __restrict__ off, int np, int nm,
-                                                 float dscale, long np3, float* __restrict__ out,
-                                                 long row_stride, long mesh_stride, int contrast,
-                                                 float cinv, const float* __restrict__ wt,
-                                                 long mstride) {
-  __shared__ DepShared<NC, CAP, kDT> sh;
-  disp = mock_ptr(disp, mstride);
-  perm = mock_ptr(perm, mstride);
-  off = mock_ptr(off, mstride);
-  out = mock_ptr(out, mstride);
-  if (wt) wt = mock_ptr(wt, mstride);
-  constexpr uint32_t kCap = CAP;
-  const int nt = nm / kTile;
-  const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
-  const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
-  const int t0[3] = {tx * kTile, ty * kTile, tz * kTile};
-
+// The region's particles as up to kMaxSeg segments of the permutation, in
+// a fixed order: thread nb < 8 takes the buckets of source tile
+// (tx, ty, tz) - (dx, dy, dz), nb = 4 dx + 2 dy + dz, whose face class covers
+// the offset bits; empty segments are dropped and seg_pre holds the
+// particles before each (one index space of seg_total particles).  Ends
+// with a barrier.
+template <class S>
+__device__ void setup_segments(S& sh, const uint32_t* __restrict__ off, int tx, int ty, int tz, int nt) {
   // Bucket offsets of the source tiles (tx-dx, ty-dy, tz-dz), one per thread.
   if (threadIdx.x < 72) {
     const int nb = threadIdx.x / 9, q = threadIdx.x - nb * 9;
@@ -400,9 +396,6 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
     if (uz < 0) uz += nt;
     sh.offs[nb][q] = off[(((uint32_t)ux * nt + uy) * nt + uz) * 8u + q];
   }
-  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT)
-#pragma unroll
-    for (int q = 0; q < NC; ++q) sh.rho[q][i] = 0.0f;
   __syncthreads();
   // Segments: thread nb < 8 takes the buckets of source tile nb whose face
   // class covers the required offset bits.
@@ -450,6 +443,32 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
     }
   }
   __syncthreads();
+}
+
+template <int NC, int CAP, int kDT>
+__global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
+                                                 const uint32_t* __restrict__ perm,
+                                                 const uint32_t* __restrict__ off, int np, int nm,
+                                                 float dscale, long np3, float* __restrict__ out,
+                                                 long row_stride, long mesh_stride, int contrast,
+                                                 float cinv, const float* __restrict__ wt,
+                                                 long mstride) {
+  __shared__ DepShared<NC, CAP, kDT> sh;
+  disp = mock_ptr(disp, mstride);
+  perm = mock_ptr(perm, mstride);
+  off = mock_ptr(off, mstride);
+  out = mock_ptr(out, mstride);
+  if (wt) wt = mock_ptr(wt, mstride);
+  constexpr uint32_t kCap = CAP;
+  const int nt = nm / kTile;
+  const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
+  const int t0[3] = {tx * kTile, ty * kTile, tz * kTile};
+
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) sh.rho[q][i] = 0.0f;
+  setup_segments(sh, off, tx, ty, tz, nt);
 
   // The region's cells in contiguous ranges [lo, hi) of the cell index,
   // taken in increasing order; a range holding more than kCap particles is
@@ -496,12 +515,97 @@ __global__ __launch_bounds__(kDT) void k_deposit(const float* __restrict__ disp,
   }
 }
 
-// 256 threads; 512 particles in LDS (27 KB, five tiles per compute unit)
-// where a tile averages at most 256 particles (a mesh 3x the particle grid
-// has about 150), else 1024 (39 KB, four tiles).  Measured: 512 threads /
-// 2048 particles (62 KB, two tiles) was slower on every mesh; 512 against
-// 1024 saves 13% on the 768^3 mesh of 256^3 particles.  Fuller regions take
-// the range-splitting path.  The result does not depend on the shape.
+// Fixed-point mass deposit: node masses in units of 2^-32 particle masses.
+struct MassShared {
+  unsigned long long acc[kTile * kTile * kTile];   // 32 KB
+  uint32_t seg_start[kMaxSeg], seg_len[kMaxSeg];
+  uint32_t seg_pre[kMaxSeg];
+  uint32_t seg_total;
+  uint32_t offs[8][9];
+  int nseg;
+};
+
+constexpr float kFixScale = 4294967296.0f;           // 2^32
+constexpr float kFixInv = 2.3283064365386963e-10f;   // 2^-32
+constexpr int kMassG = 4;                            // particles in flight per thread
+
+template <int kDT>
+__global__ __launch_bounds__(kDT) void k_deposit_mass(const float* __restrict__ disp,
+                                                      const uint32_t* __restrict__ perm,
+                                                      const uint32_t* __restrict__ off, int np, int nm,
+                                                      float dscale, long np3, float* __restrict__ out,
+                                                      long row_stride, int contrast, float cinv,
+                                                      long mstride) {
+  __shared__ MassShared sh;
+  disp = mock_ptr(disp, mstride);
+  perm = mock_ptr(perm, mstride);
+  off = mock_ptr(off, mstride);
+  out = mock_ptr(out, mstride);
+  const int nt = nm / kTile;
+  const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
+  const int t0[3] = {tx * kTile, ty * kTile, tz * kTile};
+  for (int i = threadIdx.x; i < kTile * kTile * kTile; i += kDT) sh.acc[i] = 0ull;
+  setup_segments(sh, off, tx, ty, tz, nt);
+
+  const uint32_t total = sh.seg_total;
+  const int nseg = sh.nseg;
+  for (uint32_t base = 0; base < total; base += kMassG * kDT) {
+    uint32_t ids[kMassG];
+#pragma unroll
+    for (int g = 0; g < kMassG; ++g) {
+      const uint32_t x = base + g * kDT + threadIdx.x;
+      ids[g] = 0xffffffffu;
+      if (x < total) {
+        int sg = 0;  // last segment with seg_pre <= x
+#pragma unroll
+        for (int step = kMaxSeg / 2; step > 0; step >>= 1)
+          if (sg + step < nseg && sh.seg_pre[sg + step] <= x) sg += step;
+        ids[g] = perm[sh.seg_start[sg] + (x - sh.seg_pre[sg])];
+      }
+    }
+    int c[kMassG][3];
+    float f[kMassG][3];
+#pragma unroll
+    for (int g = 0; g < kMassG; ++g)
+      if (ids[g] != 0xffffffffu) home_cell(disp, np3, ids[g], np, nm, dscale, c[g], f[g]);
+#pragma unroll
+    for (int g = 0; g < kMassG; ++g) {
+      if (ids[g] == 0xffffffffu) continue;
+      // region coordinates 0..16; the tile's nodes are region 1..16, and a
+      // cell at r feeds nodes r and r + 1, i.e. tile nodes r - 1 and r
+      const int rx = region_coord(c[g][0], t0[0], nm), ry = region_coord(c[g][1], t0[1], nm),
+                rz = region_coord(c[g][2], t0[2], nm);
+      if (rx >= kReg || ry >= kReg || rz >= kReg) continue;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int nx = rx + ((k >> 2) & 1) - 1, ny = ry + ((k >> 1) & 1) - 1, nz = rz + (k & 1) - 1;
+        if (nx < 0 || nx >= kTile || ny < 0 || ny >= kTile || nz < 0 || nz >= kTile) continue;
+        const unsigned long long q = __float2ull_rn(__fmul_rn(cic_weight(f[g], k), kFixScale));
+        atomicAdd(&sh.acc[(nx * kTile + ny) * kTile + nz], q);
+      }
+    }
+  }
+  __syncthreads();
+
+  // four consecutive z nodes per thread and store (rows of the padded
+  // layout and tile origins are 16-byte aligned)
+  for (int qd = threadIdx.x; qd < kTile * kTile * kTile / 4; qd += kDT) {
+    const int nn = qd * 4;
+    const int nx = nn / (kTile * kTile), ny = (nn / kTile) % kTile, nz = nn % kTile;
+    const long o = ((long)(t0[0] + nx) * nm + (t0[1] + ny)) * row_stride + (t0[2] + nz);
+    float r[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      r[j] = __fmul_rn(__ull2float_rn(sh.acc[nn + j]), kFixInv);
+      if (contrast) r[j] = __fsub_rn(__fmul_rn(r[j], cinv), 1.0f);
+    }
+    *reinterpret_cast<float4*>(out + o) = make_float4(r[0], r[1], r[2], r[3]);
+  }
+}
+
+// One 256-thread workgroup per tile, 33 KB of LDS (four tiles per compute
+// unit).  The result does not depend on the shape.
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off, int np, int nm,
                     float dscale, float* out, long row_stride, int contrast, hipStream_t s,
                     int nmock, long mstride) {
@@ -509,13 +613,8 @@ void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off
   const int nt = nm / kTile;
   const long ntiles = (long)nt * nt * nt;
   const float cinv = (float)((double)nm * nm * nm / (double)np3);
-  const dim3 grid((unsigned)ntiles, 1, (unsigned)nmock);
-  if (np3 <= 256 * ntiles)
-    hipLaunchKernelGGL((k_deposit<1, 512, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
-                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
-  else
-    hipLaunchKernelGGL((k_deposit<1, 1024, 256>), grid, dim3(256), 0, s, disp, perm, off, np, nm, dscale,
-                       np3, out, row_stride, 0L, contrast, cinv, nullptr, mstride);
+  hipLaunchKernelGGL(k_deposit_mass<256>, dim3((unsigned)ntiles, 1, (unsigned)nmock), dim3(256), 0, s, disp,
+                     perm, off, np, nm, dscale, np3, out, row_stride, contrast, cinv, mstride);
 }
 
 void launch_deposit3_weighted(const float* disp, const uint32_t* perm, const uint32_t* off, int np,

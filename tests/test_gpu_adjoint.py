@@ -1,9 +1,10 @@
 """GPU adjoint against the FP64 oracle adjoint (finite-difference configuration
 16^3 particles / 32^3 mesh / 37.5 Mpc/h and the 32^3 / 64^3 small run)."""
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -13,11 +14,6 @@ from oracle import adjoint, cola, ic, pk, pm  # noqa: E402
 from paper_1507_05329_amd.inputs import bbks_table, seeded_normal, step_edges, white_noise  # noqa: E402
 
 NP, NM, L = 16, 32, 37.5
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def dev(a):

@@ -6,10 +6,11 @@ particles/mesh; a 32^3/64^3 group too), distinct seeds and boxes.  Between
 graph replays the test does eager work of its own (state reads, a density)
 and synchronises, so every replay is checked against direct launches.
 """
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -28,11 +29,6 @@ SPECS = [
     dict(np=32, nmesh=64, box=120.0, seed=107),
     dict(np=96, nmesh=192, box=260.0, seed=108),
 ]
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def state_of(sim):

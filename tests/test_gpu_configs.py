@@ -10,10 +10,11 @@ against the GPU itself or at other sizes.
   300 Mpc/h: PM force at an evolved state, the 10-step P(k) and one adjoint
   step against the oracle.
 """
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -23,11 +24,6 @@ from oracle import adjoint, cola, cosmology as cosmo, ic, pk, pm  # noqa: E402
 from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges, white_noise  # noqa: E402
 
 OM = 0.27
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def dev(a):

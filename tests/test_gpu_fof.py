@@ -6,10 +6,11 @@ shares the label.
 
 All compute goes through the C ABI (paper_1507_05329_amd.sim -> libcola.so).
 """
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -18,11 +19,6 @@ torch = pytest.importorskip("torch")
 from oracle import fof  # noqa: E402
 from paper_1507_05329_amd._lib import ColaError  # noqa: E402
 from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges, white_noise  # noqa: E402
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def evolved_sim(np_side, nm, box, seed, nsteps=10):

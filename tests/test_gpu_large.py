@@ -8,11 +8,12 @@ nodes (densest, emptiest, random) against the FP32 same-order replay,
 mass conservation, a finite state after every step, and large-scale growth
 of P(k) by D1^2.
 """
-import sys
 import time
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,11 +22,6 @@ torch = pytest.importorskip("torch")
 from oracle import cic_fp32, cosmology as cosmo  # noqa: E402
 from paper_1507_05329_amd import _lib  # noqa: E402
 from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges  # noqa: E402
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.mark.timeout(1200)

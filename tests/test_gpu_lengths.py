@@ -12,10 +12,11 @@
   every element on the device.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -25,11 +26,6 @@ from oracle import cosmology as cosmo, pm  # noqa: E402
 
 BOX = 100.0
 OM = 0.27
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def padded_cols(n):

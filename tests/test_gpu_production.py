@@ -5,10 +5,11 @@ Same launch configuration as bench.py.  The oracle checks sampled outputs
 the 10-step power spectrum is compared against an FP64 oracle run of the
 same size (slow: minutes of host CPU).
 """
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -19,11 +20,6 @@ from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges, white_n
 
 CFG = CONFIGS["production"]
 NP, NM, L = CFG.np_side, CFG.nmesh, CFG.box
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")

@@ -5,10 +5,11 @@ against the oracle, and the convergence of P(k) with the number of steps.
 
 All compute goes through the C ABI (paper_1507_05329_amd.sim -> libcola.so).
 """
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -18,11 +19,6 @@ from oracle import cola, pk  # noqa: E402
 from paper_1507_05329_amd.inputs import bbks_table, white_noise  # noqa: E402
 
 NP, NM, L = 32, 64, 100.0
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def pk_edges():

@@ -2,10 +2,11 @@
 
 All compute goes through the C ABI (paper_1507_05329_amd.sim -> libcola.so).
 """
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -17,11 +18,6 @@ from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, white_noise, step_e
 
 NP, NM, L = 32, 64, 100.0
 OM = 0.27
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module")

@@ -6,10 +6,11 @@ formed in FP64 from the GPU's state and its force (cola_force).
 
 All compute goes through the C ABI (paper_1507_05329_amd.sim -> libcola.so).
 """
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -20,11 +21,6 @@ from paper_1507_05329_amd._lib import ColaError  # noqa: E402
 from paper_1507_05329_amd.inputs import CONFIGS, bbks_table, step_edges, white_noise  # noqa: E402
 
 OM, NLPT = 0.27, -2.5
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def rel_l2(a, b):

@@ -1,5 +1,6 @@
-"""Pins for the float32 same-order CIC replay."""
+"""Pins for the float32 replay of the fixed-point CIC mass deposit."""
 import itertools
+from fractions import Fraction
 
 import numpy as np
 
@@ -24,26 +25,53 @@ def test_replay_matches_fp64_deposit():
     assert abs(float(rho.astype(np.float64).sum()) - np_side ** 3) < 1e-5 * np_side ** 3
 
 
-def test_replay_against_scalar_loop():
-    # Literal scalar float32 loop over nodes, offsets and particles.
+def _round_to_f32(x: Fraction) -> np.float32:
+    """Correctly rounded (to nearest, ties to even) float32 of a non-negative rational."""
+    if x == 0:
+        return F32(0.0)
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    if Fraction(2) ** e > x:
+        e -= 1
+    scaled = x / Fraction(2) ** (e - 23)             # in [2^23, 2^24)
+    m = scaled.numerator // scaled.denominator
+    rest = scaled - m
+    if rest > Fraction(1, 2) or (rest == Fraction(1, 2) and m % 2 == 1):
+        m += 1
+    return F32(float(Fraction(m) * Fraction(2) ** (e - 23)))
+
+
+def test_node_mass_is_the_correctly_rounded_exact_sum_of_the_weights():
+    # With every float32 weight >= 2^-9 (fractions kept in [0.15, 0.85]) the
+    # node mass is the exact rational sum of its float32 weights, rounded
+    # once to float32 -- whatever order the particles come in.
     np_side, nm = 4, 8
-    disp = random_disp(np_side, nm, 1.5, 1)
-    disp[:, 5] = disp[:, 9]                     # several particles in one cell
-    disp[:, 6] = disp[:, 9] + F32(1e-3)
-    rho = cic_fp32.density(disp, np_side, nm, contrast=False)
+    rng = np.random.default_rng(1)
+    base = cic_fp32._axis_terms(np_side, nm)[1][0]          # -1/2 on a 2x mesh
+    lat = np.stack(np.meshgrid(*([np.arange(np_side)] * 3), indexing="ij")).reshape(3, -1) * (nm // np_side)
+    target = rng.integers(0, nm, (3, np_side ** 3)) + rng.uniform(0.15, 0.85, (3, np_side ** 3))
+    target[:, 5:12] = target[:, 4:5]                          # several particles in one cell
+    target[:, 6] += 1e-3
+    disp = (target - lat - base).astype(F32)
     cells, f = cic_fp32.home_cells(disp, np_side, nm)
-    for n in itertools.product(range(nm), repeat=3):
-        acc = F32(0.0)
-        for k in range(7, -1, -1):           # source cells in ascending index
+    assert f.min() > 0.1 and f.max() < 0.9
+    w = cic_fp32.weights(f)
+    assert w.min() >= 2.0 ** -9
+    exact = {}
+    for p in range(np_side ** 3):
+        for k in range(8):
             s = ((k >> 2) & 1, (k >> 1) & 1, k & 1)
-            c = [(n[e] - s[e]) % nm for e in range(3)]
-            part = F32(0.0)
-            for p in range(np_side ** 3):
-                if all(cells[e, p] == c[e] for e in range(3)):
-                    w = [[F32(1.0) - f[e, p], f[e, p]] for e in range(3)]
-                    part = F32(part + F32(F32(w[0][s[0]] * w[1][s[1]]) * w[2][s[2]]))
-            acc = F32(acc + part)
-        assert acc.tobytes() == rho[n].tobytes(), n
+            n = tuple(int((cells[e, p] + s[e]) % nm) for e in range(3))
+            exact[n] = exact.get(n, Fraction(0)) + Fraction(float(w[k, p]))
+    rho = cic_fp32.density(disp, np_side, nm, contrast=False)
+    for n in itertools.product(range(nm), repeat=3):
+        want = _round_to_f32(exact.get(n, Fraction(0)))
+        assert want.tobytes() == rho[n].tobytes(), n
+
+
+def test_fixed_point_weights_round_to_nearest_even():
+    w = np.array([1.0, 0.5, 2.0 ** -9, 2.0 ** -33, 3 * 2.0 ** -33, 2.0 ** -34, 0.0], dtype=F32)
+    q = cic_fp32.fixed_point(w)
+    assert q.tolist() == [2 ** 32, 2 ** 31, 2 ** 23, 0, 2, 0, 0]
 
 
 def test_node_sampled_replay_equals_full_replay():

@@ -3,10 +3,11 @@ sort buffers in a static device array) against cola_density_of through the
 C ABI: bitwise equal on two calls in a row, the second smaller than the
 first, and the FP32 same-order replay of the oracle."""
 import ctypes as C
-import sys
 
 import numpy as np
 import pytest
+
+from _progress import say
 
 pytestmark = pytest.mark.gpu
 
@@ -14,11 +15,6 @@ torch = pytest.importorskip("torch")
 
 from oracle import cic_fp32  # noqa: E402
 from paper_1507_05329_amd import _lib  # noqa: E402
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def noalloc_density(disp, np_side, nm):
