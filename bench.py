@@ -279,6 +279,10 @@ def batch_leg(steps, table, dev):
     e = step_edges()
     n_part = sum(c.n_particles for c in cfgs)
     b = ColaBatch([dict(np=c.np_side, nmesh=c.nmesh, box=c.box) for c in cfgs], device=dev)
+    tuned = {}
+    for m, c in zip(b.mocks, cfgs):
+        if c.nmesh not in tuned:
+            tuned[c.nmesh] = m.autotune(reps=3)[0]
     for m, c in zip(b.mocks, cfgs):
         m.init_2lpt(c.seed, *table)
     b.step(e[0], e[1])                      # warm-up; captures the graph
@@ -317,7 +321,8 @@ def batch_leg(steps, table, dev):
             "ms_per_step": t_batch / steps * 1e3,
             "sequential_value": n_part * steps / t_seq,
             "sequential_ms_per_step": t_seq / steps * 1e3,
-            "speedup": t_seq / t_batch}
+            "speedup": t_seq / t_batch,
+            "fft_block_order": {str(k): v for k, v in tuned.items()}}
 
 
 def adjoint_leg(sim, cfg, table, e, steps):
@@ -429,6 +434,10 @@ def workload_block(cfg, steps, warmup, dev, with_adjoint, with_outputs, lean):
                   a_init=cfg.a_init, device=dev)
     out = {}
     try:
+        best, ms = sim.autotune(reps=3)
+        out["fft_schedule"] = {"n": cfg.nmesh, "block_order": best,
+                               "ms_by_pass_and_order": {f"{k}/{o}": round(v, 4) for (k, o), v in ms.items()}}
+        log(f"{cfg.np_side}^3/{cfg.nmesh}^3: autotune {best} {ms}")
         if warmup:
             cycled_steps(sim, cfg, table, e, warmup)
         log(f"{cfg.np_side}^3/{cfg.nmesh}^3: {warmup} warm-up steps done")
@@ -589,6 +598,7 @@ def main():
                                "before every pass of 10 steps"},
         "fwd_adjoint": main_block.get("fwd_adjoint"),
         "fwd_adjoint_kept": main_block.get("fwd_adjoint_kept"),
+        "fft_schedule": main_block.get("fft_schedule"),
         "stages": main_block["stages"],
         "roofline": main_block["roofline"],
         "pk_parity": pk_parity_note(cfg),

@@ -374,6 +374,35 @@ int cola_init_2lpt_adjoint(cola_ctx* ctx, const float* dev_noise, const float* d
  * K (kick factor), I (drift factor), a_h, D1(a1), D2(a1). */
 int cola_step_scalars(const cola_params* p, double a_x, double a_v, double a1, double* out);
 
+/* FFT schedules.  A column pass (the y and x passes: transforms along
+ * strided axes) launches one workgroup per block of W adjacent columns of a
+ * plane.  Block order 1 hands each XCD (eight per device, each with its own
+ * L2) a contiguous range of blocks, so neighbouring columns share an L2;
+ * block order 0 keeps the hardware's round-robin assignment of workgroups
+ * to XCDs.  The setting is process-wide per transform length n (a compiled
+ * size) and pass kind: COLA_PASS_PLAIN (plain forward and inverse column
+ * passes), COLA_PASS_GREEN (the x pass of the PM step: forward transform,
+ * Green's function x ik, two inverse transforms), COLA_PASS_GRAD (the
+ * inverse y pass giving the y and z force components).  It never changes a
+ * result: each column is transformed by the same code on the same data,
+ * only the workgroup that does it differs.  Default 1.  COLA_EINVAL for an
+ * unknown length, kind or order. */
+#define COLA_PASS_PLAIN 0
+#define COLA_PASS_GREEN 1
+#define COLA_PASS_GRAD  2
+int cola_fft_set_schedule(int32_t n, int32_t pass, int32_t order);   /* order 0 or 1 */
+int cola_fft_get_schedule(int32_t n, int32_t pass, int32_t* order);
+
+/* Autotuner: times the three column-pass kinds of the PM step at the
+ * context's mesh length (in the step's mesh layout) with block order 1 and
+ * 0, reps launches each after one warm-up (HIP events on the context's
+ * stream), and keeps the faster of each in the schedule table.  Uses the
+ * context's meshes as scratch (the particle state is not touched).
+ * Synchronises.  best (may be NULL, 3 entries, by pass kind) receives the
+ * choices, ms (may be NULL, 6 entries: kind-major, order 0 then 1) the time
+ * per launch of each candidate. */
+int cola_autotune(cola_ctx* ctx, int32_t reps, int32_t* best, double* ms);
+
 /* Under COLA_F_STAGE_TIMERS: synchronises, then writes per-stage totals
  * (milliseconds, summed over the steps since the last call) to
  * ms[COLA_NSTAGE] and the launch count per stage to count[COLA_NSTAGE]

@@ -23,6 +23,7 @@ COLA_ENONFINITE = -6
 COLA_F_CHECK_FINITE = 1
 COLA_F_STAGE_TIMERS = 2
 COLA_F_D2_ODE = 4
+PASS_PLAIN, PASS_GREEN, PASS_GRAD = 0, 1, 2
 STAGES = ["sort", "deposit", "fft_z", "fft_y", "fft_x_green", "ifft_y", "ifft_z", "kick_drift",
           "ifft_y_grad", "velocity"]
 
@@ -76,6 +77,9 @@ _SIGS = {
     "cola_step_keep": (C.c_int, [_P, _D, _D, _P]),
     "cola_step_adjoint_kept": (C.c_int, [_P, _D, _D, _D, _P, _P, _P, _P, _P, _P]),
     "cola_synchronize": (C.c_int, [_P]),
+    "cola_fft_set_schedule": (C.c_int, [_I, _I, _I]),
+    "cola_fft_get_schedule": (C.c_int, [_I, _I, C.POINTER(C.c_int32)]),
+    "cola_autotune": (C.c_int, [_P, _I, C.POINTER(C.c_int32), _DP]),
     "cola_batch_workspace_query": (C.c_int, [C.POINTER(cola_params), _I, C.POINTER(C.c_size_t)]),
     "cola_batch_create": (C.c_int, [C.POINTER(cola_params), _I, _P, C.c_size_t, _P, C.POINTER(_P)]),
     "cola_batch_destroy": (C.c_int, [_P]),

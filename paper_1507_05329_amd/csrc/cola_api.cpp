@@ -193,47 +193,58 @@ double green_scale(int nm, double alpha) { return alpha * nm / (2.0 * kPi) / ((d
 // y pass turns the second into the y and z components (k_y and k_z are
 // constant along x, so phi needs only two inverse x transforms).  The Green
 // scale is read from the device coefficients c->coef (set by set_coef).
-// The spectral part alone: c->mesh[0] holds delta on entry (padded r2c layout).
+// The PM force pipeline keeps its three meshes row-interleaved: row (x, y)
+// of mesh c starts at complex value (3 (x nm + y) + c) padded_cols, so the
+// last (c2r) pass can write the force field interleaved by node in place:
+// (g_x, g_y, g_z) of node (x, y, z) at floats (x nm + y) 6 padded_cols + 3 z.
+long pm_rowc(int nm) { return 3 * padded_cols(nm); }        // complex values per row
+long force_row_stride(int nm) { return 6 * padded_cols(nm); }  // floats per row of the force field
+const float* force_field(cola_ctx* c) { return reinterpret_cast<const float*>(c->mesh[0]); }
+
+// The spectral part alone: delta on entry in the rows of mesh 0 (row stride
+// pm_rowc), the force field interleaved by node on exit.
 void fft_forces(cola_ctx* c, int nmock = 1, long mstride = 0) {
   const int nm = c->p.nmesh;
+  const long P = padded_cols(nm), rowc = pm_rowc(nm);
+  float2* m0 = c->mesh[0];
   {
     StageTimer t(c, COLA_STAGE_FFT_Z);
-    fft_r2c_z(c->mesh[0], nm, 1, 0, c->tw, c->stream, nmock, mstride);
+    fft_r2c_z(m0, nm, 1, 0, c->tw, c->stream, nmock, mstride, rowc);
   }
   {
     StageTimer t(c, COLA_STAGE_FFT_Y);
-    fft_y(c->mesh[0], nm, 1, 0, 0, c->tw, c->stream, nmock, mstride);
+    fft_y(m0, nm, 1, 0, 0, c->tw, c->stream, nmock, mstride, rowc);
   }
   XPassArgs a;
-  a.in = c->mesh[0];
-  a.out[0] = c->mesh[0];
-  a.out[1] = c->mesh[1];
+  a.in = m0;
+  a.out[0] = m0;
+  a.out[1] = m0 + P;
   a.mode = X_FWD_GREEN;
   a.coef = c->coef;
   a.nmock = nmock;
   a.mstride = mstride;
+  a.rowc = rowc;
   {
     StageTimer t(c, COLA_STAGE_FFT_X);
     fft_x(a, nm, c->tw, c->stream);
   }
   {
     StageTimer t(c, COLA_STAGE_IFFT_Y);
-    fft_y(c->mesh[0], nm, 1, 0, 1, c->tw, c->stream, nmock, mstride);
+    fft_y(m0, nm, 1, 0, 1, c->tw, c->stream, nmock, mstride, rowc);
   }
   {
     StageTimer t(c, COLA_STAGE_IFFT_Y_GRAD);
-    fft_y_grad_yz(c->mesh[1], c->mesh[2], nm, c->tw, c->stream, nmock, mstride);
+    fft_y_grad_yz(m0 + P, m0 + 2 * P, nm, c->tw, c->stream, nmock, mstride, rowc);
   }
   {
     StageTimer t(c, COLA_STAGE_IFFT_Z);
-    fft_c2r_z(c->mesh[0], nm, 3, c->mesh_stride, c->tw, c->stream, nmock, mstride);
+    fft_c2r_z_forces(m0, nm, c->tw, c->stream, nmock, mstride);
   }
 }
 
 void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 0) {
   const int nm = c->p.nmesh;
-  const long rs = 2 * padded_cols(nm);
-  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), rs, 1, disp, nmock, mstride);
+  deposit(c, nm, reinterpret_cast<float*>(c->mesh[0]), 2 * pm_rowc(nm), 1, disp, nmock, mstride);
   fft_forces(c, nmock, mstride);
 }
 
@@ -241,11 +252,9 @@ void force_meshes(cola_ctx* c, const float* disp, int nmock = 1, long mstride = 
 // sequence a batch captures into one graph.  Uses the coefficients in c->coef.
 void step_launches(cola_ctx* c, int nmock, long mstride) {
   force_meshes(c, c->disp, nmock, mstride);
-  const long rs = 2 * padded_cols(c->p.nmesh);
   StageTimer t(c, COLA_STAGE_KICKDRIFT);
-  launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
-                            reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
-                            c->psi2, c->p.np, c->p.nmesh, c->coef, nullptr, c->stream, nmock, mstride);
+  launch_readout_kick_drift(force_field(c), force_row_stride(c->p.nmesh), c->disp, c->vres, c->psi1, c->psi2,
+                            c->p.np, c->p.nmesh, c->coef, nullptr, c->stream, nmock, mstride);
 }
 
 bool same_a(double a, double b) { return std::fabs(a - b) <= 1e-12 * (std::fabs(a) > 1 ? std::fabs(a) : 1.0); }
@@ -511,10 +520,8 @@ int cola_force(cola_ctx* c, float* out) {
   v.gscale = (float)green_scale(c->p.nmesh, 1.5 * c->p.omega_m / c->a_x);
   launch_set_coef(c->coef, v, 1, 0, c->stream);
   force_meshes(c, c->disp);
-  const long rs = 2 * padded_cols(c->p.nmesh);
-  launch_readout_kick_drift(reinterpret_cast<float*>(c->mesh[0]), reinterpret_cast<float*>(c->mesh[1]),
-                            reinterpret_cast<float*>(c->mesh[2]), rs, c->disp, c->vres, c->psi1,
-                            c->psi2, c->p.np, c->p.nmesh, c->coef, out, c->stream);
+  launch_readout_kick_drift(force_field(c), force_row_stride(c->p.nmesh), c->disp, c->vres, c->psi1, c->psi2,
+                            c->p.np, c->p.nmesh, c->coef, out, c->stream);
   LAUNCH_CHECK(c, "cola_force");
   return COLA_OK;
 }
@@ -523,15 +530,14 @@ int cola_pm_gradient(cola_ctx* c, double a, const float* delta, float* g0, float
   if (!c || !delta) return fail(c, COLA_EINVAL, "null argument");
   if (!(a > 0) || !std::isfinite(a)) return fail(c, COLA_EINVAL, "a must be positive and finite");
   const int nm = c->p.nmesh;
-  const long rs = 2 * padded_cols(nm);
   StepCoef v{};
   v.gscale = (float)green_scale(nm, 1.5 * c->p.omega_m / a);
   launch_set_coef(c->coef, v, 1, 0, c->stream);
-  launch_copy_to_mesh(delta, nm, reinterpret_cast<float*>(c->mesh[0]), rs, c->stream);
+  launch_copy_to_mesh(delta, nm, reinterpret_cast<float*>(c->mesh[0]), 2 * pm_rowc(nm), c->stream);
   fft_forces(c);
   float* g[3] = {g0, g1, g2};
   for (int d = 0; d < 3; ++d)
-    if (g[d]) launch_copy_from_mesh(reinterpret_cast<const float*>(c->mesh[d]), nm, rs, g[d], 1.0f, c->stream);
+    if (g[d]) launch_copy_from_mesh(force_field(c) + d, nm, force_row_stride(nm), g[d], 1.0f, c->stream, 3);
   LAUNCH_CHECK(c, "cola_pm_gradient");
   return COLA_OK;
 }
@@ -540,7 +546,7 @@ namespace {
 
 // Coefficients of the velocity at the position time; runs the force pipeline
 // into the force meshes (g) when the kick from a_v to a_x is not zero.
-VelCoef velocity_coef_and_forces(cola_ctx* c, const float* g[3]) {
+VelCoef velocity_coef_and_forces(cola_ctx* c, const float** g) {
   const double om = c->p.omega_m, n = c->p.n_lpt, a = c->a_x;
   const double adot = a * hubble_E(a, om), alpha = 1.5 * om / a;
   const double D1 = growth_D1(a, om), D2 = D2_of(&c->p, a);
@@ -551,13 +557,13 @@ VelCoef velocity_coef_and_forces(cola_ctx* c, const float* g[3]) {
   k.u1 = (float)(a * a * adot * growth_D1_prime(a, om) - K * alpha * D1);
   k.u2 = (float)(a * a * adot * D2_prime_of(&c->p, a) - K * alpha * (D2 - D1 * D1));
   k.rsd = (float)(1.0 / (a * adot));
-  g[0] = g[1] = g[2] = nullptr;
+  *g = nullptr;
   if (K != 0.0) {
     StepCoef v{};
     v.gscale = (float)green_scale(c->p.nmesh, alpha);
     launch_set_coef(c->coef, v, 1, 0, c->stream);
     force_meshes(c, c->disp);
-    for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<const float*>(c->mesh[d]);
+    *g = force_field(c);
   }
   return k;
 }
@@ -569,11 +575,11 @@ int cola_velocity(cola_ctx* c, float* vel, float* sdisp, int32_t axis) {
   if (!c->have_state) return fail(c, COLA_ESTATE, "no particle state");
   if (sdisp && (axis < 0 || axis > 2)) return fail(c, COLA_EINVAL, "rsd_axis must be 0, 1 or 2");
   if (sdisp == vel) return fail(c, COLA_EINVAL, "dev_vel and dev_sdisp must differ");
-  const float* g[3];
-  const VelCoef k = velocity_coef_and_forces(c, g);
+  const float* g;
+  const VelCoef k = velocity_coef_and_forces(c, &g);
   {
     StageTimer t(c, COLA_STAGE_VELOCITY);
-    launch_velocity(g[0], g[1], g[2], 2 * padded_cols(c->p.nmesh), c->disp, c->vres, c->psi1, c->psi2, c->p.np,
+    launch_velocity(g, force_row_stride(c->p.nmesh), c->disp, c->vres, c->psi1, c->psi2, c->p.np,
                     c->p.nmesh, k, vel, sdisp, axis, c->stream);
   }
   LAUNCH_CHECK(c, "cola_velocity");
@@ -619,8 +625,7 @@ int cola_snapshot(cola_ctx* c, double a1, double a_s, float* dout, float* vout, 
   force_meshes(c, c->disp);
   {
     StageTimer t(c, COLA_STAGE_VELOCITY);
-    launch_snapshot(reinterpret_cast<const float*>(c->mesh[0]), reinterpret_cast<const float*>(c->mesh[1]),
-                    reinterpret_cast<const float*>(c->mesh[2]), 2 * padded_cols(c->p.nmesh), c->disp, c->vres,
+    launch_snapshot(force_field(c), force_row_stride(c->p.nmesh), c->disp, c->vres,
                     c->psi1, c->psi2, c->p.np, c->p.nmesh, k, dout, vout, sdisp, axis, c->stream);
   }
   LAUNCH_CHECK(c, "cola_snapshot");
@@ -764,14 +769,14 @@ int cola_pk_velocity(cola_ctx* c, int32_t axis, const double* edges, int32_t nbi
   if (r != COLA_OK) return r;
   HIP_TRY(c, hipMemcpyAsync(c->pk_edges, edges, (nbins + 1) * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
-  const float* g[3];
-  const VelCoef k = velocity_coef_and_forces(c, g);
+  const float* g;
+  const VelCoef k = velocity_coef_and_forces(c, &g);
   const double a = c->a_x, adot = a * hubble_E(a, c->p.omega_m);
   const double nbar = (double)c->np3 / ((double)nm * nm * nm);
   const long rs = 2 * padded_cols(nm);
   // weights: 1/nbar (density 1 + delta) and the line-of-sight shift v / (a adot) in
   // Mpc/h over nbar (momentum)
-  launch_los_weights(g[0], g[1], g[2], rs, c->disp, c->vres, c->psi1, c->psi2, c->p.np, nm, k, axis,
+  launch_los_weights(g, force_row_stride(nm), c->disp, c->vres, c->psi1, c->psi2, c->p.np, nm, k, axis,
                      (float)(1.0 / nbar), (float)(c->p.box / nm / (a * adot) / nbar), c->fbar, c->stream);
   tile_sort(c, nm, c->disp);
   launch_deposit3_weighted(c->disp, c->perm, c->offsets, c->p.np, nm, c->fbar,
@@ -943,20 +948,21 @@ int step_adjoint(cola_ctx* c, double a0, double a1, double a_v0, const float* di
   const int np = c->p.np, nm = c->p.nmesh;
   const long rs = 2 * padded_cols(nm);
   launch_set_coef(c->coef, coef, 1, 0, c->stream);
-  const float* g[3];
+  const float* g;
   if (kept) {
-    // the forward step's force meshes; sort the checkpointed positions for
+    // the forward step's force field; sort the checkpointed positions for
     // the transposed readout below
     tile_sort(c, nm, disp0);
-    for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<const float*>(kept + (size_t)d * c->mesh_stride);
+    g = reinterpret_cast<const float*>(kept);
   } else {
-    // forward force meshes at the checkpointed positions (also sorts them)
+    // forward force field at the checkpointed positions (also sorts them)
     force_meshes(c, disp0);
-    for (int d = 0; d < 3; ++d) g[d] = reinterpret_cast<const float*>(c->mesh[d]);
+    g = force_field(c);
   }
   float* gbar = reinterpret_cast<float*>(c->mesh[0]);
   // reverse kick/drift and the readout weight gradient; Fbar -> c->fbar
-  launch_adj_readout_kick(disp0, g[0], g[1], g[2], rs, np, nm, kd, dbar, vbar, p1bar, p2bar, c->fbar,
+  // (then the meshes are free for the transposed chain, in the plain layout)
+  launch_adj_readout_kick(disp0, g, force_row_stride(nm), np, nm, kd, dbar, vbar, p1bar, p2bar, c->fbar,
                           c->stream);
   // gbar_d = R^T Fbar_d (deterministic weighted deposit over the same sort)
   launch_deposit3_weighted(disp0, c->perm, c->offsets, np, nm, c->fbar, gbar, rs, 2 * c->mesh_stride,
@@ -1145,6 +1151,79 @@ int cola_init_2lpt_adjoint(cola_ctx* c, const float* noise, const float* dbar0, 
   launch_copy_from_mesh(reinterpret_cast<float*>(Wb), np, rs, noise_bar, 1.0f, c->stream);
   LAUNCH_CHECK(c, "cola_init_2lpt_adjoint");
   return COLA_OK;
+}
+
+int cola_fft_set_schedule(int32_t n, int32_t pass, int32_t order) {
+  return set_fft_block_order(n, pass, order) == 0 ? COLA_OK : COLA_EINVAL;
+}
+
+int cola_fft_get_schedule(int32_t n, int32_t pass, int32_t* order) {
+  if (!order || !fft_size_supported(n) || pass < 0 || pass > 2) return COLA_EINVAL;
+  *order = fft_block_order(n, pass);
+  return COLA_OK;
+}
+
+int cola_autotune(cola_ctx* c, int32_t reps, int32_t* best, double* ms) {
+  if (!c) return COLA_EINVAL;
+  if (reps < 1) reps = 3;
+  const int nm = c->p.nmesh;
+  const long P = padded_cols(nm), rowc = pm_rowc(nm);
+  float2* m0 = c->meshbase;
+  // the meshes are scratch between calls: zeros in, the step's column passes
+  launch_fill_u32(reinterpret_cast<uint32_t*>(m0), 2 * c->mesh_region, 0u, c->stream);
+  StepCoef v{};
+  v.gscale = 1.0f;
+  launch_set_coef(c->coef, v, 1, 0, c->stream);
+  XPassArgs green;
+  green.in = m0;
+  green.out[0] = m0;
+  green.out[1] = m0 + P;
+  green.mode = X_FWD_GREEN;
+  green.coef = c->coef;
+  green.rowc = rowc;
+  auto run = [&](int kind) {
+    if (kind == 0) fft_y(m0, nm, 1, 0, 0, c->tw, c->stream, 1, 0, rowc);
+    else if (kind == 1) fft_x(green, nm, c->tw, c->stream);
+    else fft_y_grad_yz(m0 + P, m0 + 2 * P, nm, c->tw, c->stream, 1, 0, rowc);
+  };
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(c, COLA_EHIP, "hipEventCreate");
+  }
+  int code = COLA_OK;
+  for (int kind = 0; kind < 3 && code == COLA_OK; ++kind) {
+    const int before = fft_block_order(nm, kind);
+    double tbest = 0.0;
+    int pick = before;
+    for (int cand = 0; cand < 2 && code == COLA_OK; ++cand) {
+      const int order = 1 - cand;                      // the default first
+      set_fft_block_order(nm, kind, order);
+      run(kind);                                         // warm-up
+      hipEventRecord(e0, c->stream);
+      for (int r = 0; r < reps; ++r) run(kind);
+      hipEventRecord(e1, c->stream);
+      hipError_t e = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e != hipSuccess) {
+        code = hip_fail(c, e, "cola_autotune");
+        break;
+      }
+      const double per = (double)t / reps;
+      if (ms) ms[2 * kind + order] = per;
+      if (cand == 0 || per < tbest) {
+        tbest = per;
+        pick = order;
+      }
+    }
+    set_fft_block_order(nm, kind, code == COLA_OK ? pick : before);
+    if (code == COLA_OK && best) best[kind] = pick;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return code;
 }
 
 int cola_step_scalars(const cola_params* p, double a_x, double a_v, double a1, double* out) {

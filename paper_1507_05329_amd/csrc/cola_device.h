@@ -45,6 +45,42 @@ __device__ __forceinline__ float cic_weight(const float f[3], int k) {
   return __fmul_rn(__fmul_rn(wx, wy), wz);
 }
 
+// The PM step's force field, interleaved by node: (g_x, g_y, g_z) of node
+// (x, y, z) at g[(x nm + y) row_stride + 3 z + {0, 1, 2}].  Offset of the
+// first component of the 8 nodes of home cell c, in the order of k.
+struct ForceCorners {
+  long rows[4];
+  int z0, z1;
+  __device__ __forceinline__ ForceCorners(const int c[3], int nm, long row_stride) {
+    const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
+    const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
+    const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
+    rows[0] = ((long)c[0] * nm + c[1]) * row_stride;
+    rows[1] = ((long)c[0] * nm + cy1) * row_stride;
+    rows[2] = ((long)cx1 * nm + c[1]) * row_stride;
+    rows[3] = ((long)cx1 * nm + cy1) * row_stride;
+    z0 = 3 * c[2];
+    z1 = 3 * cz1;
+  }
+  __device__ __forceinline__ long at(int k) const { return rows[k >> 1] + ((k & 1) ? z1 : z0); }
+};
+
+// CIC readout of the three force components at a particle (offsets k = 0 .. 7
+// in order, the deposit's weights).
+__device__ __forceinline__ void force_readout(const float* __restrict__ g, long row_stride, int nm,
+                                              const int c[3], const float f[3], float F[3]) {
+  const ForceCorners fc(c, nm, row_stride);
+  F[0] = F[1] = F[2] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float w = cic_weight(f, k);
+    const float* q = g + fc.at(k);
+    F[0] += w * q[0];
+    F[1] += w * q[1];
+    F[2] += w * q[2];
+  }
+}
+
 // Tile (16^3 cells) and class bits of a home cell: class bit 4/2/1 set when
 // the cell is on the upper x/y/z face of its tile (it then also feeds nodes
 // of the next tile along that axis).  nt = tiles per side.

@@ -20,6 +20,12 @@ struct FftPlan {
 };
 bool make_plan(int n, FftPlan* plan);
 bool fft_size_supported(int n);   // transform sizes with compiled kernels
+// Block order (1: contiguous block ranges per XCD, 0: hardware round-robin)
+// of the column passes of length n, per pass kind (0 plain, 1 Green's
+// function x pass, 2 gradient y pass); process-wide, results do not depend
+// on it.  set returns 0, or -1 for an unsupported length, kind or value.
+int fft_block_order(int n, int kind);
+int set_fft_block_order(int n, int kind, int order);
 
 // Padded complex row length of an n^3 real mesh in the r2c layout: the
 // (n/2+1) half-spectrum rounded up to 16 complex values (128-byte rows).
@@ -110,6 +116,7 @@ struct XPassArgs {
   const StepCoef* coef = nullptr;  // X_FWD_GREEN: scale read from coef->gscale
   int nmock = 1;                // batched mocks (blockIdx.z) ...
   long mstride = 0;             // ... at this byte stride
+  long rowc = 0;                // row stride in complex values (0: padded_cols(n))
 };
 // Spectral combination pass (adjoint): out = IDFT_x[sum_q m_q DFT_x(in_q)].
 struct CombineSpec {
@@ -125,16 +132,23 @@ void fft_combine_x(const float2* const in[3], float2* out, int n, const CombineS
                    const float* amp, const TwiddleSet& tw, hipStream_t s);
 void fft3d_forward(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
 void fft3d_inverse(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s);
+// rowc: row stride in complex values (0: padded_cols(n)); the PM force
+// pipeline keeps its three meshes row-interleaved (rowc = 3 padded_cols,
+// mesh c at offset c padded_cols).
 void fft_r2c_z(float2* mesh, int n, int nplanes_mesh, long mesh_stride, const TwiddleSet& tw,
-               hipStream_t s, int nmock = 1, long mstride = 0);
+               hipStream_t s, int nmock = 1, long mstride = 0, long rowc = 0);
 void fft_c2r_z(float2* mesh, int n, int nmesh_batch, long mesh_stride, const TwiddleSet& tw,
                hipStream_t s, int nmock = 1, long mstride = 0);
+// Inverse z pass of the three row-interleaved force meshes, the real
+// outputs interleaved by node: (g_x, g_y, g_z) of node (x, y, z) at floats
+// (x n + y) 6 padded_cols(n) + 3 z + {0, 1, 2}.
+void fft_c2r_z_forces(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s, int nmock = 1, long mstride = 0);
 void fft_y(float2* mesh, int n, int nmesh_batch, long mesh_stride, int inverse,
-           const TwiddleSet& tw, hipStream_t s, int nmock = 1, long mstride = 0);
+           const TwiddleSet& tw, hipStream_t s, int nmock = 1, long mstride = 0, long rowc = 0);
 void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s);
 // Inverse y pass of the PM gradients: b -> IDFT_y[i n_y b] in place, IDFT_y[i n_z b] -> gz.
 void fft_y_grad_yz(float2* b, float2* gz, int n, const TwiddleSet& tw, hipStream_t s, int nmock = 1,
-                   long mstride = 0);
+                   long mstride = 0, long rowc = 0);
 // Velocity at the position time (k_velocity.hip): v = v_res + K F + u1 Psi1 + u2 Psi2,
 // redshift-space shift rsd * v along one axis.
 struct VelCoef {
@@ -143,7 +157,8 @@ struct VelCoef {
   float rsd;     // 1 / (a adot)
 };
 // g0 == nullptr: no force gather (K must be 0); sdisp == nullptr: no redshift-space output.
-void launch_velocity(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+// g: the force field interleaved by node (fft_c2r_z_forces), row_stride floats per (x, y) row.
+void launch_velocity(const float* g, long row_stride, const float* disp,
                      const float* vres, const float* psi1, const float* psi2, int np, int nm,
                      const VelCoef& k, float* vel, float* sdisp, int axis, hipStream_t s);
 // Snapshot inside the coming step (k_velocity.hip): the step's kick to a_h,
@@ -154,21 +169,21 @@ struct SnapCoef {
   float sv, w1, w2; // v_s = sv v_h + w1 Psi1 + w2 Psi2
   float rsd;        // 1 / (a_s adot(a_s))
 };
-void launch_snapshot(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+void launch_snapshot(const float* g, long row_stride, const float* disp,
                      const float* vres, const float* psi1, const float* psi2, int np, int nm,
                      const SnapCoef& k, float* dout, float* vout, float* sdisp, int axis, hipStream_t s);
 // Force readout + kick/drift (k_particles.hip).
 void launch_set_coef(StepCoef* dst, const StepCoef& v, int nmock, long mstride, hipStream_t s);
-void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2,
-                               long row_stride, float* disp, float* vres,
+void launch_readout_kick_drift(const float* g, long row_stride, float* disp, float* vres,
                                const float* psi1, const float* psi2, int np, int nm,
                                const StepCoef* coef, float* force_out, hipStream_t s,
                                int nmock = 1, long mstride = 0);
 // Initial conditions (k_ic.hip).
 void launch_philox_noise(uint64_t seed, int np, float* out, long row_stride, hipStream_t s);
 void launch_copy_to_mesh(const float* src, int n, float* mesh, long row_stride, hipStream_t s);
+// elem: floats between consecutive nodes of a row (3 for one component of the force field).
 void launch_copy_from_mesh(const float* mesh, int n, long row_stride, float* dst, float scale,
-                           hipStream_t s);
+                           hipStream_t s, int elem = 1);
 void launch_source_diag(float* a, const float* b, const float* c, int n, long row_stride,
                         hipStream_t s);
 void launch_source_sub_sq(float* a, const float* b, int n, long row_stride, hipStream_t s);
@@ -203,13 +218,13 @@ void launch_halo_fill(const float* disp, const float* vel, const int32_t* lab, c
                       unsigned long long* acc, int32_t* root, int32_t* cnt, float* pos, float* vout,
                       hipStream_t s);
 // Weights of that deposit (k_velocity.hip): 1/nbar, the scaled velocity along axis, 0.
-void launch_los_weights(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+void launch_los_weights(const float* g, long row_stride, const float* disp,
                         const float* vres, const float* psi1, const float* psi2, int np, int nm,
                         const VelCoef& k, int axis, float w0, float scale, float* wt, hipStream_t s);
 // Adjoint kernels (k_adjoint.hip).
-void launch_adj_readout_kick(const float* disp, const float* g0, const float* g1, const float* g2,
-                             long row_stride, int np, int nm, const KickDrift& kd, float* dbar,
-                             float* vbar, float* p1bar, float* p2bar, float* fbar, hipStream_t s);
+void launch_adj_readout_kick(const float* disp, const float* g, long row_stride, int np, int nm,
+                             const KickDrift& kd, float* dbar, float* vbar, float* p1bar, float* p2bar,
+                             float* fbar, hipStream_t s);
 void launch_adj_deposit_grad(const float* disp, const float* field, long row_stride, int np, int ng,
                              float dscale, float coef, float* dbar, hipStream_t s);
 void launch_axpy_to_mesh(const float* a, const float* b, float alpha, int n, float* mesh,

@@ -33,8 +33,8 @@ __device__ __forceinline__ long node_index(const int c[3], int k, int nm, long r
 }
 
 __global__ __launch_bounds__(256) void k_adj_readout_kick(
-    const float* __restrict__ disp, const float* __restrict__ g0, const float* __restrict__ g1,
-    const float* __restrict__ g2, long row_stride, int np, int nm, long np3, KickDrift kd,
+    const float* __restrict__ disp, const float* __restrict__ g, long row_stride, int np, int nm, long np3,
+    KickDrift kd,
     float* __restrict__ dbar, float* __restrict__ vbar, float* __restrict__ p1bar,
     float* __restrict__ p2bar, float* __restrict__ fbar) {
   // particles of a block share mesh lines; neighbouring blocks stay on one XCD (L2)
@@ -55,14 +55,14 @@ __global__ __launch_bounds__(256) void k_adj_readout_kick(
   int c[3];
   float f[3];
   home_cell(disp, np3, (uint32_t)i, np, nm, 1.0f, c, f);
-  const float* g[3] = {g0, g1, g2};
+  const ForceCorners fc(c, nm, row_stride);  // the force field interleaved by node
   float xb[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     float gw[3];
     weight_grads(f, k, gw);
-    const long idx = node_index(c, k, nm, row_stride);
-    const float s = F[0] * g[0][idx] + F[1] * g[1][idx] + F[2] * g[2][idx];
+    const float* q = g + fc.at(k);
+    const float s = F[0] * q[0] + F[1] * q[1] + F[2] * q[2];
 #pragma unroll
     for (int e = 0; e < 3; ++e) xb[e] += gw[e] * s;
   }
@@ -70,12 +70,12 @@ __global__ __launch_bounds__(256) void k_adj_readout_kick(
   for (int e = 0; e < 3; ++e) dbar[e * np3 + i] += xb[e];
 }
 
-void launch_adj_readout_kick(const float* disp, const float* g0, const float* g1, const float* g2,
-                             long row_stride, int np, int nm, const KickDrift& kd, float* dbar,
-                             float* vbar, float* p1bar, float* p2bar, float* fbar, hipStream_t s) {
+void launch_adj_readout_kick(const float* disp, const float* g, long row_stride, int np, int nm,
+                             const KickDrift& kd, float* dbar, float* vbar, float* p1bar, float* p2bar,
+                             float* fbar, hipStream_t s) {
   const long np3 = (long)np * np * np;
   hipLaunchKernelGGL(k_adj_readout_kick, dim3((unsigned)((np3 + 255) / 256)), dim3(256), 0, s, disp,
-                     g0, g1, g2, row_stride, np, nm, np3, kd, dbar, vbar, p1bar, p2bar, fbar);
+                     g, row_stride, np, nm, np3, kd, dbar, vbar, p1bar, p2bar, fbar);
 }
 
 // dbar += coef * dscale * sum_s grad w_s(u) field[c + s]  on an ng^3 grid.

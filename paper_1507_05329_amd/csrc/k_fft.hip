@@ -18,6 +18,8 @@
 // y[(j - j mod Ns) R + j mod Ns + r Ns].  Every stage reads all of its
 // inputs into registers before any thread writes, so one LDS buffer is
 // enough.  Twiddles come from a per-length table exp(-2 pi i k / n).
+#include <atomic>
+
 #include "cola_device.h"
 #include "cola_internal.h"
 
@@ -255,6 +257,7 @@ constexpr int fcols_w(int n) {
 }
 constexpr int ftw_len(int n) { return fcols_w(n) * fld(n) * 8 + n * 8 <= kLdsLimit ? n : n / 2; }
 constexpr int fcols_threads(int n) { return threads_for(fcols_w(n) * n); }
+
 // Waves per SIMD the register budget must allow: two 1024-thread workgroups per CU.
 constexpr int min_waves(int t) { return t >= 1024 ? 8 : 4; }
 // The order whose first stage has the smaller radix, i.e. the more
@@ -450,7 +453,7 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
     const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
     ColGeom g, const float2* __restrict__ tw, int mult, int ca, int cb, float scale,
     const float* __restrict__ amp, int y_is_plane_freq, const StepCoef* __restrict__ coef,
-    long mstride) {
+    long mstride, int xcd_order) {
   in = mock_ptr(in, mstride);
   out0 = mock_ptr(out0, mstride);
   if constexpr (MODE == X_FWD_GREEN || MODE == X_INV_GRAD_YZ) out1 = mock_ptr(out1, mstride);
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
   __shared__ float2 lds[W * LD];
   __shared__ float2 twl[TL];
   const uint32_t nblk = (uint32_t)g.nchunk * g.nplanes;
-  const uint32_t bid = xcd_remap(blockIdx.x, nblk);
+  const uint32_t bid = xcd_order ? xcd_remap(blockIdx.x, nblk) : blockIdx.x;
   const int p = bid / g.nchunk;
   const int c0 = (bid - p * g.nchunk) * W;
   const long es = g.elem_stride;
@@ -634,7 +637,7 @@ __global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void
   for (int q = 0; q < KO; ++q) {
     const int i = tid + q * T;
     const int l = i / COLS, k = i - l * COLS;
-    if ((NO % T == 0 || i < NO) && r0 + l < nrows) base[(r0 + l) * COLS + k] = xs[q];
+    if ((NO % T == 0 || i < NO) && r0 + l < nrows) base[(r0 + l) * cols + k] = xs[q];
   }
 }
 
@@ -698,6 +701,93 @@ __global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) p[r * SL::NS] = z[b][r];
     }
+  }
+}
+
+// Inverse z pass of the three force meshes in the row-interleaved layout
+// (row r of mesh c is line 3 r + c, lines `cols` complex apart): NL3 lines
+// (NL3 / 3 rows, all three meshes) per workgroup, the same transform as
+// k_c2r_z, and the real outputs written back interleaved by node, row r
+// holding (g_x, g_y, g_z) of its N nodes in its first 3 N floats.  A row's
+// output lies inside its own three input lines, and a workgroup reads all
+// of its lines before it writes, so the pass runs in place.
+constexpr int frows_nl3(int n) { return frows_nl(n) / 3 * 3; }
+constexpr int frows_threads3(int n) { return threads_for(frows_nl3(n) * (n / 2)); }
+
+template <int N>
+__global__ __launch_bounds__(frows_threads3(N), 4) void k_c2r_z3(
+    float2* __restrict__ mesh, long nrows, int cols, const float2* __restrict__ tw, long mstride) {
+  constexpr int H = N / 2, LD = fld(H), NL = frows_nl3(N), T = frows_threads3(N), TL = frows_tw_len(N);
+  static_assert(NL >= 3, "three lines per workgroup at least");
+  constexpr int OR = lo_first(H);
+  using S0 = Stg<H, OR, 0, NL, T, true>;
+  using SL = Stg<H, OR, nstage(H) - 1, NL, T, true>;
+  mesh = mock_ptr(mesh, mstride);
+  __shared__ float2 lds[NL * LD];
+  __shared__ float2 twl[TL];
+  const long l0 = (long)blockIdx.x * NL;          // first line; a multiple of 3
+  const long nlines = 3 * nrows;
+  const int tid = threadIdx.x;
+  float2 xa[S0::KB][S0::R], xb[S0::KB][S0::R];
+#pragma unroll
+  for (int b = 0; b < S0::KB; ++b) {
+    const int t = tid + b * T;
+    int l, j;
+    S0::map(t, l, j);
+    const bool in = S0::ok(t) && l0 + l < nlines;
+    const float2* p = mesh + (l0 + l) * cols;
+#pragma unroll
+    for (int r = 0; r < S0::R; ++r) {
+      const int k = j + r * S0::NBL;
+      xa[b][r] = in ? p[k] : make_float2(0.f, 0.f);
+      xb[b][r] = in ? p[H - k] : make_float2(0.f, 0.f);
+    }
+  }
+  load_twiddles<TL, T>(twl, tw);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < S0::KB; ++b) {
+    int l, j;
+    S0::map(tid + b * T, l, j);
+#pragma unroll
+    for (int r = 0; r < S0::R; ++r) {
+      const int k = j + r * S0::NBL;
+      const float2 cb = make_float2(xb[b][r].x, -xb[b][r].y);
+      const float2 e = cadd(xa[b][r], cb);
+      const float2 o = cmulc(csub(xa[b][r], cb), tw_at<N, TL>(twl, k));
+      xa[b][r] = cadd(e, make_float2(-o.y, o.x));
+    }
+  }
+  float2 z[SL::KB][SL::R];
+  reg_fft<H, OR, NL, T, true, LD, 0, TL>(xa, z, lds, twl, tid);
+  // pairs (x_2m, x_2m+1) of line l in natural order at lds[l * LD + m]
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < SL::KB; ++b) {
+    const int t = tid + b * T;
+    if (SL::ok(t)) {
+      int l, j;
+      SL::map(t, l, j);
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) lds[l * LD + j + r * SL::NS] = z[b][r];
+    }
+  }
+  __syncthreads();
+  // row q of this workgroup: 3 N floats, four per thread per round
+  const float* lf = reinterpret_cast<const float*>(lds);
+  constexpr int NQ = NL / 3, PER = 3 * N / 4;
+  for (int i = tid; i < NQ * PER; i += T) {
+    const int q = i / PER, o4 = (i - q * PER) * 4;
+    const long row = l0 / 3 + q;
+    if (row >= nrows) continue;
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = o4 + u, node = o / 3, c = o - node * 3;
+      v[u] = lf[2 * ((3 * q + c) * LD) + node];
+    }
+    float* dst = reinterpret_cast<float*>(mesh + row * 3 * (long)cols) + o4;
+    *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -796,32 +886,75 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_combine(
 }
 
 // ---------------------------------------------------------------------------
+// Schedule table: the block order of the column passes, per transform
+// length and pass kind (plain, Green's function x pass, gradient y pass),
+// process-wide: 1 hands each XCD a contiguous range of column blocks
+// (xcd_remap: neighbouring blocks share the XCD's L2), 0 keeps the
+// hardware's round-robin.  The kernels and their arithmetic are the same;
+// only the workgroup that transforms a column changes.  Set by the
+// autotuner or by the caller.
+namespace {
+constexpr int kSchedLens[] = {16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
+constexpr int kNSched = sizeof(kSchedLens) / sizeof(kSchedLens[0]);
+std::atomic<int> g_order[kNSched][3] = {};   // 0: default (1), else value + 1
+int sched_slot(int n) {
+  for (int i = 0; i < kNSched; ++i)
+    if (kSchedLens[i] == n) return i;
+  return -1;
+}
+int pass_kind(int mode) { return mode == X_FWD_GREEN ? 1 : mode == X_INV_GRAD_YZ ? 2 : 0; }
+}  // namespace
+
+int fft_block_order(int n, int kind) {
+  const int i = sched_slot(n);
+  const int v = (i < 0 || kind < 0 || kind > 2) ? 0 : g_order[i][kind].load(std::memory_order_relaxed);
+  return v == 0 ? 1 : v - 1;
+}
+
+int set_fft_block_order(int n, int kind, int order) {
+  const int i = sched_slot(n);
+  if (i < 0 || kind < 0 || kind > 2 || (order != 0 && order != 1)) return -1;
+  g_order[i][kind].store(order + 1, std::memory_order_relaxed);
+  return 0;
+}
+
 namespace {
 
-ColGeom geom(int n, int w, int axis) {
+// rowc: complex values from one row (x, y) to the next, padded_cols(n) for a
+// plain mesh, 3 padded_cols(n) in the row-interleaved force layout.
+ColGeom geom(int n, int w, int axis, long rowc = 0) {
   ColGeom g;
   const long cols = padded_cols(n);
+  if (rowc <= 0) rowc = cols;
   g.cols = (int)cols;
   g.nchunk = (int)(cols / w);
   g.nplanes = n;
   if (axis == 1) {  // y: planes are x
-    g.elem_stride = cols;
-    g.plane_stride = (long)n * cols;
+    g.elem_stride = rowc;
+    g.plane_stride = (long)n * rowc;
   } else {          // x: planes are y
-    g.elem_stride = (long)n * cols;
-    g.plane_stride = cols;
+    g.elem_stride = (long)n * rowc;
+    g.plane_stride = rowc;
   }
   return g;
 }
 
 template <int N>
 void r2c_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s, int nmock,
-           long mstride) {
+           long mstride, long rowc) {
   constexpr int NL = frows_nl(N), T = frows_threads(N);
   const long nrows = (long)N * N;
   dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch, (unsigned)nmock);
-  hipLaunchKernelGGL(k_r2c_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), mesh_stride, tw,
-                     mstride);
+  hipLaunchKernelGGL(k_r2c_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)(rowc > 0 ? rowc : padded_cols(N)),
+                     mesh_stride, tw, mstride);
+}
+
+template <int N>
+void c2r3_n(float2* mesh, const float2* tw, hipStream_t s, int nmock, long mstride) {
+  constexpr int NL = frows_nl3(N), T = frows_threads3(N);
+  const long nrows = (long)N * N;
+  dim3 grid((unsigned)((3 * nrows + NL - 1) / NL), 1, (unsigned)nmock);
+  hipLaunchKernelGGL(k_c2r_z3<N>, grid, dim3(T), 0, s, mesh, nrows, (int)padded_cols(N), tw, mstride);
 }
 
 template <int N>
@@ -837,9 +970,9 @@ void c2r_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStre
 template <int N>
 void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbatch, long mesh_stride,
             const float2* tw, int mult, int ca, int cb, float scale, const float* amp, hipStream_t s,
-            const StepCoef* coef = nullptr, int nmock = 1, long mstride = 0) {
-  constexpr int W = fcols_w(N);
-  ColGeom g = geom(N, W, axis);
+            const StepCoef* coef = nullptr, int nmock = 1, long mstride = 0, long rowc = 0) {
+  constexpr int W = fcols_w(N), T = fcols_threads(N);
+  ColGeom g = geom(N, W, axis, rowc);
   // The Green pass takes only the column blocks that hold a frequency
   // 0 .. N/2 (the rest of a padded row is never read; the passes after it
   // transform whatever is there, column by column).  Measured on the 768
@@ -848,30 +981,31 @@ void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbat
   if (mode == X_FWD_GREEN) g.nchunk = (N / 2 + 1 + W - 1) / W;
   dim3 grid((unsigned)(g.nchunk * g.nplanes), (unsigned)nbatch, (unsigned)nmock);
   const int yf = axis == 0 ? 1 : 0;
+  const int xo = fft_block_order(N, pass_kind(mode));
   switch (mode) {
     case X_FWD:
-      hipLaunchKernelGGL((k_cols<N, X_FWD>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
+      hipLaunchKernelGGL((k_cols<N, X_FWD>), grid, dim3(T), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride, xo);
       break;
     case X_INV:
-      hipLaunchKernelGGL((k_cols<N, X_INV>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
+      hipLaunchKernelGGL((k_cols<N, X_INV>), grid, dim3(T), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride, xo);
       break;
     case X_FWD_AMP:
-      hipLaunchKernelGGL((k_cols<N, X_FWD_AMP>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, 0, 0, 0, 1.f, amp, yf, nullptr, mstride);
+      hipLaunchKernelGGL((k_cols<N, X_FWD_AMP>), grid, dim3(T), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, amp, yf, nullptr, mstride, xo);
       break;
     case X_MULT_INV:
-      hipLaunchKernelGGL((k_cols<N, X_MULT_INV>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], nullptr, nullptr,
-                         mesh_stride, g, tw, mult, ca, cb, scale, nullptr, yf, nullptr, mstride);
+      hipLaunchKernelGGL((k_cols<N, X_MULT_INV>), grid, dim3(T), 0, s, in, out[0], nullptr, nullptr,
+                         mesh_stride, g, tw, mult, ca, cb, scale, nullptr, yf, nullptr, mstride, xo);
       break;
     case X_FWD_GREEN:
-      hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], out[1], nullptr,
-                         mesh_stride, g, tw, M_GRAD, 0, 0, scale, nullptr, yf, coef, mstride);
+      hipLaunchKernelGGL((k_cols<N, X_FWD_GREEN>), grid, dim3(T), 0, s, in, out[0], out[1], nullptr,
+                         mesh_stride, g, tw, M_GRAD, 0, 0, scale, nullptr, yf, coef, mstride, xo);
       break;
     case X_INV_GRAD_YZ:
-      hipLaunchKernelGGL((k_cols<N, X_INV_GRAD_YZ>), grid, dim3(fcols_threads(N)), 0, s, in, out[0], out[1], nullptr,
-                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride);
+      hipLaunchKernelGGL((k_cols<N, X_INV_GRAD_YZ>), grid, dim3(T), 0, s, in, out[0], out[1], nullptr,
+                         mesh_stride, g, tw, 0, 0, 0, 1.f, nullptr, yf, nullptr, mstride, xo);
       break;
   }
 }
@@ -891,9 +1025,9 @@ bool fft_size_supported(int n) {
 }
 
 void fft_r2c_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleSet& tw, hipStream_t s,
-               int nmock, long mstride) {
+               int nmock, long mstride, long rowc) {
   switch (n) {
-#define X(NN) case NN: r2c_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s, nmock, mstride); break;
+#define X(NN) case NN: r2c_n<NN>(mesh, nbatch, mesh_stride, tw.get(NN), s, nmock, mstride, rowc); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;
@@ -910,12 +1044,21 @@ void fft_c2r_z(float2* mesh, int n, int nbatch, long mesh_stride, const TwiddleS
   }
 }
 
+void fft_c2r_z_forces(float2* mesh, int n, const TwiddleSet& tw, hipStream_t s, int nmock, long mstride) {
+  switch (n) {
+#define X(NN) case NN: c2r3_n<NN>(mesh, tw.get(NN), s, nmock, mstride); break;
+    COLA_FFT_SIZES(X)
+#undef X
+    default: break;
+  }
+}
+
 void fft_y(float2* mesh, int n, int nbatch, long mesh_stride, int inverse, const TwiddleSet& tw,
-           hipStream_t s, int nmock, long mstride) {
+           hipStream_t s, int nmock, long mstride, long rowc) {
   float2* outs[3] = {mesh, nullptr, nullptr};
   const int mode = inverse ? X_INV : X_FWD;
   switch (n) {
-#define X(NN) case NN: cols_n<NN>(mode, 1, mesh, outs, nbatch, mesh_stride, tw.get(NN), 0, 0, 0, 1.f, nullptr, s, nullptr, nmock, mstride); break;
+#define X(NN) case NN: cols_n<NN>(mode, 1, mesh, outs, nbatch, mesh_stride, tw.get(NN), 0, 0, 0, 1.f, nullptr, s, nullptr, nmock, mstride, rowc); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;
@@ -923,10 +1066,10 @@ void fft_y(float2* mesh, int n, int nbatch, long mesh_stride, int inverse, const
 }
 
 void fft_y_grad_yz(float2* b, float2* gz, int n, const TwiddleSet& tw, hipStream_t s, int nmock,
-                   long mstride) {
+                   long mstride, long rowc) {
   float2* outs[3] = {b, gz, nullptr};
   switch (n) {
-#define X(NN) case NN: cols_n<NN>(X_INV_GRAD_YZ, 1, b, outs, 1, 0, tw.get(NN), 0, 0, 0, 1.f, nullptr, s, nullptr, nmock, mstride); break;
+#define X(NN) case NN: cols_n<NN>(X_INV_GRAD_YZ, 1, b, outs, 1, 0, tw.get(NN), 0, 0, 0, 1.f, nullptr, s, nullptr, nmock, mstride, rowc); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;
@@ -936,7 +1079,7 @@ void fft_y_grad_yz(float2* b, float2* gz, int n, const TwiddleSet& tw, hipStream
 void fft_x(const XPassArgs& a, int n, const TwiddleSet& tw, hipStream_t s) {
   float2* outs[3] = {a.out[0], a.out[1], a.out[2]};
   switch (n) {
-#define X(NN) case NN: cols_n<NN>(a.mode, 0, a.in, outs, 1, 0, tw.get(NN), a.mult, a.comp_a, a.comp_b, a.scale, a.amp, s, a.coef, a.nmock, a.mstride); break;
+#define X(NN) case NN: cols_n<NN>(a.mode, 0, a.in, outs, 1, 0, tw.get(NN), a.mult, a.comp_a, a.comp_b, a.scale, a.amp, s, a.coef, a.nmock, a.mstride, a.rowc); break;
     COLA_FFT_SIZES(X)
 #undef X
     default: break;

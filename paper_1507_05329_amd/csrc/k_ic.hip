@@ -68,19 +68,19 @@ void launch_copy_to_mesh(const float* src, int n, float* mesh, long row_stride, 
 }
 
 __global__ void k_copy_from_mesh(const float* __restrict__ mesh, int n, long n3, long row_stride,
-                                 float* __restrict__ dst, float scale) {
+                                 float* __restrict__ dst, float scale, int elem) {
   for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n3;
        p += (long)gridDim.x * blockDim.x) {
     const long row = p / n, col = p - row * n;
-    dst[p] = scale * mesh[row * row_stride + col];
+    dst[p] = scale * mesh[row * row_stride + col * elem];
   }
 }
 
 void launch_copy_from_mesh(const float* mesh, int n, long row_stride, float* dst, float scale,
-                           hipStream_t s) {
+                           hipStream_t s, int elem) {
   const long n3 = (long)n * n * n;
   hipLaunchKernelGGL(k_copy_from_mesh, dim3(grid_1d(n3)), dim3(256), 0, s, mesh, n,
-                     n3, row_stride, dst, scale);
+                     n3, row_stride, dst, scale, elem);
 }
 
 // 2LPT source, diagonal part: a <- a b + b c + c a (a, b, c = phi_xx, phi_yy, phi_zz).

@@ -7,8 +7,9 @@
 //   v_d  += K F_d - c1 Psi1_d - c2 Psi2_d             (c1 = K alpha D1, c2 = K alpha (D2 - D1^2):
 //                                                      the residual force F - d^2/dt^2-term of 2LPT)
 //   d_d  += I v_d + e1 Psi1_d + e2 Psi2_d             (e1 = dD1, e2 = dD2)
-// All three force meshes are read before the particle's own position is
-// updated, so the update is in place.
+// The force field is interleaved by node (cola_device.h: force_readout), so
+// a corner's three components share one cache line; it is read before the
+// particle's own position is updated, so the update is in place.
 #include "cola_device.h"
 #include "cola_internal.h"
 
@@ -19,16 +20,13 @@ namespace cola {
 // loads are in flight during the mesh gathers.
 template <bool FORCE_ONLY>
 __global__ __launch_bounds__(256) void k_readout_kick_drift(
-    const float* __restrict__ g0, const float* __restrict__ g1, const float* __restrict__ g2,
-    long row_stride, float* __restrict__ disp, float* __restrict__ vres,
+    const float* __restrict__ g, long row_stride, float* __restrict__ disp, float* __restrict__ vres,
     const float* __restrict__ psi1, const float* __restrict__ psi2, int np, int nm, long np3,
     const StepCoef* __restrict__ coef, float* __restrict__ force_out, long mstride) {
   // neighbouring blocks share mesh lines: keep them on one XCD (L2)
   const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
   if (i >= np3) return;
-  g0 = mock_ptr(g0, mstride);
-  g1 = mock_ptr(g1, mstride);
-  g2 = mock_ptr(g2, mstride);
+  g = mock_ptr(g, mstride);
   disp = mock_ptr(disp, mstride);
   float v0[3], p1[3], p2[3];
   if constexpr (!FORCE_ONLY) {
@@ -46,20 +44,8 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
   float f[3];
   const float dscale = 1.0f;
   home_cell(disp, np3, (uint32_t)i, np, nm, dscale, c, f);
-  const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
-  const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
-  const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
-  const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
-                        ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
-  float F[3] = {0.f, 0.f, 0.f};
-  const float* g[3] = {g0, g1, g2};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float w = cic_weight(f, k);
-    const long idx = rows[k >> 1] + ((k & 1) ? cz1 : c[2]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) F[d] += w * g[d][idx];
-  }
+  float F[3];
+  force_readout(g, row_stride, nm, c, f, F);
   if constexpr (FORCE_ONLY) {
     force_out = mock_ptr(force_out, mstride);
 #pragma unroll
@@ -76,17 +62,16 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
   }
 }
 
-void launch_readout_kick_drift(const float* g0, const float* g1, const float* g2, long row_stride,
-                               float* disp, float* vres, const float* psi1, const float* psi2,
-                               int np, int nm, const StepCoef* coef, float* force_out,
+void launch_readout_kick_drift(const float* g, long row_stride, float* disp, float* vres, const float* psi1,
+                               const float* psi2, int np, int nm, const StepCoef* coef, float* force_out,
                                hipStream_t s, int nmock, long mstride) {
   const long np3 = (long)np * np * np;
   const dim3 grid((unsigned)((np3 + 255) / 256), 1, (unsigned)nmock);
   if (force_out)
-    hipLaunchKernelGGL(k_readout_kick_drift<true>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres,
+    hipLaunchKernelGGL(k_readout_kick_drift<true>, grid, dim3(256), 0, s, g, row_stride, disp, vres,
                        psi1, psi2, np, nm, np3, coef, force_out, mstride);
   else
-    hipLaunchKernelGGL(k_readout_kick_drift<false>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp,
+    hipLaunchKernelGGL(k_readout_kick_drift<false>, grid, dim3(256), 0, s, g, row_stride, disp,
                        vres, psi1, psi2, np, nm, np3, coef, force_out, mstride);
 }
 

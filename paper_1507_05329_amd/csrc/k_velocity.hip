@@ -6,7 +6,8 @@
 // (dx/dt . xhat) / H).
 //
 // Per particle (one thread each, the readout's column order):
-//   F_d  = sum_s w_s g_d[c + s]                 (only when the kick is not zero)
+//   F_d  = sum_s w_s g_d[c + s]                 (only when the kick is not zero; the
+//                                                force field interleaved by node)
 //   v_d  = v_res_d + K F_d + u1 Psi1_d + u2 Psi2_d
 //          K  = kick factor from a_v to a_x with the force at a_x,
 //          u1 = a^2 adot D1' - K alpha D1,  u2 = a^2 adot D2' - K alpha (D2 - D1^2)
@@ -26,8 +27,7 @@
 namespace cola {
 
 template <bool KICK, bool RSD>
-__global__ __launch_bounds__(256) void k_velocity(const float* __restrict__ g0, const float* __restrict__ g1,
-                                                  const float* __restrict__ g2, long row_stride,
+__global__ __launch_bounds__(256) void k_velocity(const float* __restrict__ g, long row_stride,
                                                   const float* __restrict__ disp, const float* __restrict__ vres,
                                                   const float* __restrict__ psi1, const float* __restrict__ psi2,
                                                   int np, int nm, long np3, VelCoef k, float* __restrict__ vel,
@@ -47,19 +47,7 @@ __global__ __launch_bounds__(256) void k_velocity(const float* __restrict__ g0, 
     int c[3];
     float f[3];
     home_cell(disp, np3, (uint32_t)i, np, nm, 1.0f, c, f);
-    const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
-    const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
-    const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
-    const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
-                          ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
-    const float* g[3] = {g0, g1, g2};
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const float w = cic_weight(f, s);
-      const long idx = rows[s >> 1] + ((s & 1) ? cz1 : c[2]);
-#pragma unroll
-      for (int e = 0; e < 3; ++e) F[e] += w * g[e][idx];
-    }
+    force_readout(g, row_stride, nm, c, f, F);
   }
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
@@ -70,8 +58,7 @@ __global__ __launch_bounds__(256) void k_velocity(const float* __restrict__ g0, 
 }
 
 template <bool RSD>
-__global__ __launch_bounds__(256) void k_snapshot(const float* __restrict__ g0, const float* __restrict__ g1,
-                                                  const float* __restrict__ g2, long row_stride,
+__global__ __launch_bounds__(256) void k_snapshot(const float* __restrict__ g, long row_stride,
                                                   const float* __restrict__ disp, const float* __restrict__ vres,
                                                   const float* __restrict__ psi1, const float* __restrict__ psi2,
                                                   int np, int nm, long np3, SnapCoef k, float* __restrict__ dout,
@@ -89,20 +76,8 @@ __global__ __launch_bounds__(256) void k_snapshot(const float* __restrict__ g0, 
   int c[3];
   float f[3];
   home_cell(disp, np3, (uint32_t)i, np, nm, 1.0f, c, f);
-  const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
-  const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
-  const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
-  const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
-                        ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
-  const float* g[3] = {g0, g1, g2};
-  float F[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const float w = cic_weight(f, s);
-    const long idx = rows[s >> 1] + ((s & 1) ? cz1 : c[2]);
-#pragma unroll
-    for (int e = 0; e < 3; ++e) F[e] += w * g[e][idx];
-  }
+  float F[3];
+  force_readout(g, row_stride, nm, c, f, F);
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const float vh = v[e] + k.K * F[e] - k.c1 * p1[e] - k.c2 * p2[e];
@@ -114,16 +89,16 @@ __global__ __launch_bounds__(256) void k_snapshot(const float* __restrict__ g0, 
   }
 }
 
-void launch_snapshot(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+void launch_snapshot(const float* g, long row_stride, const float* disp,
                      const float* vres, const float* psi1, const float* psi2, int np, int nm,
                      const SnapCoef& k, float* dout, float* vout, float* sdisp, int axis, hipStream_t s) {
   const long np3 = (long)np * np * np;
   const dim3 grid((unsigned)((np3 + 255) / 256));
   if (sdisp)
-    hipLaunchKernelGGL(k_snapshot<true>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2,
+    hipLaunchKernelGGL(k_snapshot<true>, grid, dim3(256), 0, s, g, row_stride, disp, vres, psi1, psi2,
                        np, nm, np3, k, dout, vout, sdisp, axis);
   else
-    hipLaunchKernelGGL(k_snapshot<false>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2,
+    hipLaunchKernelGGL(k_snapshot<false>, grid, dim3(256), 0, s, g, row_stride, disp, vres, psi1, psi2,
                        np, nm, np3, k, dout, vout, sdisp, axis);
 }
 
@@ -131,8 +106,7 @@ void launch_snapshot(const float* g0, const float* g1, const float* g2, long row
 // wt[1] = scale * v_axis (the velocity of k_velocity, scaled to the shift per
 // particle over nbar), wt[2] = 0.
 template <bool KICK>
-__global__ __launch_bounds__(256) void k_los_weights(const float* __restrict__ g0, const float* __restrict__ g1,
-                                                     const float* __restrict__ g2, long row_stride,
+__global__ __launch_bounds__(256) void k_los_weights(const float* __restrict__ g, long row_stride,
                                                      const float* __restrict__ disp, const float* __restrict__ vres,
                                                      const float* __restrict__ psi1, const float* __restrict__ psi2,
                                                      int np, int nm, long np3, VelCoef k, int axis, float w0,
@@ -145,17 +119,9 @@ __global__ __launch_bounds__(256) void k_los_weights(const float* __restrict__ g
     int c[3];
     float f[3];
     home_cell(disp, np3, (uint32_t)i, np, nm, 1.0f, c, f);
-    const int cx1 = c[0] + 1 == nm ? 0 : c[0] + 1;
-    const int cy1 = c[1] + 1 == nm ? 0 : c[1] + 1;
-    const int cz1 = c[2] + 1 == nm ? 0 : c[2] + 1;
-    const long rows[4] = {((long)c[0] * nm + c[1]) * row_stride, ((long)c[0] * nm + cy1) * row_stride,
-                          ((long)cx1 * nm + c[1]) * row_stride, ((long)cx1 * nm + cy1) * row_stride};
-    const float* g = axis == 0 ? g0 : axis == 1 ? g1 : g2;
+    const ForceCorners fc(c, nm, row_stride);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const long idx = rows[s >> 1] + ((s & 1) ? cz1 : c[2]);
-      F += cic_weight(f, s) * g[idx];
-    }
+    for (int s = 0; s < 8; ++s) F += cic_weight(f, s) * g[fc.at(s) + axis];
   }
   const float v = vres[j] + k.K * F + k.u1 * psi1[j] + k.u2 * psi2[j];
   wt[i] = w0;
@@ -163,36 +129,36 @@ __global__ __launch_bounds__(256) void k_los_weights(const float* __restrict__ g
   wt[2 * np3 + i] = 0.f;
 }
 
-void launch_los_weights(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+void launch_los_weights(const float* g, long row_stride, const float* disp,
                         const float* vres, const float* psi1, const float* psi2, int np, int nm,
                         const VelCoef& k, int axis, float w0, float scale, float* wt, hipStream_t s) {
   const long np3 = (long)np * np * np;
   const dim3 grid((unsigned)((np3 + 255) / 256));
-  if (g0)
-    hipLaunchKernelGGL(k_los_weights<true>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1, psi2,
+  if (g)
+    hipLaunchKernelGGL(k_los_weights<true>, grid, dim3(256), 0, s, g, row_stride, disp, vres, psi1, psi2,
                        np, nm, np3, k, axis, w0, scale, wt);
   else
-    hipLaunchKernelGGL(k_los_weights<false>, grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+    hipLaunchKernelGGL(k_los_weights<false>, grid, dim3(256), 0, s, g, row_stride, disp, vres, psi1,
                        psi2, np, nm, np3, k, axis, w0, scale, wt);
 }
 
-void launch_velocity(const float* g0, const float* g1, const float* g2, long row_stride, const float* disp,
+void launch_velocity(const float* g, long row_stride, const float* disp,
                      const float* vres, const float* psi1, const float* psi2, int np, int nm,
                      const VelCoef& k, float* vel, float* sdisp, int axis, hipStream_t s) {
   const long np3 = (long)np * np * np;
   const dim3 grid((unsigned)((np3 + 255) / 256));
-  const bool kick = g0 != nullptr, rsd = sdisp != nullptr;
+  const bool kick = g != nullptr, rsd = sdisp != nullptr;
   if (kick && rsd)
-    hipLaunchKernelGGL((k_velocity<true, true>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+    hipLaunchKernelGGL((k_velocity<true, true>), grid, dim3(256), 0, s, g, row_stride, disp, vres, psi1,
                        psi2, np, nm, np3, k, vel, sdisp, axis);
   else if (kick)
-    hipLaunchKernelGGL((k_velocity<true, false>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+    hipLaunchKernelGGL((k_velocity<true, false>), grid, dim3(256), 0, s, g, row_stride, disp, vres, psi1,
                        psi2, np, nm, np3, k, vel, sdisp, axis);
   else if (rsd)
-    hipLaunchKernelGGL((k_velocity<false, true>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres, psi1,
+    hipLaunchKernelGGL((k_velocity<false, true>), grid, dim3(256), 0, s, g, row_stride, disp, vres, psi1,
                        psi2, np, nm, np3, k, vel, sdisp, axis);
   else
-    hipLaunchKernelGGL((k_velocity<false, false>), grid, dim3(256), 0, s, g0, g1, g2, row_stride, disp, vres,
+    hipLaunchKernelGGL((k_velocity<false, false>), grid, dim3(256), 0, s, g, row_stride, disp, vres,
                        psi1, psi2, np, nm, np3, k, vel, sdisp, axis);
 }
 

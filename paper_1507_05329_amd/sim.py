@@ -300,6 +300,30 @@ class ColaSim:
     def synchronize(self):
         self._chk(self.lib.cola_synchronize(self.ctx), "synchronize")
 
+    def autotune(self, reps=3):
+        """Times the column-pass block orders of the PM step at this mesh
+        length and keeps the fastest (process-wide).  Returns
+        ({pass kind: order}, {(pass kind, order): ms})."""
+        best = (C.c_int32 * 3)()
+        ms = np.zeros(6)
+        self._chk(self.lib.cola_autotune(self.ctx, int(reps), best, dptr(ms)), "autotune")
+        kinds = ("plain", "green", "grad")
+        return ({kinds[k]: int(best[k]) for k in range(3)},
+                {(kinds[k], o): float(ms[2 * k + o]) for k in range(3) for o in (0, 1)})
+
+
+def fft_schedule(n, pass_kind, order=None):
+    """Get (and with order, set) the column-pass block order (1: contiguous
+    block ranges per XCD, 0: round-robin) of pass kind pass_kind
+    (_lib.PASS_PLAIN / PASS_GREEN / PASS_GRAD) at transform length n;
+    returns the value in force before the call."""
+    lib = _lib.load()
+    cur = C.c_int32()
+    check(lib.cola_fft_get_schedule(int(n), int(pass_kind), C.byref(cur)), what="fft_get_schedule")
+    if order is not None:
+        check(lib.cola_fft_set_schedule(int(n), int(pass_kind), int(order)), what="fft_set_schedule")
+    return cur.value
+
 
 class ColaBatch:
     """Many independent realisations stepped together (libcola batch).

@@ -208,3 +208,18 @@ def test_new_entry_points_reject_a_null_context_without_a_device():
         lib.cola_fof_halos(None, None, None, 32, 0, C.byref(nh), None, None, None, None, None, 0),
     ]
     assert all(c == _lib.COLA_EINVAL for c in calls), calls
+
+
+def test_fft_schedule_table_validates_and_round_trips():
+    lib = _lib.load()
+    v = C.c_int32()
+    assert lib.cola_fft_get_schedule(768, _lib.PASS_GREEN, C.byref(v)) == 0 and v.value in (0, 1)
+    old = v.value
+    assert lib.cola_fft_set_schedule(100, _lib.PASS_GREEN, 0) == _lib.COLA_EINVAL   # no compiled length 100
+    assert lib.cola_fft_set_schedule(768, 3, 0) == _lib.COLA_EINVAL                 # no pass kind 3
+    assert lib.cola_fft_set_schedule(768, _lib.PASS_GREEN, 2) == _lib.COLA_EINVAL   # order 0 or 1
+    assert lib.cola_fft_get_schedule(768, 5, C.byref(v)) == _lib.COLA_EINVAL
+    assert lib.cola_fft_set_schedule(768, _lib.PASS_GREEN, 0) == 0
+    assert lib.cola_fft_get_schedule(768, _lib.PASS_GREEN, C.byref(v)) == 0 and v.value == 0
+    assert lib.cola_fft_get_schedule(768, _lib.PASS_PLAIN, C.byref(v)) == 0 and v.value == 1
+    assert lib.cola_fft_set_schedule(768, _lib.PASS_GREEN, old) == 0
