@@ -16,8 +16,8 @@ namespace cola {
 // is reproducible bit for bit.  `nm` is the target grid; displacements are
 // stored in cells of the PM mesh and multiplied by dscale = target/PM
 // (exactly 1 on the PM mesh, where the product is the identity).
-__device__ __forceinline__ void home_cell(const float* __restrict__ disp, long np3, uint32_t id,
-                                          int np, int nm, float dscale, int c[3], float f[3]) {
+__device__ __forceinline__ void home_cell_of(const float dv[3], uint32_t id, int np, int nm, float dscale,
+                                             int c[3], float f[3]) {
 #pragma clang fp contract(off)
   const uint32_t unp = (uint32_t)np;
   const uint32_t li[3] = {id / (unp * unp), (id / unp) % unp, id % unp};
@@ -27,12 +27,18 @@ __device__ __forceinline__ void home_cell(const float* __restrict__ disp, long n
     const int qi = (int)(t / unp);
     const int rem = (int)(t - (uint32_t)qi * unp);
     const float qf = __fdiv_rn((float)(2 * rem - np), (float)(2 * np));
-    const float u = __fadd_rn(qf, __fmul_rn(disp[e * np3 + id], dscale));
+    const float u = __fadd_rn(qf, __fmul_rn(dv[e], dscale));
     const float fl = floorf(u);
     f[e] = __fsub_rn(u, fl);
     int ci = (qi + (int)fl) % nm;
     c[e] = ci < 0 ? ci + nm : ci;
   }
+}
+
+__device__ __forceinline__ void home_cell(const float* __restrict__ disp, long np3, uint32_t id,
+                                          int np, int nm, float dscale, int c[3], float f[3]) {
+  const float dv[3] = {disp[id], disp[np3 + id], disp[2 * np3 + id]};
+  home_cell_of(dv, id, np, nm, dscale, c, f);
 }
 
 // CIC weight of offset k = 4 sx + 2 sy + sz: (w_sx(fx) * w_sy(fy)) * w_sz(fz),

@@ -236,18 +236,19 @@ constexpr int seg_o(int n, int ord, int s) { return n / rad_o(n, ord, s + 1); }
 constexpr int pad_o(int n, int ord, int s) {
   return seg_o(n, ord, s) < 16 ? 0 : ((ns_o(n, ord, s) - seg_o(n, ord, s)) % 16 + 16) % 16;
 }
-// Line pitch: holds every layout of both orders; 2 mod 16 float2, so the 8
-// lines x 2 rows that 16 lanes of a column pass touch fall on distinct bank
-// pairs.
-constexpr int fld(int n) {
+// Longest line any layout of either order needs.
+constexpr int fspan(int n) {
   int m = n;
   for (int o = 0; o < 2; ++o)
     for (int s = 0; s + 1 < nstage(n); ++s) {
       const int sp = rad_o(n, o, s + 1) * (seg_o(n, o, s) + pad_o(n, o, s));
       if (sp > m) m = sp;
     }
-  return (m + 13) / 16 * 16 + 2;
+  return m;
 }
+// Line pitch of the z passes (and the size model of the column passes):
+// 2 mod 16 float2.
+constexpr int fld(int n) { return (fspan(n) + 13) / 16 * 16 + 2; }
 // Column passes: W lines of length n.  Twiddle entries kept in LDS: the
 // whole period where it fits, else the first half.
 constexpr int fcols_w(int n) {
@@ -257,6 +258,18 @@ constexpr int fcols_w(int n) {
 }
 constexpr int ftw_len(int n) { return fcols_w(n) * fld(n) * 8 + n * 8 <= kLdsLimit ? n : n / 2; }
 constexpr int fcols_threads(int n) { return threads_for(fcols_w(n) * n); }
+// Line pitch of the column passes.  The 16 lanes that share an LDS cycle of
+// a 64-bit access cover W lines x 16/W rows (lane -> line t mod W, row t / W);
+// a pitch of 16/W mod 16 float2 puts them on 16 distinct bank pairs (a
+// model of every stage's reads and writes: 1.0x the conflict-free cycles at
+// W = 16 against 2.0x with pitch 2; 1.75x against 2.25x at length 2048).
+// Only the LDS addresses change, not the arithmetic.
+constexpr int fcols_ld(int n) {
+  return (fspan(n) + 15) / 16 * 16 + (fcols_w(n) >= 2 ? 16 / fcols_w(n) : 2);
+}
+static_assert(fcols_w(2048) * fcols_ld(2048) * 8 + ftw_len(2048) * 8 <= kLdsLimit, "column-pass LDS");
+static_assert(fcols_w(512) * fcols_ld(512) * 8 + ftw_len(512) * 8 <= kLdsLimit, "column-pass LDS");
+static_assert(fcols_w(1024) * fcols_ld(1024) * 8 + ftw_len(1024) * 8 <= kLdsLimit, "column-pass LDS");
 
 // Waves per SIMD the register budget must allow: two 1024-thread workgroups per CU.
 constexpr int min_waves(int t) { return t >= 1024 ? 8 : 4; }
@@ -460,7 +473,7 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
   if constexpr (MODE == X_FWD_GREEN) {
     if (coef) scale = mock_ptr(coef, mstride)->gscale;
   }
-  constexpr int W = fcols_w(N), LD = fld(N), T = fcols_threads(N), TL = ftw_len(N);
+  constexpr int W = fcols_w(N), LD = fcols_ld(N), T = fcols_threads(N), TL = ftw_len(N);
   constexpr int NST = nstage(N);
   __shared__ float2 lds[W * LD];
   __shared__ float2 twl[TL];
@@ -804,7 +817,7 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_combine(
     const float2* __restrict__ in0, const float2* __restrict__ in1, const float2* __restrict__ in2,
     float2* out, ColGeom g, const float2* __restrict__ tw, CombineSpec cs,
     const float* __restrict__ amp) {
-  constexpr int W = fcols_w(N), LD = fld(N), T = fcols_threads(N), TL = ftw_len(N);
+  constexpr int W = fcols_w(N), LD = fcols_ld(N), T = fcols_threads(N), TL = ftw_len(N);
   constexpr int NST = nstage(N), OF = lo_first(N);
   using S0 = Stg<N, OF, 0, W, T, false>;
   using SL = Stg<N, OF, NST - 1, W, T, false>;

@@ -28,7 +28,9 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
   if (i >= np3) return;
   g = mock_ptr(g, mstride);
   disp = mock_ptr(disp, mstride);
-  float v0[3], p1[3], p2[3];
+  float d0[3], v0[3], p1[3], p2[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) d0[d] = disp[d * np3 + i];
   if constexpr (!FORCE_ONLY) {
     vres = mock_ptr(vres, mstride);
     psi1 = mock_ptr(psi1, mstride);
@@ -40,10 +42,12 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
       p2[d] = psi2[d * np3 + i];
     }
   }
+  // every state load issued before the mesh gathers (the scheduler would
+  // otherwise sink some below the first store: one more memory round trip)
+  __builtin_amdgcn_sched_barrier(0);
   int c[3];
   float f[3];
-  const float dscale = 1.0f;
-  home_cell(disp, np3, (uint32_t)i, np, nm, dscale, c, f);
+  home_cell_of(d0, (uint32_t)i, np, nm, 1.0f, c, f);
   float F[3];
   force_readout(g, row_stride, nm, c, f, F);
   if constexpr (FORCE_ONLY) {
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
       const long j = d * np3 + i;
       const float v = v0[d] + kd.K * F[d] - kd.c1 * p1[d] - kd.c2 * p2[d];
       vres[j] = v;
-      disp[j] = disp[j] + kd.I * v + kd.e1 * p1[d] + kd.e2 * p2[d];
+      disp[j] = d0[d] + kd.I * v + kd.e1 * p1[d] + kd.e2 * p2[d];
     }
   }
 }
