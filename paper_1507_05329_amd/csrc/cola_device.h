@@ -7,6 +7,44 @@
 
 namespace cola {
 
+// Division by the lattice side np (1 .. 1024) of values below 2^30 with one
+// 32 x 32 -> 64-bit multiply: q = (n m) >> s, s = 30 + ceil(log2 np),
+// m = ceil(2^s / np) < 2^32.  Exact: m = 2^s / np + e with 0 <= e < 1, so
+// n m / 2^s = n / np + n e / 2^s, and n e / 2^s < 2^-ceil(log2 np) <= 1/np
+// cannot carry floor(n / np) to the next integer.
+// The offset (2 rem - np) / (2 np) is the double product (2 rem - np) x
+// (1 / (2 np)) rounded once to float, which equals the correctly rounded
+// float quotient: a quotient of integers below 2^12 is either a float or
+// more than 2^-35 (relative) away from every float rounding boundary, while
+// the double product is within 2^-52 of it.
+struct LatDivTable {
+  uint32_t m[1025];
+  uint32_t s[1025];
+  double inv2[1025];   // 1 / (2 np)
+  constexpr LatDivTable() : m(), s(), inv2() {
+    for (uint32_t d = 1; d <= 1024; ++d) {
+      uint32_t l = 0;
+      while ((1u << l) < d) ++l;
+      const uint64_t p = 1ull << (30 + l);
+      m[d] = (uint32_t)((p + d - 1) / d);
+      s[d] = 30 + l;
+      inv2[d] = 1.0 / (2.0 * (double)d);
+    }
+  }
+};
+static __constant__ LatDivTable kLatDiv;
+
+struct LatGeom {
+  uint32_t np, nm, m, s;
+  double inv2;
+};
+__device__ __forceinline__ LatGeom lat_geom(int np, int nm) {
+  return {(uint32_t)np, (uint32_t)nm, kLatDiv.m[np], kLatDiv.s[np], kLatDiv.inv2[np]};
+}
+__device__ __forceinline__ uint32_t lat_div(uint32_t n, const LatGeom& g) {
+  return (uint32_t)(((uint64_t)n * g.m) >> g.s);
+}
+
 // Home cell and fractional offset of particle `id` (CIC, nodes at cell
 // centres).  Lattice point of axis e sits at i_e * nm / np cells; the node
 // coordinate is u = i_e nm / np - 1/2 + d_e, computed as
@@ -19,19 +57,29 @@ namespace cola {
 __device__ __forceinline__ void home_cell_of(const float dv[3], uint32_t id, int np, int nm, float dscale,
                                              int c[3], float f[3]) {
 #pragma clang fp contract(off)
-  const uint32_t unp = (uint32_t)np;
-  const uint32_t li[3] = {id / (unp * unp), (id / unp) % unp, id % unp};
+  const LatGeom g = lat_geom(np, nm);
+  const uint32_t q1 = lat_div(id, g);
+  const uint32_t q0 = lat_div(q1, g);
+  const uint32_t li[3] = {q0, q1 - q0 * g.np, id - q1 * g.np};
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const uint32_t t = li[e] * (uint32_t)nm;       // < 2048 * 2048: no overflow
-    const int qi = (int)(t / unp);
-    const int rem = (int)(t - (uint32_t)qi * unp);
-    const float qf = __fdiv_rn((float)(2 * rem - np), (float)(2 * np));
+    const uint32_t t = li[e] * g.nm;                // < 1024 * 2048: below 2^30
+    const uint32_t qi = lat_div(t, g);
+    const int rem = (int)(t - qi * g.np);
+    const float qf = (float)((double)(2 * rem - np) * g.inv2);
     const float u = __fadd_rn(qf, __fmul_rn(dv[e], dscale));
     const float fl = floorf(u);
     f[e] = __fsub_rn(u, fl);
-    int ci = (qi + (int)fl) % nm;
-    c[e] = ci < 0 ? ci + nm : ci;
+    // the cell, periodic: one conditional add or subtract unless the
+    // displacement exceeds the box
+    int ci = (int)qi + (int)fl;
+    if (ci >= nm) ci -= nm;
+    else if (ci < 0) ci += nm;
+    if ((uint32_t)ci >= (uint32_t)nm) {
+      ci %= nm;
+      if (ci < 0) ci += nm;
+    }
+    c[e] = ci;
   }
 }
 

@@ -250,26 +250,40 @@ constexpr int fspan(int n) {
 // 2 mod 16 float2.
 constexpr int fld(int n) { return (fspan(n) + 13) / 16 * 16 + 2; }
 // Column passes: W lines of length n.  Twiddle entries kept in LDS: the
-// whole period where it fits, else the first half.
-constexpr int fcols_w(int n) {
+// whole period where it fits, else the first half.  lim: LDS bytes per
+// workgroup (kLdsLimit: two workgroups per compute unit).
+constexpr int fcols_w(int n, int lim = kLdsLimit) {
   int w = 16;
-  while (w > 1 && w * fld(n) * 8 + n * 4 > kLdsLimit) w /= 2;
+  while (w > 1 && w * fld(n) * 8 + n * 4 > lim) w /= 2;
   return w;
 }
-constexpr int ftw_len(int n) { return fcols_w(n) * fld(n) * 8 + n * 8 <= kLdsLimit ? n : n / 2; }
-constexpr int fcols_threads(int n) { return threads_for(fcols_w(n) * n); }
+constexpr int ftw_len(int n, int lim = kLdsLimit) { return fcols_w(n, lim) * fld(n) * 8 + n * 8 <= lim ? n : n / 2; }
+constexpr int fcols_threads(int n, int lim = kLdsLimit) {
+  return lim > kLdsLimit ? 1024 : threads_for(fcols_w(n, lim) * n);
+}
 // Line pitch of the column passes.  The 16 lanes that share an LDS cycle of
 // a 64-bit access cover W lines x 16/W rows (lane -> line t mod W, row t / W);
 // a pitch of 16/W mod 16 float2 puts them on 16 distinct bank pairs (a
 // model of every stage's reads and writes: 1.0x the conflict-free cycles at
 // W = 16 against 2.0x with pitch 2; 1.75x against 2.25x at length 2048).
 // Only the LDS addresses change, not the arithmetic.
-constexpr int fcols_ld(int n) {
-  return (fspan(n) + 15) / 16 * 16 + (fcols_w(n) >= 2 ? 16 / fcols_w(n) : 2);
+constexpr int fcols_ld(int n, int lim = kLdsLimit) {
+  return (fspan(n) + 15) / 16 * 16 + (fcols_w(n, lim) >= 2 ? 16 / fcols_w(n, lim) : 2);
 }
+// The Green's function x pass at length 2048 runs one workgroup of 1024
+// threads per compute unit on 8 columns (156 KB of LDS) instead of two of
+// 512 threads on 4 columns: its three transforms per column leave the
+// memory idle for long stretches, and wider runs per row cut its HBM
+// transactions (measured at 1024^3/2048^3: 38.9 against 43.9 ms; the
+// one-transform passes are faster on 4 columns).
+constexpr int kWideLds = 156 * 1024;
+constexpr int cols_lim(int n, int mode) { return (mode == X_FWD_GREEN && n == 2048) ? kWideLds : kLdsLimit; }
 static_assert(fcols_w(2048) * fcols_ld(2048) * 8 + ftw_len(2048) * 8 <= kLdsLimit, "column-pass LDS");
 static_assert(fcols_w(512) * fcols_ld(512) * 8 + ftw_len(512) * 8 <= kLdsLimit, "column-pass LDS");
 static_assert(fcols_w(1024) * fcols_ld(1024) * 8 + ftw_len(1024) * 8 <= kLdsLimit, "column-pass LDS");
+static_assert(fcols_w(2048, kWideLds) == 8 && fcols_threads(2048, kWideLds) == 1024 &&
+                  8 * fcols_ld(2048, kWideLds) * 8 + ftw_len(2048, kWideLds) * 8 <= kWideLds,
+              "wide Green pass LDS");
 
 // Waves per SIMD the register budget must allow: two 1024-thread workgroups per CU.
 constexpr int min_waves(int t) { return t >= 1024 ? 8 : 4; }
@@ -462,7 +476,7 @@ __device__ __forceinline__ void col_store_global(const float2 (&v)[St::KB][St::R
 constexpr int kPlainOrd = 1;
 
 template <int N, int MODE>
-__global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
+__global__ __launch_bounds__(fcols_threads(N, cols_lim(N, MODE)), 4) void k_cols(
     const float2* __restrict__ in, float2* out0, float2* out1, float2* out2, long mesh_stride,
     ColGeom g, const float2* __restrict__ tw, int mult, int ca, int cb, float scale,
     const float* __restrict__ amp, int y_is_plane_freq, const StepCoef* __restrict__ coef,
@@ -473,7 +487,8 @@ __global__ __launch_bounds__(fcols_threads(N), 4) void k_cols(
   if constexpr (MODE == X_FWD_GREEN) {
     if (coef) scale = mock_ptr(coef, mstride)->gscale;
   }
-  constexpr int W = fcols_w(N), LD = fcols_ld(N), T = fcols_threads(N), TL = ftw_len(N);
+  constexpr int LIM = cols_lim(N, MODE);
+  constexpr int W = fcols_w(N, LIM), LD = fcols_ld(N, LIM), T = fcols_threads(N, LIM), TL = ftw_len(N, LIM);
   constexpr int NST = nstage(N);
   __shared__ float2 lds[W * LD];
   __shared__ float2 twl[TL];
@@ -984,7 +999,9 @@ template <int N>
 void cols_n(int mode, int axis, const float2* in, float2* const out[3], int nbatch, long mesh_stride,
             const float2* tw, int mult, int ca, int cb, float scale, const float* amp, hipStream_t s,
             const StepCoef* coef = nullptr, int nmock = 1, long mstride = 0, long rowc = 0) {
-  constexpr int W = fcols_w(N), T = fcols_threads(N);
+  constexpr int LG = cols_lim(N, X_FWD_GREEN);
+  const int W = mode == X_FWD_GREEN ? fcols_w(N, LG) : fcols_w(N);
+  const int T = mode == X_FWD_GREEN ? fcols_threads(N, LG) : fcols_threads(N);
   ColGeom g = geom(N, W, axis, rowc);
   // The Green pass takes only the column blocks that hold a frequency
   // 0 .. N/2 (the rest of a padded row is never read; the passes after it
