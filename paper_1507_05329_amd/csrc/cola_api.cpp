@@ -172,7 +172,7 @@ void tile_sort(cola_ctx* c, int ng, const float* disp, int nmock = 1, long mstri
   launch_fill_u32(c->counts, nb + 1, 0u, c->stream, nmock, mstride);
   launch_bin_count(disp, c->p.np, ng, dscale, c->counts, c->pkey, c->prank, c->stream, nmock, mstride);
   launch_exclusive_scan(c->counts, c->offsets, nb, c->scan_scratch, c->stream, nmock, mstride);
-  launch_scatter(c->pkey, c->prank, c->offsets, c->np3, c->perm, c->stream, nmock, mstride);
+  launch_scatter_walk(c->pkey, c->prank, c->offsets, c->p.np, c->perm, c->stream, nmock, mstride);
 }
 
 void deposit(cola_ctx* c, int ng, float* out, long row_stride, int contrast, const float* disp,

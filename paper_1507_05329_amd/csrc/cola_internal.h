@@ -79,6 +79,10 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, long n,
                            uint32_t* scratch, hipStream_t s, int nmock = 1, long mstride = 0);
 void launch_scatter(const uint32_t* pkey, const uint32_t* prank, const uint32_t* off,
                     long np3, uint32_t* perm, hipStream_t s, int nmock = 1, long mstride = 0);
+// The same scatter for the tile sort of np^3 lattice particles, walking them
+// as the bucket count does (np a multiple of 16).
+void launch_scatter_walk(const uint32_t* pkey, const uint32_t* prank, const uint32_t* off, int np,
+                         uint32_t* perm, hipStream_t s, int nmock = 1, long mstride = 0);
 // Deterministic CIC gather (k_deposit.hip).
 void launch_deposit(const float* disp, const uint32_t* perm, const uint32_t* off,
                     int np, int nm, float dscale, float* out, long row_stride, int contrast,

@@ -69,7 +69,7 @@ extern "C" int cola_density_noalloc(const float* disp, int32_t np, int32_t nmesh
   cola::launch_fill_u32(counts, nb + 1, 0u, s);
   cola::launch_bin_count(disp, np, nmesh, 1.0f, counts, pkey, prank, s);
   cola::launch_exclusive_scan(counts, offsets, nb, scan, s);
-  cola::launch_scatter(pkey, prank, offsets, np3, perm, s);
+  cola::launch_scatter_walk(pkey, prank, offsets, np, perm, s);
   cola::launch_deposit(disp, perm, offsets, np, nmesh, 1.0f, out, nmesh, 1, s);
   return hipGetLastError() == hipSuccess ? COLA_OK : COLA_EHIP;
 }

@@ -740,10 +740,15 @@ __global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void
 // output lies inside its own three input lines, and a workgroup reads all
 // of its lines before it writes, so the pass runs in place.
 constexpr int frows_nl3(int n) { return frows_nl(n) / 3 * 3; }
-constexpr int frows_threads3(int n) { return threads_for(frows_nl3(n) * (n / 2)); }
+// 1024 threads where 15 lines of 384 leave 6 values per thread (the 768
+// mesh: 2.33 against 2.54 ms; two such workgroups per CU).  At 2048 (6
+// lines of 1024) 1024 threads are slower: 52.1 against 45.1 ms.
+constexpr int frows_threads3(int n) {
+  return frows_nl3(n) * (n / 2) == 5760 ? 1024 : threads_for(frows_nl3(n) * (n / 2));
+}
 
 template <int N>
-__global__ __launch_bounds__(frows_threads3(N), 4) void k_c2r_z3(
+__global__ __launch_bounds__(frows_threads3(N), min_waves(frows_threads3(N))) void k_c2r_z3(
     float2* __restrict__ mesh, long nrows, int cols, const float2* __restrict__ tw, long mstride) {
   constexpr int H = N / 2, LD = fld(H), NL = frows_nl3(N), T = frows_threads3(N), TL = frows_tw_len(N);
   static_assert(NL >= 3, "three lines per workgroup at least");

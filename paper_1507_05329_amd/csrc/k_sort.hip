@@ -187,4 +187,27 @@ void launch_scatter(const uint32_t* pkey, const uint32_t* prank, const uint32_t*
                      pkey, prank, off, np3, perm, mstride);
 }
 
+// The tile sort's scatter, in the bucket count's particle-to-workgroup walk:
+// the count reserved one contiguous run per (workgroup, bucket), so each
+// workgroup's writes fill a few whole runs instead of single ids scattered
+// over many.  The result is the same in any walk (every id has its slot).
+__global__ __launch_bounds__(256) void k_scatter_walk(const uint32_t* __restrict__ pkey,
+                                                      const uint32_t* __restrict__ prank,
+                                                      const uint32_t* __restrict__ off, int np,
+                                                      uint32_t* __restrict__ perm, long mstride) {
+  pkey = mock_ptr(pkey, mstride);
+  prank = mock_ptr(prank, mstride);
+  off = mock_ptr(off, mstride);
+  perm = mock_ptr(perm, mstride);
+  const long i = subcube_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  perm[off[pkey[i]] + prank[i]] = (uint32_t)i;
+}
+
+void launch_scatter_walk(const uint32_t* pkey, const uint32_t* prank, const uint32_t* off, int np,
+                         uint32_t* perm, hipStream_t s, int nmock, long mstride) {
+  const long np3 = (long)np * np * np;   // np is a multiple of 16: whole workgroups
+  hipLaunchKernelGGL(k_scatter_walk, dim3((unsigned)(np3 / 256), 1, (unsigned)nmock), dim3(256), 0, s,
+                     pkey, prank, off, np, perm, mstride);
+}
+
 }  // namespace cola
