@@ -502,9 +502,12 @@ __global__ __launch_bounds__(fcols_threads(N, cols_lim(N, MODE)), 4) void k_cols
   const int pfreq = y_is_plane_freq ? signed_freq(p, N) : 0;
   // plain transforms in order kPlainOrd; the others start in the order
   // with the smaller first radix (the Green pass returns in the other one),
-  // except the gradient y pass at 2048 (that order spills registers there)
-  constexpr int O0 = (MODE == X_FWD || MODE == X_INV) ? kPlainOrd
-                     : (MODE == X_INV_GRAD_YZ && N >= 2048) ? 0 : lo_first(N);
+  // except at 2048: the gradient y pass (that order spills registers there)
+  // and the Green pass (the larger first radix: 38.6 against 39.4 ms)
+  constexpr int O0 = (MODE == X_FWD || MODE == X_INV)       ? kPlainOrd
+                     : (MODE == X_INV_GRAD_YZ && N >= 2048) ? 0
+                     : (MODE == X_FWD_GREEN && N == 2048)   ? 1 - lo_first(N)
+                                                            : lo_first(N);
   using S0 = Stg<N, O0, 0, W, T, false>;
   using SL = Stg<N, O0, NST - 1, W, T, false>;
   float2 v[S0::KB][S0::R];
@@ -604,11 +607,19 @@ __global__ __launch_bounds__(fcols_threads(N, cols_lim(N, MODE)), 4) void k_cols
 // Forward: Z = DFT_H[x_2m + i x_2m+1], then the split step
 //   X_k = E_k + W_N^k O_k,  E = (Z_k + conj Z_{H-k})/2,  O = -i (Z_k - conj Z_{H-k})/2
 // for k = 0 .. H (columns beyond H are written as zeros).
+// The forward z pass at 2048 runs 2 rows per workgroup on 256 threads
+// (14.3 against 15.6 ms for 8 rows on 512 threads); at 768 the most rows
+// that fit stay faster (0.78 against 0.80 ms for 4 rows).
+constexpr int frows_nl_r2c(int n) { return n == 2048 ? 2 : frows_nl(n); }
+constexpr int frows_threads_r2c(int n) {
+  return n == 2048 ? threads_for(frows_nl_r2c(n) * (n / 2)) : frows_threads(n);
+}
+
 template <int N>
-__global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void k_r2c_z(
+__global__ __launch_bounds__(frows_threads_r2c(N), min_waves(frows_threads_r2c(N))) void k_r2c_z(
     float2* __restrict__ mesh, long nrows, int cols, long mesh_stride, const float2* __restrict__ tw,
     long mstride) {
-  constexpr int H = N / 2, LD = fld(H), NL = frows_nl(N), T = frows_threads(N), TL = frows_tw_len(N);
+  constexpr int H = N / 2, LD = fld(H), NL = frows_nl_r2c(N), T = frows_threads_r2c(N), TL = frows_tw_len(N);
   constexpr int OR = lo_first(H);
   using S0 = Stg<H, OR, 0, NL, T, true>;
   using SL = Stg<H, OR, nstage(H) - 1, NL, T, true>;
@@ -739,13 +750,20 @@ __global__ __launch_bounds__(frows_threads(N), min_waves(frows_threads(N))) void
 // holding (g_x, g_y, g_z) of its N nodes in its first 3 N floats.  A row's
 // output lies inside its own three input lines, and a workgroup reads all
 // of its lines before it writes, so the pass runs in place.
-constexpr int frows_nl3(int n) { return frows_nl(n) / 3 * 3; }
-// 1024 threads where 15 lines of 384 leave 6 values per thread (the 768
-// mesh: 2.33 against 2.54 ms; two such workgroups per CU).  At 2048 (6
-// lines of 1024) 1024 threads are slower: 52.1 against 45.1 ms.
-constexpr int frows_threads3(int n) {
-  return frows_nl3(n) * (n / 2) == 5760 ? 1024 : threads_for(frows_nl3(n) * (n / 2));
+// Lines per workgroup: whole row triples, at most about 3072 complex values
+// (one triple at 2048, two at 768 and 1024), on 256 threads.  Smaller
+// workgroups, several per compute unit, beat the most lines that fit the
+// LDS: at 2048 41.6 against 45.1 ms (6 lines) and 52.1 ms (6 lines on 1024
+// threads); at 768 2.24 against 2.29 (3 lines), 2.34 (15 lines, 1024
+// threads) and 2.74 ms (9 lines).
+constexpr int frows_nl3(int n) {
+  const int fit = frows_nl(n) / 3 * 3, want = 3 * (3072 / (3 * (n / 2)));
+  return fit < want ? fit : (want < 3 ? 3 : want);
 }
+constexpr int frows_threads3(int n) { return threads_for(frows_nl3(n) * (n / 2)); }
+static_assert(frows_nl3(2048) == 3 && frows_nl3(768) == 6 && frows_nl3(1024) == 6 && frows_nl3(1536) == 3 &&
+                  frows_nl3(512) == 12 && frows_nl3(256) == frows_nl(256) / 3 * 3,
+              "c2r lines per workgroup");
 
 template <int N>
 __global__ __launch_bounds__(frows_threads3(N), min_waves(frows_threads3(N))) void k_c2r_z3(
@@ -975,7 +993,7 @@ ColGeom geom(int n, int w, int axis, long rowc = 0) {
 template <int N>
 void r2c_n(float2* mesh, int nbatch, long mesh_stride, const float2* tw, hipStream_t s, int nmock,
            long mstride, long rowc) {
-  constexpr int NL = frows_nl(N), T = frows_threads(N);
+  constexpr int NL = frows_nl_r2c(N), T = frows_threads_r2c(N);
   const long nrows = (long)N * N;
   dim3 grid((unsigned)((nrows + NL - 1) / NL), (unsigned)nbatch, (unsigned)nmock);
   hipLaunchKernelGGL(k_r2c_z<N>, grid, dim3(T), 0, s, mesh, nrows, (int)(rowc > 0 ? rowc : padded_cols(N)),
