@@ -396,7 +396,8 @@ int cola_fft_get_schedule(int32_t n, int32_t pass, int32_t* order);
 /* Autotuner: times the three column-pass kinds of the PM step at the
  * context's mesh length (in the step's mesh layout) with block order 1 and
  * 0, reps launches each after one warm-up (HIP events on the context's
- * stream), and keeps the faster of each in the schedule table.  Uses the
+ * stream), and keeps the faster of each in the schedule table (block
+ * order 1 unless order 0 is more than 2% faster).  Uses the
  * context's meshes as scratch (the particle state is not touched).
  * Synchronises.  best (may be NULL, 3 entries, by pass kind) receives the
  * choices, ms (may be NULL, 6 entries: kind-major, order 0 then 1) the time

@@ -1213,7 +1213,9 @@ int cola_autotune(cola_ctx* c, int32_t reps, int32_t* best, double* ms) {
       }
       const double per = (double)t / reps;
       if (ms) ms[2 * kind + order] = per;
-      if (cand == 0 || per < tbest) {
+      // the default order unless the other one is faster by more than 2%
+      // (timing noise would otherwise flip near-ties from run to run)
+      if (cand == 0 || per < 0.98 * tbest) {
         tbest = per;
         pick = order;
       }
