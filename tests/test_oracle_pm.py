@@ -129,3 +129,33 @@ def test_isolated_particle_force_beyond_few_cells():
         ratio = (F[m] * dirs[m]).sum(1).mean() / (ref[m] * dirs[m]).sum(1).mean()
         assert abs(ratio - 1) < rad_tol, (lo, ratio)
         assert np.median(err[m]) < med_tol, (lo, np.median(err[m]))
+
+
+@pytest.mark.parametrize("n,slab", [(16, 5), (24, 7), (32, 32)])
+def test_slab_rfftn_equals_rfftn(n, slab):
+    # the axis-by-axis transform in slabs is the 3D DFT
+    x = np.random.default_rng(n).standard_normal((n, n, n)).astype(np.float32)
+    want = np.fft.rfftn(x.astype(np.float64))
+    got = pm.rfftn_slabs(x, slab=slab)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("n", [16, 24, 32])
+def test_force_by_mode_sums_equals_inverse_fft(n):
+    # direct summation of the inverse DFT at chosen nodes (every node at 16)
+    # against the irfftn of force_component, and its Parseval rms against
+    # the rms of the whole mesh
+    rng = np.random.default_rng(40 + n)
+    dk = np.fft.rfftn(rng.standard_normal((n, n, n)))
+    if n == 16:
+        nodes = np.stack(np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    else:
+        nodes = np.concatenate([[[0, 0, 0], [n - 1, n - 1, n - 1], [n // 2, n // 2, n // 2]],
+                                rng.integers(0, n, (30, 3))])
+    g, rms = pm.force_at_nodes(dk, n, 150.0, 0.9, nodes, slab=3)
+    for d in range(3):
+        full = pm.force_component(dk, n, 150.0, 0.9, d)
+        scale = np.sqrt((full ** 2).mean())
+        assert abs(rms[d] / scale - 1) < 1e-12
+        ref = full[nodes[:, 0], nodes[:, 1], nodes[:, 2]]
+        assert np.abs(g[d] - ref).max() <= 1e-12 * scale
