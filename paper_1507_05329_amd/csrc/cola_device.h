@@ -181,8 +181,12 @@ __device__ __forceinline__ long subcube_particle(uint32_t b, int t, int np) {
 // Measured on the 256^3 / 768^3 run: readout 1.89 against 2.00 ms per step
 // (2 x 4 x 32), 1.90 for 4 x 2 x 32, 1.95 for 4 x 4 x 16, 2.14 for 1 x 8 x 32;
 // the bucket count (which aggregates atomics per wave) is slower with it.
-__device__ __forceinline__ long readout_particle(uint32_t b, int t, int np) {
-  const int lk = (np & 31) == 0 ? 5 : 4;           // ids along k per block row: 32 or 16
+// Where the mesh is at least 3x the particle grid (particles 3 or more
+// cells apart) and np is a multiple of 256, one row of 256 ids along k
+// instead: 1.13 against 1.24 ms at 256^3 / 768^3 (at 1024^3 / 2048^3, 2
+// cells apart, rows of 256 take 59.5 against 47.9 ms and rows of 64 48.7).
+__device__ __forceinline__ long readout_particle(uint32_t b, int t, int np, int nm) {
+  const int lk = (nm >= 3 * np && (np & 255) == 0) ? 8 : (np & 31) == 0 ? 5 : 4;   // ids along k per block row
   const uint32_t nbk = (uint32_t)np >> lk, nbj = (uint32_t)np;
   const uint32_t bk = b % nbk, bj = (b / nbk) % nbj, bi = b / (nbk * nbj);
   const int k = (int)bk * (1 << lk) + (t & ((1 << lk) - 1));

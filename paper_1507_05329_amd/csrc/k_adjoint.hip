@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_adj_readout_kick(
     float* __restrict__ dbar, float* __restrict__ vbar, float* __restrict__ p1bar,
     float* __restrict__ p2bar, float* __restrict__ fbar) {
   // particles of a block share mesh lines; neighbouring blocks stay on one XCD (L2)
-  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np, nm);
   if (i >= np3) return;
   float F[3];
 #pragma unroll
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_adj_deposit_grad(const float* __restric
                                                           float dscale, long np3, float coef,
                                                           float* __restrict__ dbar) {
   // particles of a block share mesh lines; neighbouring blocks stay on one XCD (L2)
-  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np, ng);
   if (i >= np3) return;
   int c[3];
   float f[3];

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_readout_kick_drift(
     const float* __restrict__ psi1, const float* __restrict__ psi2, int np, int nm, long np3,
     const StepCoef* __restrict__ coef, float* __restrict__ force_out, long mstride) {
   // neighbouring blocks share mesh lines: keep them on one XCD (L2)
-  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np, nm);
   if (i >= np3) return;
   g = mock_ptr(g, mstride);
   disp = mock_ptr(disp, mstride);

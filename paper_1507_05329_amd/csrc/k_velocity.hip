@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_velocity(const float* __restrict__ g, l
                                                   const float* __restrict__ psi1, const float* __restrict__ psi2,
                                                   int np, int nm, long np3, VelCoef k, float* __restrict__ vel,
                                                   float* __restrict__ sdisp, int axis) {
-  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np, nm);
   if (i >= np3) return;
   float v[3], p1[3], p2[3], d[3];
 #pragma unroll
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_snapshot(const float* __restrict__ g, l
                                                   const float* __restrict__ psi1, const float* __restrict__ psi2,
                                                   int np, int nm, long np3, SnapCoef k, float* __restrict__ dout,
                                                   float* __restrict__ vout, float* __restrict__ sdisp, int axis) {
-  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np, nm);
   if (i >= np3) return;
   float v[3], p1[3], p2[3], d[3];
 #pragma unroll
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_los_weights(const float* __restrict__ g
                                                      const float* __restrict__ psi1, const float* __restrict__ psi2,
                                                      int np, int nm, long np3, VelCoef k, int axis, float w0,
                                                      float scale, float* __restrict__ wt) {
-  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np);
+  const long i = readout_particle(xcd_remap(blockIdx.x, gridDim.x), threadIdx.x, np, nm);
   if (i >= np3) return;
   const long j = axis * np3 + i;
   float F = 0.f;
