@@ -1,12 +1,13 @@
 """The largest single-GPU workload: 1024^3 particles, 2048^3 mesh, 1200 Mpc/h,
 10 steps (182 GB of workspace).
 
-The FP64 oracle cannot run at this size (it needs about 350 GB of host
-memory), so this checks what holds at any size and what the oracle can
+A full FP64 oracle run does not fit at this size (it needs about 344 GB of
+host memory), so this checks what holds at any size and what the oracle can
 compute one node at a time: zero net PM force, bit-exact density at sampled
 nodes (densest, emptiest, random) against the FP32 same-order replay,
 mass conservation, a finite state after every step, and large-scale growth
-of P(k) by D1^2.
+of P(k) by D1^2.  The 2048 mesh's spectral pipeline is compared with the
+oracle at sampled nodes in test_gpu_lengths.py.
 """
 import time
 
