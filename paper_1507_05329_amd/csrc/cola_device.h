@@ -176,22 +176,26 @@ __device__ __forceinline__ long subcube_particle(uint32_t b, int t, int np) {
   return ((long)i * np + j) * np + k;
 }
 
-// The same for the force readout and its adjoint, in columns of 8 x 1 x 32
-// ids (16 x 1 x 16 when np is not a multiple of 32): deeper along i, one j.
-// Measured on the 256^3 / 768^3 run: readout 1.89 against 2.00 ms per step
-// (2 x 4 x 32), 1.90 for 4 x 2 x 32, 1.95 for 4 x 4 x 16, 2.14 for 1 x 8 x 32;
-// the bucket count (which aggregates atomics per wave) is slower with it.
-// Where the mesh is at least 3x the particle grid (particles 3 or more
-// cells apart) and np is a multiple of 256, one row of 256 ids along k
-// instead: 1.13 against 1.24 ms at 256^3 / 768^3 (at 1024^3 / 2048^3, 2
-// cells apart, rows of 256 take 59.5 against 47.9 ms and rows of 64 48.7).
+// The same for the force readout and its adjoint.  Where the mesh is at
+// least 3x the particle grid (particles 3 or more cells apart) and np is a
+// multiple of 256: one row of 256 ids along k (1.13 against 1.24 ms for
+// 8 x 1 x 32 columns at 256^3 / 768^3).  Otherwise blocks of 4 x 2 x 32 ids
+// (i, j, k; 47.0 against 47.7 ms for 8 x 1 x 32 at 1024^3 / 2048^3, where
+// rows of 64, 128 and 256 along k take 48.7, 53.3 and 59.5 ms and 16 x 1 x
+// 16 56.1 ms), or 16 x 1 x 16 when np is not a multiple of 32.
 __device__ __forceinline__ long readout_particle(uint32_t b, int t, int np, int nm) {
-  const int lk = (nm >= 3 * np && (np & 255) == 0) ? 8 : (np & 31) == 0 ? 5 : 4;   // ids along k per block row
-  const uint32_t nbk = (uint32_t)np >> lk, nbj = (uint32_t)np;
+  if (nm >= 3 * np && (np & 255) == 0) {
+    const uint32_t bj = b % (uint32_t)np, bi = b / (uint32_t)np;
+    return ((long)bi * np + (int)bj) * np + t;
+  }
+  const int lk = (np & 31) == 0 ? 5 : 4;           // ids along k per block row: 32 or 16
+  const int lj = lk == 5 ? 1 : 0;                   // block depth along j: 2 or 1
+  const uint32_t nbk = (uint32_t)np >> lk, nbj = (uint32_t)np >> lj;
   const uint32_t bk = b % nbk, bj = (b / nbk) % nbj, bi = b / (nbk * nbj);
   const int k = (int)bk * (1 << lk) + (t & ((1 << lk) - 1));
-  const int i = (int)bi * (256 >> lk) + (t >> lk);
-  return ((long)i * np + (int)bj) * np + k;
+  const int j = (int)bj * (1 << lj) + ((t >> lk) & ((1 << lj) - 1));
+  const int i = (int)bi * (256 >> (lk + lj)) + (t >> (lk + lj));
+  return ((long)i * np + j) * np + k;
 }
 
 // Mock index of a batched launch is blockIdx.z; every per-mock array of a
